@@ -1,0 +1,122 @@
+"""Pins of the oracle's refinement (Alg. 2 Phase 3) and beam search (Alg. 1).
+
+Pins used: the PRUNE stage equals per-node Prune; the REVERSE stage output is
+the Prune of the reverse union computed here independently; connectivity is
+checked with an independent BFS; beam search with L >= n on a connected graph
+and search on a complete graph return the brute-force answer.
+"""
+from collections import deque
+
+import numpy as np
+import pytest
+
+
+def _reach(ids, deg, src):
+    seen = {src}
+    q = deque([src])
+    while q:
+        x = q.popleft()
+        for y in ids[x, :deg[x]]:
+            if y >= 0 and y not in seen:
+                seen.add(int(y))
+                q.append(int(y))
+    return seen
+
+
+def _knn_input(oracle, X, K):
+    ids, _ = oracle.exact_knn(X, X, K, exclude=np.arange(len(X)))
+    return ids
+
+
+def test_prune_stage_is_per_node_prune(oracle, datagen):
+    X = datagen.uniform_int(400, 12, seed=0)
+    cand = _knn_input(oracle, X, 16)
+    r = oracle.refine(X, cand, 8, stages=oracle.STAGE_PRUNE)
+    for u in range(400):
+        ref, rd = oracle.prune_one(X, u, cand[u], 8)
+        assert list(r["ids"][u, :r["deg"][u]]) == list(ref)
+        assert np.array_equal(r["d2"][u, :r["deg"][u]], rd)
+        assert (r["ids"][u, r["deg"][u]:] == -1).all()
+
+
+def test_reverse_stage(oracle, datagen):
+    X = datagen.uniform_int(300, 10, seed=1)
+    cand = _knn_input(oracle, X, 12)
+    p = oracle.refine(X, cand, 6, stages=oracle.STAGE_PRUNE)
+    r = oracle.refine(X, cand, 6, stages=oracle.STAGE_PRUNE | oracle.STAGE_REVERSE)
+    rev = [[] for _ in range(300)]
+    for v in range(300):
+        for w in p["ids"][v, :p["deg"][v]]:
+            rev[w].append(v)
+    for u in range(300):
+        union = list(p["ids"][u, :p["deg"][u]]) + rev[u]
+        ref, _ = oracle.prune_one(X, u, union, 6)
+        got = r["ids"][u, :r["deg"][u]]
+        assert list(got) == list(ref)
+        assert set(got.tolist()) <= set(int(x) for x in union)
+        assert r["deg"][u] <= 6
+
+
+def test_connect_reaches_everything(oracle, datagen):
+    # well separated clusters: the pruned kNN graph is disconnected
+    X, _ = datagen.sift_like(1200, 0, d=16, n_clusters=12, sigma=4.0, seed=5)
+    cand = _knn_input(oracle, X, 10)
+    no = oracle.refine(X, cand, 8, stages=oracle.STAGE_PRUNE | oracle.STAGE_REVERSE)
+    before = _reach(no["ids"], no["deg"], no["ep"])
+    assert len(before) < 1200
+    r = oracle.refine(X, cand, 8)
+    assert r["ep"] == oracle.entry_point(X)
+    assert len(_reach(r["ids"], r["deg"], r["ep"])) == 1200
+    assert (r["deg"] <= 8).all()
+    # one extra edge per restart root; every root is a target of an added edge
+    added = int((r["deg"] - no["deg"]).sum())
+    assert added == len(r["roots"]) > 0
+    assert r["roots"][0] == min(set(range(1200)) - before)
+    for root in r["roots"]:
+        assert (r["ids"] == root).any()
+
+
+def test_search_large_pool_is_exact(oracle, datagen):
+    X = datagen.uniform_int(500, 8, seed=2)
+    Q = datagen.uniform_int(30, 8, seed=3)
+    cand = _knn_input(oracle, X, 10)
+    g = oracle.refine(X, cand, 8)
+    assert len(_reach(g["ids"], g["deg"], g["ep"])) == 500
+    ids, d2, st = oracle.search(X, g["ids"], g["deg"], Q, [g["ep"]], 10, 500)
+    gt, gd = oracle.exact_knn(X, Q, 10)
+    assert np.array_equal(ids, gt)
+    assert np.array_equal(d2, gd)
+    assert (st[:, 1] == 500).all()  # every node evaluated exactly once
+
+
+def test_search_complete_graph_is_exact(oracle):
+    rng = np.random.default_rng(8)
+    n = 60
+    X = rng.standard_normal((n, 5)).astype(np.float32)
+    Q = rng.standard_normal((20, 5)).astype(np.float32)
+    ids = np.array([[v for v in range(n) if v != u] for u in range(n)], np.int32)
+    deg = np.full(n, n - 1, np.int32)
+    got, gd, _ = oracle.search(X, ids, deg, Q, [0], 5, 5)
+    gt, gtd = oracle.exact_knn(X, Q, 5)
+    assert np.array_equal(got, gt)
+    assert np.array_equal(gd, gtd)
+
+
+def test_search_path_graph(oracle):
+    # points 0..9 on a line, edges i -> i+1 only: from entry 0 with L = 1 the
+    # beam walks to the end and returns the query's nearest reachable points
+    X = np.arange(10, dtype=np.float32)[:, None]
+    ids = np.array([[i + 1] if i < 9 else [-1] for i in range(10)], np.int32)
+    deg = np.array([1] * 9 + [0], np.int32)
+    got, d2, st = oracle.search(X, ids, deg, np.array([[6.2]], np.float32), [0], 1, 1)
+    assert got[0, 0] == 6
+    assert st[0, 0] == 7  # expands 0..6; 7 is evaluated but farther than 6
+
+
+def test_multiple_entries_and_padding(oracle):
+    X = np.arange(6, dtype=np.float32)[:, None]
+    ids = np.full((6, 1), -1, np.int32)
+    deg = np.zeros(6, np.int32)
+    got, d2, _ = oracle.search(X, ids, deg, np.array([[4.4]], np.float32), [1, 4, 4, 0], 5, 8)
+    assert list(got[0]) == [4, 1, 0, -1, -1]
+    assert np.isinf(d2[0, 3:]).all()
