@@ -1,0 +1,204 @@
+/*
+ * pg.h -- C ABI of the MI355X (gfx950) proximity-graph build library
+ * (arXiv 2410.01231, "Revisiting the Index Construction of Proximity
+ * Graph-Based Approximate Nearest Neighbor Search").
+ *
+ * The library builds an approximate k-nearest-neighbour graph by NN-Descent
+ * local joins (the paper's initialization phase), refines it with the paper's
+ * pruning rule (Alg. 3, with the alpha test of Section 4.1), reverse-edge
+ * re-pruning and connectivity repair (Alg. 2, refinement phase), and answers
+ * k-ANN queries by beam search (Alg. 1).
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument is DEVICE memory (allocated by the caller, e.g.
+ *    through torch) unless the comment says "host".  The caller owns every
+ *    buffer; the library never frees or keeps a pointer after a call returns.
+ *  - Vectors are float32 rows: X is n rows of d floats with leading dimension
+ *    ldx (in floats).  d and ldx must be multiples of 4 and X 16-byte aligned.
+ *  - Ids are int32 in [0, n); n < 2^31.  Missing entries are padded with id -1
+ *    and distance +inf.
+ *  - Distances are SQUARED L2 distances (monotone in the paper's dist), in
+ *    float32, evaluated as s = fma(x_i - y_i, x_i - y_i, s) over i = 0..d-1 in
+ *    order; the same evaluation is used by every kernel, so a pair's distance
+ *    has one bit pattern wherever it is computed.
+ *  - Every order and tie is the total order on (d2, id).
+ *  - Calls run on the context's HIP stream.  pg_knn_build and pg_prune (with
+ *    the connect stage) read small counters back and therefore return after
+ *    their work has finished on the stream; the other calls only enqueue work.
+ *  - Argument errors return PG_EINVAL (or PG_EUNSUPPORTED) synchronously,
+ *    before any work is enqueued, with a message from pg_last_error().  Device
+ *    errors surface as PG_EDEVICE.  Nothing is silently truncated: a bounded
+ *    internal buffer that cannot hold a result makes the call retry
+ *    deterministically, or fail with PG_EOVERFLOW.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef PG_H
+#define PG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pg_ctx pg_ctx;
+
+typedef enum {
+    PG_OK = 0,
+    PG_EINVAL = -1,        /* bad argument */
+    PG_ENOMEM = -2,        /* workspace too small or host allocation failed */
+    PG_EDEVICE = -3,       /* HIP runtime or kernel error */
+    PG_EUNSUPPORTED = -4,  /* valid but outside what the kernels implement */
+    PG_EOVERFLOW = -5      /* a bounded structure could not hold the result */
+} pg_status;
+
+typedef enum { PG_FP32 = 0, PG_FP16 = 1, PG_BF16 = 2 } pg_precision;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int pg_version(void);
+
+/* Message of the last failing call on this host thread (never NULL). */
+const char *pg_last_error(void);
+
+/* Create a context bound to HIP device `device` and the HIP stream
+ * `hip_stream` (a hipStream_t; NULL means the null stream).  *out receives
+ * the context (host pointer). */
+pg_status pg_ctx_create(int device, void *hip_stream, pg_ctx **out);
+pg_status pg_ctx_destroy(pg_ctx *ctx);
+
+/* Per-kernel timing.  When enabled, every launch of the named kernels is
+ * bracketed by HIP events on the context stream.  pg_ctx_kernel_time (host
+ * outputs) returns, for kernel `name`, the summed event time in ms, the number
+ * of launches, and the summed algorithmic work of those launches (flops for
+ * the distance kernels, bytes for the others, as documented per kernel).
+ * Reading the times synchronises the stream.  Names: "join", "merge", "init",
+ * "sample", "prune", "search", "exact_knn". */
+pg_status pg_ctx_set_timing(pg_ctx *ctx, int enable);
+pg_status pg_ctx_kernel_time(pg_ctx *ctx, const char *name, double *total_ms,
+                             int64_t *launches, double *work);
+pg_status pg_ctx_reset_timing(pg_ctx *ctx);
+
+/* ------------------------------------------------------------------ */
+/* Approximate kNN graph: NN-Descent (initialization phase)            */
+/* ------------------------------------------------------------------ */
+/*
+ * Section 3.1 (Initialization) builds the initial KNNG G_k0 with KGraph;
+ * Section 6, Exp. 12 describes the iterations (k random neighbours, then
+ * distances to 2-hop neighbours).  The library runs NN-Descent local joins,
+ * synchronous and deterministic:
+ *   init:  K distinct random neighbours per node from a counter-based hash
+ *          of (seed, 0, u, attempt);
+ *   iteration t: sample <= S new entries per list (smallest hash keys), build
+ *          reverse samples (<= S per node), join every new-new and new-old pair
+ *          of each node's sample set, propose each pair to both ends when it
+ *          beats the K-th entry of the end's list, and merge: each list becomes
+ *          the K smallest distinct ids of (list U proposals).
+ *   stop:  after max_iters iterations or when an iteration changes at most
+ *          stop_updates list entries.
+ * The result depends only on (X, K, S, max_iters, stop_updates, seed); the
+ * tuning fields (bucket_cap, chunks) change speed and memory, never results.
+ * exact != 0 computes the exact kNN lists instead (brute force).
+ */
+typedef struct {
+    int32_t K;            /* list length, 1 <= K <= 64, K < n */
+    int32_t S;            /* sample size per list, 1 <= S <= K (NN-Descent rho*K) */
+    int32_t max_iters;    /* 0 <= max_iters <= 64 */
+    int32_t exact;        /* nonzero: brute-force exact lists, other fields unused */
+    int64_t stop_updates; /* stop when an iteration changes <= this many entries */
+    uint64_t seed;
+    int32_t precision;    /* pg_precision of the join tiles; PG_FP32 only for now */
+    float margin_rel;     /* reserved for the mixed-precision recheck margin */
+    int32_t bucket_cap;   /* proposal slots per node per pass (>= 2K); 0 = default */
+    int32_t chunks;       /* source passes in the first iteration; 0 = default */
+} pg_knn_params;
+
+typedef struct {
+    int32_t iters_run;
+    int32_t reserved;
+    int64_t updates[64];   /* list entries changed in iteration t (index t-1) */
+    int64_t pairs[64];     /* local-join pairs evaluated in iteration t */
+    int64_t proposals[64]; /* proposals that passed the K-th filter at emission */
+    int64_t retries;       /* extra join passes caused by full proposal buckets */
+} pg_knn_stats;
+
+/* Workspace bytes needed by pg_knn_build for these sizes (host output). */
+pg_status pg_knn_build_workspace(const pg_knn_params *p, int64_t n, int32_t d,
+                                 size_t *bytes);
+
+/* Build the kNN lists: knn_ids / knn_d2 are n x K (row u sorted by (d2, id),
+ * never containing u).  ws is device scratch of ws_bytes >= the size above.
+ * stats (host, optional) is filled when the call returns. */
+pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                       const pg_knn_params *p, void *ws, size_t ws_bytes,
+                       int32_t *knn_ids, float *knn_d2, pg_knn_stats *stats);
+
+/* Brute-force k nearest neighbours of each query row among the rows of X
+ * (k-ANN problem statement of Section 2, solved exactly).  Q is nq x d with
+ * leading dimension ldq.  exclude (optional, nq ints) names a row of X to skip
+ * for each query (-1 for none).  out_ids / out_d2 are nq x k, 1 <= k <= 64. */
+pg_status pg_exact_knn(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                       const float *Q, int64_t nq, int64_t ldq, const int32_t *exclude,
+                       int32_t k, int32_t *out_ids, float *out_d2);
+
+/* ------------------------------------------------------------------ */
+/* Refinement: Prune (Alg. 3), reverse re-prune and connect (Alg. 2)   */
+/* ------------------------------------------------------------------ */
+enum { PG_STAGE_PRUNE = 1, PG_STAGE_REVERSE = 2, PG_STAGE_CONNECT = 4 };
+
+typedef struct {
+    int32_t R;            /* out-degree bound M of the paper, 1 <= R <= 64 */
+    float alpha_deg;      /* alpha of Section 4.1; <= 60 means RNG pruning */
+    uint32_t stages;      /* PG_STAGE_* bits; PRUNE is required */
+    int32_t strict_ties;  /* nonzero: w occludes v only if also d2(u,w) < d2(u,v) */
+    const float *pair_d2; /* optional test hook, PRUNE stage alone: n tables of
+                             (C+1) x (C+1) floats, positions 0 = u and 1..C =
+                             cand_ids[u][0..C-1]; all distances are read from it */
+} pg_prune_params;
+
+/* Workspace bytes needed by pg_prune (host output). */
+pg_status pg_prune_workspace(const pg_prune_params *p, int64_t n, int32_t C,
+                             size_t *bytes);
+
+/*
+ * cand_ids: n x C candidate lists (C <= 64; -1, u itself and repeats are
+ * skipped).  Stage PRUNE: N(u) <- Prune(u, C(u), R) for every u (Alg. 3 and,
+ * for alpha > 60, the alpha test).  Stage REVERSE: N(u) <- Prune(u, N(u) U
+ * {v : u in N(v)}, R), every node reading the PRUNE result.  Entry point:
+ * the node closest to the centroid of X (argmin of (d2, id); centroid summed
+ * in double).  Stage CONNECT: from ep, while some node is unreachable, the
+ * smallest unreachable id r gets the edge p -> r from the reachable node p
+ * nearest to r with degree < R; extra edges are appended.
+ * Outputs: g_ids / g_d2 (n x R, rows padded with -1 / +inf), g_deg (n),
+ * ep (1 int), roots (optional, n ints: the restart nodes r in order) and
+ * n_roots (host, optional).  PG_EOVERFLOW if CONNECT finds every reachable
+ * node already at degree R.
+ */
+pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                   const int32_t *cand_ids, int32_t C, const pg_prune_params *p,
+                   void *ws, size_t ws_bytes, int32_t *g_ids, float *g_d2,
+                   int32_t *g_deg, int32_t *ep, int32_t *roots, int32_t *n_roots);
+
+/* ------------------------------------------------------------------ */
+/* Beam search (Alg. 1)                                                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t k;                /* results per query, 1 <= k <= L */
+    int32_t L;                /* pool width, L <= 1024 */
+    int32_t n_entry;          /* number of entering points, >= 1 */
+    const int32_t *entry_ids; /* device, n_entry ids (repeats dropped) */
+} pg_search_params;
+
+/* KANNSearch of Alg. 1 for every query row, starting from the entering
+ * points: the pool keeps the L closest by (d2, id); the closest unexpanded
+ * entry is expanded until the first min(L, |pool|) are expanded.
+ * g_ids is n x R with degrees g_deg.  out_ids / out_d2 are nq x k. */
+pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                    const int32_t *g_ids, int32_t R, const int32_t *g_deg,
+                    const float *Q, int64_t nq, int64_t ldq,
+                    const pg_search_params *p, int32_t *out_ids, float *out_d2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PG_H */

@@ -179,11 +179,12 @@ int orc_exact_knn(const float *X, int64_t n, int32_t d, int64_t ldx,
  *
  *  iteration t >= 1 reads a snapshot of every list:
  *   (a) new_f(u): the min(S, #new) new-flagged entries with the smallest
- *       (h(seed, 3t, u, v), v); they are flagged old from now on.
+ *       (h(seed, 3t, u, v) >> 32, v) (the high 32 bits of the hash, then the
+ *       id); they are flagged old from now on.
  *       old_f(u): the entries flagged old in the snapshot.
  *   (b) Rnew(v) = {u : v in new_f(u)} keeping the S smallest
- *       (h(seed, 3t+1, v, u), u);  Rold(v) likewise from old_f with stream
- *       3t+2.
+ *       (h(seed, 3t+1, v, u) >> 32, u);  Rold(v) likewise from old_f with
+ *       stream 3t+2.
  *   (c) new(u) = new_f(u) U Rnew(u);  old(u) = (old_f(u) U Rold(u)) \ new(u).
  *   (d) local join at u: every unordered pair {v, w} of distinct members of
  *       new(u), and every pair v in new(u), w in old(u).  w is proposed to v
@@ -339,7 +340,7 @@ int orc_nndescent(const float *X, int64_t n, int32_t d, int64_t ldx,
             for (int32_t j = 0; j < K; ++j) {
                 int32_t v = L.ids[u * K + j];
                 if (L.isnew[u * K + j]) {
-                    hk[m].h = orc_hash(seed, 3 * (uint64_t)t, (uint64_t)u, (uint64_t)v);
+                    hk[m].h = orc_hash(seed, 3 * (uint64_t)t, (uint64_t)u, (uint64_t)v) >> 32;
                     hk[m].id = v;
                     ++m;
                 } else {
@@ -393,7 +394,7 @@ int orc_nndescent(const float *X, int64_t n, int32_t d, int64_t ldx,
                 }
                 for (int64_t i = 0; i < cnt; ++i) {
                     int32_t u = rev[roff[v] + i];
-                    hk[i].h = orc_hash(seed, stream, (uint64_t)v, (uint64_t)u);
+                    hk[i].h = orc_hash(seed, stream, (uint64_t)v, (uint64_t)u) >> 32;
                     hk[i].id = u;
                 }
                 qsort(hk, (size_t)cnt, sizeof(orc_hkey), cmp_hkey);

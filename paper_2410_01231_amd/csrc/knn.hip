@@ -1,0 +1,923 @@
+// knn.hip -- approximate kNN graph by NN-Descent local joins (the paper's
+// initialization phase: Section 3.1 and Alg. 2 Phase 1 build G_k0 with
+// KGraph; Section 6, Exp. 12: k random neighbours, then distances to 2-hop
+// neighbours), plus exact brute-force kNN, for gfx950.
+//
+// One iteration, all kernels on the context stream:
+//   k_sample      wave per node: sample <= S new entries by hash, flip them to
+//                 old, list the old ones, count reverse in-degrees
+//   scan x2       exclusive prefix sums of the in-degrees
+//   k_rev_scatter wave per node: CSR reverse lists
+//   k_build_join  wave per node: keep the S smallest-hash reverse entries,
+//                 form new(u) and old(u) (the join set of u)
+//   k_join        workgroup per source u: the join set's vectors are staged
+//                 through LDS in 32-dim chunks; every new-new and new-old pair
+//                 gets its squared distance in registers (4x4 micro-tiles);
+//                 a pair is proposed to each end whose K-th key it beats and
+//                 appended to that end's proposal bucket
+//   k_merge       wave per node: each list becomes the K smallest distinct
+//                 keys of (list U bucket) by wave64 bitonic sort and merge
+// Sources are joined in several passes (chunks) per iteration; each pass is
+// merged before the next one starts.  Merging is a set operation (K smallest
+// distinct keys of a union), and a proposal rejected by the tighter K-th key
+// of a later pass could not have entered the list, so the result equals the
+// single synchronous iteration whatever the pass boundaries.  A bucket that
+// fills up marks its node; the pass is repeated for marked nodes only, without
+// the keys those nodes already list, until none overflows (each repeat
+// inserts at least one new key, so the node's K-th key strictly falls).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pg_common.h"
+
+namespace pgi {
+
+enum { C_UPDATES = 0, C_PROPOSALS = 1, C_OVF = 2, C_PAIRS = 3, C_NCOUNTERS = 8 };
+
+// ---------------------------------------------------------------------------
+// init: K distinct random neighbours, hash4(seed, 0, u, attempt) mod (n-1)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64_t ldx, int d,
+                                              int64_t n, int K, uint64_t seed,
+                                              uint64_t *__restrict__ keys,
+                                              uint64_t *__restrict__ newm,
+                                              uint64_t *__restrict__ insm) {
+    __shared__ int32_t acc_s[4][PG_WAVE];
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t u = (int64_t)blockIdx.x * 4 + w;
+    if (u >= n) return;
+    int32_t *acc = acc_s[w];
+    int na = 0;
+    uint64_t j0 = 0;
+    const uint64_t nm1 = (uint64_t)(n - 1);
+    while (na < K) {
+        const uint64_t r = hash4(seed, 0, (uint64_t)u, j0 + (uint64_t)lane) % nm1;
+        const int32_t c = (int32_t)(r >= (uint64_t)u ? r + 1 : r);
+        bool dup = false;
+        for (int i = 0; i < na; ++i) dup |= (acc[i] == c);
+        for (int i = 0; i < PG_WAVE - 1; ++i) {
+            const int ci = __builtin_amdgcn_readlane(c, i);
+            dup |= (i < lane) && (ci == c);
+        }
+        const uint64_t m = __ballot(!dup);
+        const int rank = __popcll(m & lanemask_lt());
+        if (!dup && rank < K - na) acc[na + rank] = c;
+        __builtin_amdgcn_wave_barrier();
+        na += min(__popcll(m), K - na);
+        j0 += PG_WAVE;
+    }
+    const int32_t id = lane < K ? acc[lane] : -1;
+    uint64_t key = KEY_INF;
+    if (id >= 0) key = pack_key(dist_chain(X + u * ldx, X + (int64_t)id * ldx, d), id);
+    wave_sort(key);
+    if (lane < K) keys[u * K + lane] = key;
+    if (lane == 0) {
+        newm[u] = (K == 64) ? ~0ull : ((1ull << K) - 1ull);
+        insm[u] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sampling (step (a) of the iteration)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sample(const uint64_t *__restrict__ keys,
+                                                uint64_t *__restrict__ newm,
+                                                int64_t n, int K, int S, uint64_t seed,
+                                                uint64_t stream, int32_t *__restrict__ nf,
+                                                int32_t *__restrict__ nf_c,
+                                                int32_t *__restrict__ of,
+                                                int32_t *__restrict__ of_c,
+                                                int32_t *__restrict__ rn_cnt,
+                                                int32_t *__restrict__ ro_cnt) {
+    const int lane = lane_id();
+    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u >= n) return;
+    const uint64_t nm = newm[u];
+    const uint64_t key = lane < K ? keys[u * K + lane] : KEY_INF;
+    const int32_t id = key_id(key);
+    const bool isnew = lane < K && ((nm >> lane) & 1ull);
+    const bool isold = lane < K && !isnew;
+    uint64_t sk = isnew ? sample_key(hash4(seed, stream, (uint64_t)u, (uint64_t)id), id) : KEY_INF;
+    int pos = lane;
+    wave_sort(sk, pos);
+    const bool sel = lane < S && sk != KEY_INF;
+    uint64_t selbit = sel ? (1ull << pos) : 0ull;
+#pragma unroll
+    for (int off = 1; off < PG_WAVE; off <<= 1) selbit |= shfl_xor64(selbit, off);
+    if (sel) {
+        const int32_t v = key_id(sk);
+        nf[u * S + lane] = v;
+        atomicAdd(&rn_cnt[v], 1);
+    }
+    const uint64_t om = __ballot(isold);
+    if (isold) {
+        of[u * K + __popcll(om & lanemask_lt())] = id;
+        atomicAdd(&ro_cnt[id], 1);
+    }
+    if (lane == 0) {
+        nf_c[u] = min(S, __popcll(nm & ((K == 64) ? ~0ull : ((1ull << K) - 1ull))));
+        of_c[u] = __popcll(om);
+        newm[u] = nm & ~selbit;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse lists (CSR)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rev_scatter(int64_t n, const int32_t *__restrict__ nf,
+                                                     const int32_t *__restrict__ nf_c, int S,
+                                                     const int32_t *__restrict__ of,
+                                                     const int32_t *__restrict__ of_c, int K,
+                                                     const int64_t *__restrict__ rn_off,
+                                                     int32_t *__restrict__ rn_cur,
+                                                     int32_t *__restrict__ rn_list,
+                                                     const int64_t *__restrict__ ro_off,
+                                                     int32_t *__restrict__ ro_cur,
+                                                     int32_t *__restrict__ ro_list) {
+    const int lane = lane_id();
+    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u >= n) return;
+    if (lane < nf_c[u]) {
+        const int32_t v = nf[u * S + lane];
+        const int p = atomicAdd(&rn_cur[v], 1);
+        rn_list[rn_off[v] + p] = (int32_t)u;
+    }
+    if (lane < of_c[u]) {
+        const int32_t v = of[u * K + lane];
+        const int p = atomicAdd(&ro_cur[v], 1);
+        ro_list[ro_off[v] + p] = (int32_t)u;
+    }
+}
+
+// S smallest sample keys among the CSR list of v (stream `stream`), ascending.
+__device__ __forceinline__ uint64_t select_reverse(int64_t v, const int64_t *__restrict__ off,
+                                                   const int32_t *__restrict__ list,
+                                                   uint64_t seed, uint64_t stream) {
+    const int lane = lane_id();
+    const int64_t beg = off[v], cnt = off[v + 1] - beg;
+    uint64_t top = KEY_INF;
+    int dummy = 0;
+    for (int64_t b = 0; b < cnt; b += PG_WAVE) {
+        uint64_t sk = KEY_INF;
+        if (b + lane < cnt) {
+            const int32_t x = list[beg + b + lane];
+            sk = sample_key(hash4(seed, stream, (uint64_t)v, (uint64_t)x), x);
+        }
+        int p = 0;
+        wave_sort(sk, p);
+        wave_merge_lowest(top, dummy, sk, p);
+    }
+    return top;
+}
+
+__device__ __forceinline__ bool wave_contains(uint64_t sorted, uint64_t x) {
+    const int c = wave_count_less(sorted, x);
+    const uint64_t at = shfl64(sorted, min(c, PG_WAVE - 1));
+    return x != KEY_INF && c < PG_WAVE && at == x;
+}
+
+// ---------------------------------------------------------------------------
+// join sets: new(v) = new_f(v) U Rnew(v); old(v) = (old_f(v) U Rold(v)) \ new(v)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_build_join(
+    int64_t n, int K, int S, uint64_t seed, uint64_t stream_rn, uint64_t stream_ro,
+    const int32_t *__restrict__ nf, const int32_t *__restrict__ nf_c,
+    const int32_t *__restrict__ of, const int32_t *__restrict__ of_c,
+    const int64_t *__restrict__ rn_off, const int32_t *__restrict__ rn_list,
+    const int64_t *__restrict__ ro_off, const int32_t *__restrict__ ro_list,
+    int32_t *__restrict__ jn, int32_t *__restrict__ jn_c, int JN, int32_t *__restrict__ jo,
+    int32_t *__restrict__ jo_c, int JO, unsigned long long *__restrict__ counters) {
+    __shared__ unsigned long long pairs_s[4];
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int64_t v = (int64_t)blockIdx.x * 4 + w;
+    unsigned long long pairs = 0;
+    if (v < n) {
+        const uint64_t rsel = select_reverse(v, rn_off, rn_list, seed, stream_rn);
+        const uint64_t osel = select_reverse(v, ro_off, ro_list, seed, stream_ro);
+        // new set (|new_f| <= S and |Rnew| <= S, S <= 32: one id per lane)
+        const int nfc = nf_c[v];
+        const uint64_t rsel_id = (lane < S && rsel != KEY_INF) ? (uint64_t)(uint32_t)key_id(rsel) : KEY_INF;
+        uint64_t a = lane < nfc ? (uint64_t)(uint32_t)nf[v * S + lane] : KEY_INF;
+        {
+            const int r = lane - nfc;
+            const uint64_t fromr = shfl64(rsel_id, max(0, min(r, PG_WAVE - 1)));
+            if (r >= 0 && r < S) a = fromr;
+        }
+        int pa = 0;
+        wave_sort(a, pa);
+        const uint64_t prev = shfl64(a, max(lane - 1, 0));
+        const int nn = wave_compact(a, pa, a != KEY_INF && (lane == 0 || prev != a));
+        if (lane < nn) jn[v * JN + lane] = (int32_t)a;
+        // old set
+        const int ofc = of_c[v];
+        uint64_t A = lane < ofc ? (uint64_t)(uint32_t)of[v * K + lane] : KEY_INF;
+        int pA = 0;
+        wave_sort(A, pA);
+        uint64_t Bk = (lane < S && osel != KEY_INF) ? (uint64_t)(uint32_t)key_id(osel) : KEY_INF;
+        int pB = 0;
+        wave_sort(Bk, pB);
+        // cross-lane lookups run on every lane (no short-circuit around shuffles)
+        const bool b_in_A = wave_contains(A, Bk);
+        const bool b_in_new = wave_contains(a, Bk);
+        const bool a_in_new = wave_contains(a, A);
+        const bool b_ok = Bk != KEY_INF && !b_in_A && !b_in_new;
+        const bool a_ok = A != KEY_INF && !a_in_new;
+        const int ca = wave_compact(A, pA, a_ok);
+        const int cb = wave_compact(Bk, pB, b_ok);
+        if (lane < ca) jo[v * JO + lane] = (int32_t)A;
+        if (lane < cb) jo[v * JO + ca + lane] = (int32_t)Bk;
+        if (lane == 0) {
+            jn_c[v] = nn;
+            jo_c[v] = ca + cb;
+            pairs = (unsigned long long)nn * (nn - 1) / 2 + (unsigned long long)nn * (ca + cb);
+        }
+    }
+    if (lane == 0) pairs_s[w] = pairs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = pairs_s[0] + pairs_s[1] + pairs_s[2] + pairs_s[3];
+        if (t) atomicAdd(&counters[C_PAIRS], t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// local join tile
+// ---------------------------------------------------------------------------
+// Is `key` one of the K sorted keys of a list?  (binary search)
+__device__ __forceinline__ bool list_has(const uint64_t *__restrict__ row, int K, uint64_t key) {
+    int lo = 0, hi = K;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (row[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < K && row[lo] == key;
+}
+
+constexpr int JT = 256;          // threads per source
+constexpr int JDC = 32;          // dims per LDS chunk
+constexpr int JSTR = JDC + 4;    // LDS row stride (floats)
+constexpr int JMAXB = 4;         // 4x4 micro-tiles per thread per pass
+
+static size_t join_lds_bytes(int maxm) {
+    const int mp = (maxm + 3) & ~3;
+    return (size_t)mp * (4 + 8 + 4 + 4 + 4) + (size_t)mp * JSTR * 4 + 64;
+}
+
+__global__ __launch_bounds__(JT) void k_join(
+    const float *__restrict__ X, int64_t ldx, int d, int K, const int32_t *__restrict__ jn,
+    const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
+    const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
+    int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
+    const uint8_t *__restrict__ mark, int64_t u0, int maxm,
+    unsigned long long *__restrict__ counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int mp_max = (maxm + 3) & ~3;
+    float *tile = reinterpret_cast<float *>(smem);
+    uint64_t *kth = reinterpret_cast<uint64_t *>(tile + (size_t)mp_max * JSTR);
+    int32_t *ids = reinterpret_cast<int32_t *>(kth + mp_max);
+    int32_t *cnt = ids + mp_max;
+    int32_t *base = cnt + mp_max;
+    int32_t *mk = base + mp_max;
+
+    const int tid = threadIdx.x;
+    const int64_t u = u0 + blockIdx.x;
+    const int nn = jn_c[u], no = jo_c[u];
+    const int m = nn + no;
+    if (nn == 0 || m < 2) return;
+    const int mp = (m + 3) & ~3;
+    int anymark = 0;
+    for (int i = tid; i < mp; i += JT) {
+        const int32_t id = i < nn ? jn[u * JN + i] : (i < m ? jo[u * JO + (i - nn)] : -1);
+        ids[i] = id;
+        kth[i] = id >= 0 ? keys[(int64_t)id * K + (K - 1)] : 0ull;
+        cnt[i] = 0;
+        const int mkv = (mark && id >= 0) ? (int)mark[id] : (mark ? 0 : 1);
+        mk[i] = mkv;
+        anymark |= (id >= 0 && mkv);
+    }
+    if (!__syncthreads_or(anymark)) return;
+
+    const int RB = (nn + 3) >> 2, CB = mp >> 2;
+    const int T = RB * CB - RB * (RB - 1) / 2;  // micro-tiles with cb >= rb
+    unsigned long long local_props = 0;
+    for (int pass0 = 0; pass0 < T; pass0 += JT * JMAXB) {
+        float acc[JMAXB][4][4];
+        int brb[JMAXB], bcb[JMAXB];
+#pragma unroll
+        for (int i = 0; i < JMAXB; ++i) {
+            int b = pass0 + tid + JT * i;
+            brb[i] = -1;
+            bcb[i] = 0;
+            if (b < T) {
+                int rb = 0;
+                while (b >= CB - rb) {
+                    b -= CB - rb;
+                    ++rb;
+                }
+                brb[i] = rb;
+                bcb[i] = rb + b;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[i][a][c] = 0.0f;
+        }
+        for (int c0 = 0; c0 < d; c0 += JDC) {
+            __syncthreads();
+            for (int e = tid; e < mp * (JDC / 4); e += JT) {
+                const int r = e / (JDC / 4), q = e % (JDC / 4);
+                const int32_t id = ids[r];
+                float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (id >= 0 && c0 + 4 * q < d)
+                    val = *reinterpret_cast<const float4 *>(X + (int64_t)id * ldx + c0 + 4 * q);
+                *reinterpret_cast<float4 *>(tile + r * JSTR + 4 * q) = val;
+            }
+            __syncthreads();
+            const int dlim = min(JDC, d - c0);
+#pragma unroll
+            for (int i = 0; i < JMAXB; ++i) {
+                if (brb[i] < 0) continue;
+                const float *rp = tile + (4 * brb[i]) * JSTR;
+                const float *cp = tile + (4 * bcb[i]) * JSTR;
+                for (int dd = 0; dd < dlim; dd += 4) {
+                    float4 r4[4], c4[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) r4[a] = *reinterpret_cast<const float4 *>(rp + a * JSTR + dd);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) c4[c] = *reinterpret_cast<const float4 *>(cp + c * JSTR + dd);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            float s = acc[i][a][c], t;
+                            t = r4[a].x - c4[c].x;
+                            s = fmaf(t, t, s);
+                            t = r4[a].y - c4[c].y;
+                            s = fmaf(t, t, s);
+                            t = r4[a].z - c4[c].z;
+                            s = fmaf(t, t, s);
+                            t = r4[a].w - c4[c].w;
+                            s = fmaf(t, t, s);
+                            acc[i][a][c] = s;
+                        }
+                }
+            }
+        }
+        // emission: count per member, reserve bucket ranges, write
+        for (int phase = 0; phase < 2; ++phase) {
+#pragma unroll
+            for (int i = 0; i < JMAXB; ++i) {
+                if (brb[i] < 0) continue;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int r = 4 * brb[i] + a, col = 4 * bcb[i] + c;
+                        if (r >= nn || col >= m || (col < nn && col <= r)) continue;
+                        const float d2 = acc[i][a][c];
+                        const int32_t v = ids[r], w = ids[col];
+                        const uint64_t kw = pack_key(d2, w), kv = pack_key(d2, v);
+                        // a repeat pass (mark != null) skips keys already listed, so
+                        // every repeat inserts at least one new key into each node it serves
+                        const bool to_v = mk[r] && kw < kth[r] &&
+                                          !(mark && list_has(keys + (int64_t)v * K, K, kw));
+                        const bool to_w = mk[col] && kv < kth[col] &&
+                                          !(mark && list_has(keys + (int64_t)w * K, K, kv));
+                        if (to_v) {
+                            if (phase == 0) {
+                                atomicAdd(&cnt[r], 1);
+                            } else {
+                                const int slot = base[r] + atomicAdd(&cnt[r], 1);
+                                if (slot < B) bucket[(int64_t)v * B + slot] = kw;
+                            }
+                        }
+                        if (to_w) {
+                            if (phase == 0) {
+                                atomicAdd(&cnt[col], 1);
+                            } else {
+                                const int slot = base[col] + atomicAdd(&cnt[col], 1);
+                                if (slot < B) bucket[(int64_t)w * B + slot] = kv;
+                            }
+                        }
+                    }
+            }
+            __syncthreads();
+            if (phase == 0) {
+                for (int i = tid; i < m; i += JT) {
+                    const int c = cnt[i];
+                    if (c > 0) {
+                        base[i] = atomicAdd(&pcnt[ids[i]], c);
+                        local_props += (unsigned long long)c;
+                    }
+                    cnt[i] = 0;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
+}
+
+// ---------------------------------------------------------------------------
+// merge: list <- K smallest distinct keys of (list U bucket)
+// flags per entry: bit 0 = new, bit 1 = inserted during this iteration
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
+                                               uint64_t *__restrict__ newm,
+                                               uint64_t *__restrict__ insm, int64_t n, int K,
+                                               int32_t *__restrict__ pcnt,
+                                               const uint64_t *__restrict__ bucket, int B,
+                                               uint8_t *__restrict__ ovf_next,
+                                               unsigned long long *__restrict__ counters) {
+    const int lane = lane_id();
+    const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= n) return;
+    const int c = pcnt[v];
+    if (c == 0) return;
+    uint64_t a = lane < K ? keys[v * K + lane] : KEY_INF;
+    const uint64_t nm = newm[v], im = insm[v];
+    int fl = lane < K ? (int)(((nm >> lane) & 1ull) | (((im >> lane) & 1ull) << 1)) : 0;
+    const int cc = min(c, B);
+    for (int b0 = 0; b0 < cc; b0 += PG_WAVE) {
+        const uint64_t kth = shfl64(a, K - 1);
+        uint64_t bk = (b0 + lane < cc) ? bucket[v * B + b0 + lane] : KEY_INF;
+        if (bk >= kth) bk = KEY_INF;
+        if (__ballot(bk != KEY_INF) == 0) continue;
+        int pb = 3;
+        wave_sort(bk, pb);
+        const uint64_t prev = shfl64(bk, max(lane - 1, 0));
+        const bool dup = lane > 0 && prev == bk;
+        const bool in_list = wave_contains(a, bk);
+        const bool valid = bk != KEY_INF && !dup && !in_list;
+        if (wave_compact(bk, pb, valid) == 0) continue;
+        wave_merge_lowest(a, fl, bk, pb);
+        if (lane >= K) {
+            a = KEY_INF;
+            fl = 0;
+        }
+    }
+    if (lane < K) keys[v * K + lane] = a;
+    const uint64_t nmo = __ballot(lane < K && (fl & 1));
+    const uint64_t imo = __ballot(lane < K && (fl & 2));
+    if (lane == 0) {
+        newm[v] = nmo;
+        insm[v] = imo;
+        pcnt[v] = 0;
+        if (c > B) {
+            ovf_next[v] = 1;
+            atomicAdd(&counters[C_OVF], 1ull);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count_updates(uint64_t *__restrict__ insm, int64_t n,
+                                                       unsigned long long *__restrict__ counters) {
+    __shared__ unsigned long long s[256];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned long long c = 0;
+    if (v < n) {
+        c = (unsigned long long)__popcll(insm[v]);
+        insm[v] = 0;
+    }
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && s[0]) atomicAdd(&counters[C_UPDATES], s[0]);
+}
+
+__global__ void k_unpack(const uint64_t *__restrict__ keys, int64_t total,
+                         int32_t *__restrict__ ids, float *__restrict__ d2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const uint64_t k = keys[i];
+    ids[i] = k == KEY_INF ? -1 : key_id(k);
+    d2[i] = k == KEY_INF ? __int_as_float(0x7f800000) : key_d2(k);
+}
+
+__global__ void k_mark_swap(uint8_t *__restrict__ mark, uint8_t *__restrict__ next, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    mark[i] = next[i];
+    next[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// exact brute-force kNN: 64 queries x 64 points tiles, running top-k per query
+// ---------------------------------------------------------------------------
+constexpr int EQ = 64, EP = 64, EDC = 32, ESTR = EDC + 4;
+
+__global__ __launch_bounds__(256) void k_exact_knn(const float *__restrict__ X, int64_t n, int d,
+                                                   int64_t ldx, const float *__restrict__ Q,
+                                                   int64_t nq, int64_t ldq,
+                                                   const int32_t *__restrict__ exclude,
+                                                   int self_excl, int k,
+                                                   int32_t *__restrict__ out_ids,
+                                                   float *__restrict__ out_d2) {
+    __shared__ __align__(16) float qt[EQ * ESTR];
+    __shared__ __align__(16) float pt[EP * ESTR];
+    __shared__ float dt[EQ * (EP + 1)];
+    __shared__ uint64_t topk[EQ * PG_WAVE];
+    __shared__ int32_t excl[EQ];
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int64_t q0 = (int64_t)blockIdx.x * EQ;
+    for (int i = tid; i < EQ * PG_WAVE; i += 256) topk[i] = KEY_INF;
+    for (int i = tid; i < EQ; i += 256)
+        excl[i] = q0 + i >= nq ? -1 : (self_excl ? (int32_t)(q0 + i) : (exclude ? exclude[q0 + i] : -1));
+    for (int64_t p0 = 0; p0 < n; p0 += EP) {
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0f;
+        for (int c0 = 0; c0 < d; c0 += EDC) {
+            __syncthreads();
+            for (int e = tid; e < (EQ + EP) * (EDC / 4); e += 256) {
+                const int r = e / (EDC / 4), q = e % (EDC / 4);
+                float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r < EQ) {
+                    if (q0 + r < nq && c0 + 4 * q < d)
+                        val = *reinterpret_cast<const float4 *>(Q + (q0 + r) * ldq + c0 + 4 * q);
+                    *reinterpret_cast<float4 *>(qt + r * ESTR + 4 * q) = val;
+                } else {
+                    const int rr = r - EQ;
+                    if (p0 + rr < n && c0 + 4 * q < d)
+                        val = *reinterpret_cast<const float4 *>(X + (p0 + rr) * ldx + c0 + 4 * q);
+                    *reinterpret_cast<float4 *>(pt + rr * ESTR + 4 * q) = val;
+                }
+            }
+            __syncthreads();
+            const int dlim = min(EDC, d - c0);
+            for (int dd = 0; dd < dlim; dd += 4) {
+                float4 r4[4], c4[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    r4[a] = *reinterpret_cast<const float4 *>(qt + (4 * ty + a) * ESTR + dd);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    c4[b] = *reinterpret_cast<const float4 *>(pt + (4 * tx + b) * ESTR + dd);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        float s = acc[a][b], t;
+                        t = r4[a].x - c4[b].x;
+                        s = fmaf(t, t, s);
+                        t = r4[a].y - c4[b].y;
+                        s = fmaf(t, t, s);
+                        t = r4[a].z - c4[b].z;
+                        s = fmaf(t, t, s);
+                        t = r4[a].w - c4[b].w;
+                        s = fmaf(t, t, s);
+                        acc[a][b] = s;
+                    }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) dt[(4 * ty + a) * (EP + 1) + 4 * tx + b] = acc[a][b];
+        __syncthreads();
+        for (int qq = 0; qq < EQ / 4; ++qq) {
+            const int q = w * (EQ / 4) + qq;
+            if (q0 + q >= nq) break;
+            const int64_t pid = p0 + lane;
+            uint64_t key = (pid < n && pid != excl[q]) ? pack_key(dt[q * (EP + 1) + lane], (int32_t)pid)
+                                                       : KEY_INF;
+            uint64_t cur = topk[q * PG_WAVE + lane];
+            const uint64_t kth = shfl64(cur, k - 1);
+            if (key >= kth) key = KEY_INF;
+            if (__ballot(key != KEY_INF) == 0) continue;
+            int pk = 0, pc = 0;
+            wave_sort(key, pk);
+            wave_merge_lowest(cur, pc, key, pk);
+            if (lane >= k) cur = KEY_INF;
+            topk[q * PG_WAVE + lane] = cur;
+        }
+    }
+    __syncthreads();
+    for (int qq = 0; qq < EQ / 4; ++qq) {
+        const int q = w * (EQ / 4) + qq;
+        if (q0 + q >= nq) break;
+        if (lane < k) {
+            const uint64_t key = topk[q * PG_WAVE + lane];
+            out_ids[(q0 + q) * k + lane] = key == KEY_INF ? -1 : key_id(key);
+            out_d2[(q0 + q) * k + lane] = key == KEY_INF ? __int_as_float(0x7f800000) : key_d2(key);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct KnnLayout {
+    size_t keys, newm, insm, nf, nf_c, of, of_c, rn_cnt, ro_cnt, rn_off, ro_off, rn_list, ro_list,
+        jn, jn_c, jo, jo_c, pcnt, bucket, mark, mark_next, counters, scan_tmp, total;
+    int B, JN, JO;
+};
+
+static int default_bucket(int K) { return 4 * K; }
+
+static KnnLayout knn_layout(const pg_knn_params *p, int64_t n) {
+    KnnLayout L{};
+    const int64_t K = p->K, S = p->S;
+    L.B = p->bucket_cap > 0 ? p->bucket_cap : default_bucket(p->K);
+    L.JN = (int)(2 * S);
+    L.JO = (int)(K + S);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += pg_align(bytes);
+        return at;
+    };
+    L.keys = take(sizeof(uint64_t) * n * K);
+    L.newm = take(sizeof(uint64_t) * n);
+    L.insm = take(sizeof(uint64_t) * n);
+    L.nf = take(sizeof(int32_t) * n * S);
+    L.nf_c = take(sizeof(int32_t) * n);
+    L.of = take(sizeof(int32_t) * n * K);
+    L.of_c = take(sizeof(int32_t) * n);
+    L.rn_cnt = take(sizeof(int32_t) * n);
+    L.ro_cnt = take(sizeof(int32_t) * n);
+    L.rn_off = take(sizeof(int64_t) * (n + 1));
+    L.ro_off = take(sizeof(int64_t) * (n + 1));
+    L.rn_list = take(sizeof(int32_t) * n * S);
+    L.ro_list = take(sizeof(int32_t) * n * K);
+    L.jn = take(sizeof(int32_t) * n * L.JN);
+    L.jn_c = take(sizeof(int32_t) * n);
+    L.jo = take(sizeof(int32_t) * n * L.JO);
+    L.jo_c = take(sizeof(int32_t) * n);
+    L.pcnt = take(sizeof(int32_t) * n);
+    L.bucket = take(sizeof(uint64_t) * n * (size_t)L.B);
+    L.mark = take(n);
+    L.mark_next = take(n);
+    L.counters = take(sizeof(unsigned long long) * C_NCOUNTERS);
+    L.scan_tmp = take(scan_tmp_bytes(n + 1));
+    L.total = o;
+    return L;
+}
+
+static pg_status check_knn(const pg_knn_params *p, int64_t n, int32_t d) {
+    if (!p) {
+        set_error("pg_knn_build: params is NULL");
+        return PG_EINVAL;
+    }
+    if (n < 2 || n >= (int64_t)1 << 31) {
+        set_error("pg_knn_build: n=%lld out of range [2, 2^31)", (long long)n);
+        return PG_EINVAL;
+    }
+    if (d <= 0 || d % 4) {
+        set_error("pg_knn_build: d=%d must be a positive multiple of 4", d);
+        return d <= 0 ? PG_EINVAL : PG_EUNSUPPORTED;
+    }
+    if (p->K < 1 || p->K > 64 || p->K >= n) {
+        set_error("pg_knn_build: K=%d must satisfy 1 <= K <= 64 and K < n", p->K);
+        return PG_EINVAL;
+    }
+    if (p->exact) return PG_OK;
+    if (p->S < 1 || p->S > p->K || p->S > 32) {
+        set_error("pg_knn_build: S=%d must satisfy 1 <= S <= min(K, 32)", p->S);
+        return PG_EINVAL;
+    }
+    if (p->max_iters < 0 || p->max_iters > 64) {
+        set_error("pg_knn_build: max_iters=%d out of [0, 64]", p->max_iters);
+        return PG_EINVAL;
+    }
+    if (p->precision != PG_FP32) {
+        set_error("pg_knn_build: precision %d not supported", p->precision);
+        return PG_EUNSUPPORTED;
+    }
+    if (p->bucket_cap != 0 && p->bucket_cap < 2 * p->K) {
+        set_error("pg_knn_build: bucket_cap=%d must be 0 or >= 2K", p->bucket_cap);
+        return PG_EINVAL;
+    }
+    if (p->chunks < 0) {
+        set_error("pg_knn_build: chunks=%d must be >= 0", p->chunks);
+        return PG_EINVAL;
+    }
+    return PG_OK;
+}
+
+}  // namespace pgi
+
+using namespace pgi;
+
+extern "C" pg_status pg_knn_build_workspace(const pg_knn_params *p, int64_t n, int32_t d,
+                                            size_t *bytes) {
+    PG_TRY(check_knn(p, n, d));
+    if (!bytes) {
+        set_error("pg_knn_build_workspace: bytes is NULL");
+        return PG_EINVAL;
+    }
+    *bytes = p->exact ? 0 : knn_layout(p, n).total;
+    return PG_OK;
+}
+
+static pg_status launch_exact(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                              const float *Q, int64_t nq, int64_t ldq, const int32_t *exclude,
+                              int self_excl, int32_t k, int32_t *out_ids, float *out_d2) {
+    if (nq == 0) return PG_OK;
+    const int64_t blocks = (nq + EQ - 1) / EQ;
+    TimedLaunch tl(ctx, K_EXACT, 3.0 * (double)n * (double)nq * d);
+    hipLaunchKernelGGL(k_exact_knn, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, X, n, d, ldx, Q,
+                       nq, ldq, exclude, self_excl, k, out_ids, out_d2);
+    PG_HIP(hipGetLastError());
+    return PG_OK;
+}
+
+extern "C" pg_status pg_exact_knn(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                  const float *Q, int64_t nq, int64_t ldq, const int32_t *exclude,
+                                  int32_t k, int32_t *out_ids, float *out_d2) {
+    if (!ctx || !X || !Q || !out_ids || !out_d2) {
+        set_error("pg_exact_knn: NULL argument");
+        return PG_EINVAL;
+    }
+    if (n < 1 || n >= (int64_t)1 << 31 || nq < 0 || k < 1 || k > 64 || d <= 0 || ldx < d ||
+        ldq < d) {
+        set_error("pg_exact_knn: bad sizes n=%lld nq=%lld d=%d k=%d", (long long)n,
+                  (long long)nq, d, k);
+        return PG_EINVAL;
+    }
+    if (d % 4 || ldx % 4 || ldq % 4 || ((uintptr_t)X & 15) || ((uintptr_t)Q & 15)) {
+        set_error("pg_exact_knn: d, ldx, ldq must be multiples of 4 and X, Q 16-byte aligned");
+        return PG_EUNSUPPORTED;
+    }
+    return launch_exact(ctx, X, n, d, ldx, Q, nq, ldq, exclude, 0, k, out_ids, out_d2);
+}
+
+static pg_status knn_exact_lists(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                 int K, int32_t *ids, float *d2) {
+    // the rows of X are their own queries; each skips itself
+    PG_TRY(launch_exact(ctx, X, n, d, ldx, X, n, ldx, nullptr, 1, K, ids, d2));
+    PG_HIP(hipStreamSynchronize(ctx->stream));
+    return PG_OK;
+}
+
+extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                  const pg_knn_params *p, void *ws, size_t ws_bytes,
+                                  int32_t *knn_ids, float *knn_d2, pg_knn_stats *stats) {
+    if (!ctx || !X || !knn_ids || !knn_d2) {
+        set_error("pg_knn_build: NULL argument");
+        return PG_EINVAL;
+    }
+    PG_TRY(check_knn(p, n, d));
+    if (ldx < d || ldx % 4 || ((uintptr_t)X & 15)) {
+        set_error("pg_knn_build: ldx must be >= d and a multiple of 4, X 16-byte aligned");
+        return PG_EUNSUPPORTED;
+    }
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (p->exact) return knn_exact_lists(ctx, X, n, d, ldx, p->K, knn_ids, knn_d2);
+    const KnnLayout L = knn_layout(p, n);
+    if (!ws || ws_bytes < L.total) {
+        set_error("pg_knn_build: workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                  L.total);
+        return PG_ENOMEM;
+    }
+    char *w = (char *)ws;
+    uint64_t *keys = (uint64_t *)(w + L.keys), *newm = (uint64_t *)(w + L.newm),
+             *insm = (uint64_t *)(w + L.insm);
+    int32_t *nf = (int32_t *)(w + L.nf), *nf_c = (int32_t *)(w + L.nf_c), *of = (int32_t *)(w + L.of),
+            *of_c = (int32_t *)(w + L.of_c), *rn_cnt = (int32_t *)(w + L.rn_cnt),
+            *ro_cnt = (int32_t *)(w + L.ro_cnt), *rn_list = (int32_t *)(w + L.rn_list),
+            *ro_list = (int32_t *)(w + L.ro_list), *jn = (int32_t *)(w + L.jn),
+            *jn_c = (int32_t *)(w + L.jn_c), *jo = (int32_t *)(w + L.jo),
+            *jo_c = (int32_t *)(w + L.jo_c), *pcnt = (int32_t *)(w + L.pcnt);
+    int64_t *rn_off = (int64_t *)(w + L.rn_off), *ro_off = (int64_t *)(w + L.ro_off);
+    uint64_t *bucket = (uint64_t *)(w + L.bucket);
+    uint8_t *mark = (uint8_t *)(w + L.mark), *mark_next = (uint8_t *)(w + L.mark_next);
+    unsigned long long *counters = (unsigned long long *)(w + L.counters);
+    void *scan_tmp = w + L.scan_tmp;
+    hipStream_t st = ctx->stream;
+    const int K = p->K, S = p->S;
+    const unsigned wave_blocks = (unsigned)((n + 3) / 4);
+
+    PG_HIP(hipMemsetAsync(pcnt, 0, sizeof(int32_t) * n, st));
+    PG_HIP(hipMemsetAsync(mark_next, 0, n, st));
+    {
+        TimedLaunch tl(ctx, K_INIT, (double)n * K * (8.0 + 4.0 * d));
+        hipLaunchKernelGGL(k_init, dim3(wave_blocks), dim3(256), 0, st, X, ldx, d, n, K, p->seed,
+                           keys, newm, insm);
+        PG_HIP(hipGetLastError());
+    }
+    const int maxm = 3 * S + K;
+    const size_t lds = join_lds_bytes(maxm);
+    int iters = 0;
+    int64_t prev_props = -1;
+    for (int t = 1; t <= p->max_iters; ++t) {
+        PG_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * C_NCOUNTERS, st));
+        PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
+        PG_HIP(hipMemsetAsync(ro_cnt, 0, sizeof(int32_t) * n, st));
+        {
+            TimedLaunch tl(ctx, K_SAMPLE, (double)n * K * 8.0);
+            hipLaunchKernelGGL(k_sample, dim3(wave_blocks), dim3(256), 0, st, keys, newm, n, K, S,
+                               p->seed, (uint64_t)(3 * t), nf, nf_c, of, of_c, rn_cnt, ro_cnt);
+            PG_HIP(hipGetLastError());
+        }
+        PG_TRY(scan_exclusive(ctx, rn_cnt, rn_off, n, scan_tmp));
+        PG_TRY(scan_exclusive(ctx, ro_cnt, ro_off, n, scan_tmp));
+        PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
+        PG_HIP(hipMemsetAsync(ro_cnt, 0, sizeof(int32_t) * n, st));
+        hipLaunchKernelGGL(k_rev_scatter, dim3(wave_blocks), dim3(256), 0, st, n, nf, nf_c, S, of,
+                           of_c, K, rn_off, rn_cnt, rn_list, ro_off, ro_cnt, ro_list);
+        PG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_build_join, dim3(wave_blocks), dim3(256), 0, st, n, K, S, p->seed,
+                           (uint64_t)(3 * t + 1), (uint64_t)(3 * t + 2), nf, nf_c, of, of_c, rn_off,
+                           rn_list, ro_off, ro_list, jn, jn_c, L.JN, jo, jo_c, L.JO, counters);
+        PG_HIP(hipGetLastError());
+        // source passes: many in the first iteration (random lists accept almost
+        // every proposal), fewer once the lists are good; the count never
+        // changes the result
+        // first iteration: pass sizes n/c, n/c, 2n/c, 4n/c, ... (each merge
+        // tightens every K-th key, so later passes emit fewer proposals)
+        std::vector<int64_t> bounds{0};
+        if (prev_props < 0) {
+            const int64_t c0 = p->chunks > 0 ? p->chunks : 64;
+            int64_t sz = std::max<int64_t>(1, n / c0), at = 0;
+            bool first = true;
+            while (at < n) {
+                at = std::min<int64_t>(n, at + sz);
+                bounds.push_back(at);
+                if (!first) sz *= 2;
+                first = false;
+            }
+        } else {
+            const double cap = 0.5 * (double)L.B * (double)n;
+            const int nch = (int)std::min<double>(
+                64.0, std::max<double>(1.0, std::ceil((double)prev_props / cap)));
+            const int64_t step = (n + nch - 1) / nch;
+            for (int64_t at = step; ; at += step) {
+                bounds.push_back(std::min(at, n));
+                if (at >= n) break;
+            }
+        }
+        for (size_t ci = 0; ci + 1 < bounds.size(); ++ci) {
+            const int64_t u0 = bounds[ci];
+            const int64_t cnt = bounds[ci + 1] - u0;
+            const uint8_t *mk = nullptr;
+            for (int attempt = 0;; ++attempt) {
+                {
+                    TimedLaunch tl(ctx, K_JOIN, -1.0);
+                    hipLaunchKernelGGL(k_join, dim3((unsigned)cnt), dim3(JT), lds, st, X, ldx, d, K, jn,
+                                       jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt, bucket, L.B, mk, u0,
+                                       maxm, counters);
+                    PG_HIP(hipGetLastError());
+                }
+                {
+                    TimedLaunch tl(ctx, K_MERGE, -1.0);
+                    hipLaunchKernelGGL(k_merge, dim3(wave_blocks), dim3(256), 0, st, keys, newm, insm,
+                                       n, K, pcnt, bucket, L.B, mark_next, counters);
+                    PG_HIP(hipGetLastError());
+                }
+                unsigned long long ovf = 0;
+                PG_HIP(hipMemcpyAsync(&ovf, counters + C_OVF, sizeof(ovf), hipMemcpyDeviceToHost, st));
+                PG_HIP(hipStreamSynchronize(st));
+                if (ovf == 0) break;
+                if (attempt >= 1000) {
+                    set_error("pg_knn_build: proposal buckets kept overflowing");
+                    return PG_EOVERFLOW;
+                }
+                if (stats) stats->retries++;
+                PG_HIP(hipMemsetAsync(counters + C_OVF, 0, sizeof(unsigned long long), st));
+                hipLaunchKernelGGL(k_mark_swap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                                   mark, mark_next, n);
+                PG_HIP(hipGetLastError());
+                mk = mark;
+            }
+        }
+        hipLaunchKernelGGL(k_count_updates, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, insm,
+                           n, counters);
+        PG_HIP(hipGetLastError());
+        unsigned long long hc[C_NCOUNTERS];
+        PG_HIP(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+        PG_HIP(hipStreamSynchronize(st));
+        iters = t;
+        prev_props = (int64_t)hc[C_PROPOSALS];
+        if (stats) {
+            stats->updates[t - 1] = (int64_t)hc[C_UPDATES];
+            stats->pairs[t - 1] = (int64_t)hc[C_PAIRS];
+            stats->proposals[t - 1] = (int64_t)hc[C_PROPOSALS];
+        }
+        ctx_add_work(ctx, K_JOIN, 3.0 * (double)hc[C_PAIRS] * d);
+        if ((int64_t)hc[C_UPDATES] <= p->stop_updates) break;
+    }
+    if (stats) stats->iters_run = iters;
+    const int64_t total = n * K;
+    hipLaunchKernelGGL(k_unpack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys, total,
+                       knn_ids, knn_d2);
+    PG_HIP(hipGetLastError());
+    PG_HIP(hipStreamSynchronize(st));
+    return PG_OK;
+}

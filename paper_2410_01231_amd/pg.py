@@ -1,0 +1,262 @@
+"""Thin Python binding of the C ABI in include/pg.h (libpg.so, gfx950 HIP kernels).
+
+Argument marshalling only: every step of the build and search runs in the
+library's kernels.  torch supplies device memory and the current HIP stream.
+The library must be built (``paper_2410_01231_amd.build.build()``); there is no
+fallback of any kind, so importing a function without the library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t, \
+    c_uint32, c_uint64, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpg.so")
+
+STAGE_PRUNE, STAGE_REVERSE, STAGE_CONNECT = 1, 2, 4
+STAGES_ALL = STAGE_PRUNE | STAGE_REVERSE | STAGE_CONNECT
+FP32, FP16, BF16 = 0, 1, 2
+
+
+class PgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pg status {status}: {msg}")
+        self.status = status
+
+
+class KnnParams(ctypes.Structure):
+    _fields_ = [("K", c_int32), ("S", c_int32), ("max_iters", c_int32), ("exact", c_int32),
+                ("stop_updates", c_int64), ("seed", c_uint64), ("precision", c_int32),
+                ("margin_rel", c_float), ("bucket_cap", c_int32), ("chunks", c_int32)]
+
+
+class KnnStats(ctypes.Structure):
+    _fields_ = [("iters_run", c_int32), ("reserved", c_int32), ("updates", c_int64 * 64),
+                ("pairs", c_int64 * 64), ("proposals", c_int64 * 64), ("retries", c_int64)]
+
+
+class PruneParams(ctypes.Structure):
+    _fields_ = [("R", c_int32), ("alpha_deg", c_float), ("stages", c_uint32),
+                ("strict_ties", c_int32), ("pair_d2", c_void_p)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("k", c_int32), ("L", c_int32), ("n_entry", c_int32), ("entry_ids", c_void_p)]
+
+
+EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
+           "pg_ctx_kernel_time", "pg_ctx_reset_timing", "pg_knn_build_workspace", "pg_knn_build",
+           "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpg.so and declare every exported signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2410_01231_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    lib.pg_version.restype = c_int
+    lib.pg_last_error.restype = c_char_p
+    lib.pg_ctx_create.argtypes = [c_int, P, POINTER(c_void_p)]
+    lib.pg_ctx_destroy.argtypes = [P]
+    lib.pg_ctx_set_timing.argtypes = [P, c_int]
+    lib.pg_ctx_reset_timing.argtypes = [P]
+    lib.pg_ctx_kernel_time.argtypes = [P, c_char_p, POINTER(c_double), POINTER(c_int64),
+                                       POINTER(c_double)]
+    lib.pg_knn_build_workspace.argtypes = [POINTER(KnnParams), c_int64, c_int32, POINTER(c_size_t)]
+    lib.pg_knn_build.argtypes = [P, P, c_int64, c_int32, c_int64, POINTER(KnnParams), P, c_size_t,
+                                 P, P, POINTER(KnnStats)]
+    lib.pg_exact_knn.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int64, c_int64, P, c_int32,
+                                 P, P]
+    lib.pg_prune_workspace.argtypes = [POINTER(PruneParams), c_int64, c_int32, POINTER(c_size_t)]
+    lib.pg_prune.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, POINTER(PruneParams), P,
+                             c_size_t, P, P, P, P, P, POINTER(c_int32)]
+    lib.pg_search.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, P, P, c_int64, c_int64,
+                              POINTER(SearchParams), P, P]
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        if name not in ("pg_version", "pg_last_error"):
+            f.restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != 0:
+        msg = load_library().pg_last_error().decode()
+        raise PgError(status, f"{what}: {msg}")
+
+
+class Context:
+    """A pg_ctx bound to a device and a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device=None, stream=None):
+        lib = load_library()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = c_void_p()
+        _check(lib.pg_ctx_create(dev.index, c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "pg_ctx_create")
+        self.handle = h
+
+    def set_timing(self, enable: bool):
+        _check(load_library().pg_ctx_set_timing(self.handle, int(bool(enable))), "set_timing")
+
+    def reset_timing(self):
+        _check(load_library().pg_ctx_reset_timing(self.handle), "reset_timing")
+
+    def kernel_time(self, name: str):
+        """(total_ms, launches, work) of the named kernel since the last reset."""
+        ms, cnt, work = c_double(), c_int64(), c_double()
+        _check(load_library().pg_ctx_kernel_time(self.handle, name.encode(), ctypes.byref(ms),
+                                                 ctypes.byref(cnt), ctypes.byref(work)),
+               "kernel_time")
+        return ms.value, cnt.value, work.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.pg_ctx_destroy(self.handle)
+        except Exception:
+            pass
+
+
+_contexts = {}
+
+
+def context(device=None) -> Context:
+    """The cached context for the device's current stream."""
+    dev = torch.cuda.current_device() if device is None else device
+    s = torch.cuda.current_stream(dev)
+    key = (dev, s.cuda_stream)
+    if key not in _contexts:
+        _contexts[key] = Context(dev, s)
+    return _contexts[key]
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+def _dev_f32(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.dim() == 2):
+        raise TypeError(f"{name} must be a 2-D float32 device tensor")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit stride along its rows")
+    return t
+
+
+def _dev_i32(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32):
+        raise TypeError(f"{name} must be an int32 device tensor")
+    return t.contiguous()
+
+
+def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001, exact=False,
+              bucket_cap=0, chunks=0, ctx=None):
+    """NN-Descent kNN lists of the rows of X: returns (ids, d2, stats dict)."""
+    lib = load_library()
+    X = _dev_f32(X, "X")
+    n, d = X.shape
+    S = (K + 1) // 2 if S is None else S
+    if stop_updates is None:
+        stop_updates = int(delta * n * K)
+    p = KnnParams(K=K, S=S, max_iters=max_iters, exact=int(bool(exact)), stop_updates=stop_updates,
+                  seed=seed & (2**64 - 1), precision=FP32, margin_rel=0.0, bucket_cap=bucket_cap,
+                  chunks=chunks)
+    ws_bytes = c_size_t()
+    _check(lib.pg_knn_build_workspace(ctypes.byref(p), n, d, ctypes.byref(ws_bytes)), "workspace")
+    ws = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=X.device)
+    ids = torch.empty((n, K), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((n, K), dtype=torch.float32, device=X.device)
+    st = KnnStats()
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_knn_build(ctx.handle, _ptr(X), n, d, X.stride(0), ctypes.byref(p), _ptr(ws),
+                            ws_bytes.value, _ptr(ids), _ptr(d2), ctypes.byref(st)), "pg_knn_build")
+    it = st.iters_run
+    stats = {"iters": it, "updates": list(st.updates[:it]), "pairs": list(st.pairs[:it]),
+             "proposals": list(st.proposals[:it]), "retries": st.retries}
+    return ids, d2, stats
+
+
+def exact_knn(X, Q, k, exclude=None, ctx=None):
+    """Brute-force k nearest rows of X for every row of Q: returns (ids, d2)."""
+    lib = load_library()
+    X, Q = _dev_f32(X, "X"), _dev_f32(Q, "Q")
+    n, d = X.shape
+    nq = Q.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((nq, k), dtype=torch.float32, device=X.device)
+    ex = None if exclude is None else _dev_i32(exclude, "exclude")
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_exact_knn(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(Q), nq, Q.stride(0),
+                            _ptr(ex), k, _ptr(ids), _ptr(d2)), "pg_exact_knn")
+    return ids, d2
+
+
+def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair_d2=None,
+          ctx=None):
+    """Refinement of Alg. 2: returns dict(ids, d2, deg, ep, roots)."""
+    lib = load_library()
+    X = _dev_f32(X, "X")
+    cand = _dev_i32(cand, "cand")
+    n, d = X.shape
+    C = cand.shape[1]
+    tab = None
+    if pair_d2 is not None:
+        tab = pair_d2.contiguous()
+        if tab.dtype != torch.float32 or tuple(tab.shape) != (n, C + 1, C + 1):
+            raise ValueError("pair_d2 must be float32 of shape (n, C+1, C+1)")
+    p = PruneParams(R=R, alpha_deg=float(alpha_deg), stages=stages, strict_ties=int(bool(strict_ties)),
+                    pair_d2=tab.data_ptr() if tab is not None else None)
+    ws_bytes = c_size_t()
+    _check(lib.pg_prune_workspace(ctypes.byref(p), n, C, ctypes.byref(ws_bytes)), "workspace")
+    ws = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=X.device)
+    g_ids = torch.empty((n, R), dtype=torch.int32, device=X.device)
+    g_d2 = torch.empty((n, R), dtype=torch.float32, device=X.device)
+    g_deg = torch.empty(n, dtype=torch.int32, device=X.device)
+    ep = torch.empty(1, dtype=torch.int32, device=X.device)
+    roots = torch.empty(n, dtype=torch.int32, device=X.device)
+    nroots = c_int32(0)
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_prune(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(cand), C, ctypes.byref(p),
+                        _ptr(ws), ws_bytes.value, _ptr(g_ids), _ptr(g_d2), _ptr(g_deg), _ptr(ep),
+                        _ptr(roots), ctypes.byref(nroots)), "pg_prune")
+    return {"ids": g_ids, "d2": g_d2, "deg": g_deg, "ep": ep, "roots": roots[:nroots.value]}
+
+
+def search(X, g_ids, g_deg, Q, entries, k, L, ctx=None):
+    """Alg. 1 beam search for every row of Q: returns (ids, d2)."""
+    lib = load_library()
+    X, Q = _dev_f32(X, "X"), _dev_f32(Q, "Q")
+    g_ids, g_deg = _dev_i32(g_ids, "g_ids"), _dev_i32(g_deg, "g_deg")
+    entries = _dev_i32(entries.reshape(-1), "entries")
+    n, d = X.shape
+    nq = Q.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((nq, k), dtype=torch.float32, device=X.device)
+    p = SearchParams(k=k, L=L, n_entry=entries.numel(), entry_ids=entries.data_ptr())
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_search(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(g_ids), g_ids.shape[1],
+                         _ptr(g_deg), _ptr(Q), nq, Q.stride(0), ctypes.byref(p), _ptr(ids), _ptr(d2)),
+           "pg_search")
+    return ids, d2
+
+
+def build_graph(X, K, R, S=None, max_iters=12, seed=0, delta=0.001, alpha_deg=60.0, ctx=None,
+                **knn_kw):
+    """The whole build path: NN-Descent lists, then prune, reverse, entry point, connect."""
+    ids, d2, st = knn_build(X, K, S=S, max_iters=max_iters, seed=seed, delta=delta, ctx=ctx, **knn_kw)
+    g = prune(X, ids, R, alpha_deg=alpha_deg, ctx=ctx)
+    g["knn_ids"], g["knn_d2"], g["knn_stats"] = ids, d2, st
+    return g

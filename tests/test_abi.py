@@ -1,0 +1,94 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/pg.h declares; the binding's ctypes structures match the header's
+layout (checked against gcc's own sizeof/offsetof of the header)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pg_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2410_01231_amd import pg
+    if not os.path.exists(pg.LIB_PATH):
+        pytest.fail("libpg.so is not built (run __graft_entry__.build())")
+    return pg.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert len(declared) >= 13
+    out = subprocess.run(["nm", "-D", "--defined-only",
+                          os.path.join(ROOT, "paper_2410_01231_amd", "libpg.so")],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (pg_[a-z_]+)", out))
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    for s in declared:
+        assert hasattr(lib, s)
+
+
+def test_binding_covers_header():
+    from paper_2410_01231_amd import pg
+    assert sorted(pg.EXPORTS) == _declared()
+
+
+def test_version_and_error_without_gpu(lib):
+    assert lib.pg_version() >= 100
+    assert isinstance(lib.pg_last_error(), bytes)
+
+
+def test_argument_errors_need_no_device(lib):
+    from paper_2410_01231_amd import pg
+    p = pg.KnnParams(K=0, S=1, max_iters=1)
+    sz = ctypes.c_size_t()
+    rc = lib.pg_knn_build_workspace(ctypes.byref(p), 100, 8, ctypes.byref(sz))
+    assert rc == -1 and b"K=0" in lib.pg_last_error()
+    p = pg.KnnParams(K=8, S=4, max_iters=3)
+    assert lib.pg_knn_build_workspace(ctypes.byref(p), 1000, 8, ctypes.byref(sz)) == 0
+    assert sz.value > 1000 * 8 * 8
+    p = pg.KnnParams(K=8, S=4, max_iters=3)
+    assert lib.pg_knn_build_workspace(ctypes.byref(p), 1000, 6, ctypes.byref(sz)) == -4
+    q = pg.PruneParams(R=8, alpha_deg=60.0, stages=2)
+    assert lib.pg_prune_workspace(ctypes.byref(q), 100, 8, ctypes.byref(sz)) == -1
+    q = pg.PruneParams(R=8, alpha_deg=60.0, stages=pg.STAGES_ALL)
+    assert lib.pg_prune_workspace(ctypes.byref(q), 100, 8, ctypes.byref(sz)) == 0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_2410_01231_amd import pg
+    prog = tmp_path / "layout.c"
+    prog.write_text("""
+#include <stddef.h>
+#include <stdio.h>
+#include "pg.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(pg_knn_params), sizeof(pg_knn_stats),
+         sizeof(pg_prune_params), sizeof(pg_search_params));
+  printf("%zu %zu %zu %zu\\n", offsetof(pg_knn_params, stop_updates), offsetof(pg_knn_params, chunks),
+         offsetof(pg_prune_params, pair_d2), offsetof(pg_search_params, entry_ids));
+  printf("%zu\\n", offsetof(pg_knn_stats, retries));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    sizes = [int(x) for x in lines[0].split()]
+    offs = [int(x) for x in lines[1].split()]
+    assert sizes == [ctypes.sizeof(pg.KnnParams), ctypes.sizeof(pg.KnnStats),
+                     ctypes.sizeof(pg.PruneParams), ctypes.sizeof(pg.SearchParams)]
+    assert offs == [pg.KnnParams.stop_updates.offset, pg.KnnParams.chunks.offset,
+                    pg.PruneParams.pair_d2.offset, pg.SearchParams.entry_ids.offset]
+    assert int(lines[2]) == pg.KnnStats.retries.offset

@@ -1,0 +1,256 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Integer-valued data makes every float32 squared distance exact (all partial
+sums are integers below 2^24), so on it the two sides must agree bit for bit:
+distances, kNN lists, NN-Descent counters, prune edge sets, entry point,
+connect roots and search results.  On float data the distances must agree to
+1e-5 relative and whole-graph results statistically.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pg():
+    from paper_2410_01231_amd import pg as _pg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    _pg.load_library()
+    return _pg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------- exact kNN
+@pytest.mark.parametrize("n,d,k", [(3000, 128, 10), (777, 96, 64), (65, 4, 1)])
+def test_exact_knn_bit_exact(pg, oracle, datagen, n, d, k):
+    log("exact_knn", n, d, k)
+    X = datagen.uniform_int(n, d, seed=n)
+    Q = datagen.uniform_int(123, d, seed=n + 1)
+    ids, d2 = pg.exact_knn(dev(X), dev(Q), k)
+    rid, rd2 = oracle.exact_knn(X, Q, k)
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d2), rd2.astype(np.float32))
+    # data as its own queries, each skipping itself
+    ex = np.arange(200, dtype=np.int32)
+    ids, d2 = pg.exact_knn(dev(X), dev(X[:200]), k, exclude=dev(ex))
+    rid, rd2 = oracle.exact_knn(X, X[:200], k, exclude=ex)
+    assert np.array_equal(host(ids), rid)
+
+
+def test_exact_knn_float_tolerance(pg, oracle, datagen):
+    X, Q = datagen.gist_like(1500, 40, d=960, seed=3)
+    ids, d2 = pg.exact_knn(dev(X), dev(Q), 10)
+    rid, rd2 = oracle.exact_knn(X, Q, 10)
+    g = host(d2).astype(np.float64)
+    assert np.max(np.abs(g - rd2) / rd2) < 1e-5
+    # ids may differ only where the two candidates' true distances are within tolerance
+    same = host(ids) == rid
+    assert same.mean() > 0.99
+
+
+# ---------------------------------------------------------------- NN-Descent
+def _knn_oracle(oracle, X, K, S, T, seed, stop):
+    return oracle.nndescent(X, K, S, T, seed, stop_updates=stop)
+
+
+@pytest.mark.parametrize("n,d,K,S,T", [(1500, 32, 16, 8, 5), (700, 12, 8, 4, 6), (90, 8, 64, 32, 3)])
+def test_nndescent_bit_exact(pg, oracle, datagen, n, d, K, S, T):
+    log("nndescent", n, d, K, S, T)
+    X = datagen.uniform_int(n, d, seed=7)
+    ids, d2, st = pg.knn_build(dev(X), K, S=S, max_iters=T, seed=5, stop_updates=-1)
+    rid, rd2, _, rst = _knn_oracle(oracle, X, K, S, T, 5, -1)
+    assert st["updates"] == rst["updates"]
+    assert st["pairs"] == rst["pairs"]
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d2), rd2.astype(np.float32))
+
+
+def test_nndescent_tuning_knobs_do_not_change_result(pg, datagen):
+    # bucket capacity and pass boundaries change speed only: tiny buckets force
+    # the overflow-retry path, many passes split every iteration
+    X = datagen.uniform_int(2000, 16, seed=11)
+    base = pg.knn_build(dev(X), 16, S=8, max_iters=6, seed=3, stop_updates=-1)
+    for cap, ch in [(32, 1), (32, 7), (64, 200), (512, 2)]:
+        ids, d2, st = pg.knn_build(dev(X), 16, S=8, max_iters=6, seed=3, stop_updates=-1,
+                                   bucket_cap=cap, chunks=ch)
+        assert torch.equal(ids, base[0]) and torch.equal(d2, base[1]), (cap, ch)
+        assert st["updates"] == base[2]["updates"]
+        if cap == 32:
+            assert st["retries"] > 0
+
+
+def test_nndescent_c1_config(pg, oracle, datagen):
+    # tiny config: 10,000 x 128 integers, K = 32, S = 16, delta = 0.001
+    X = datagen.uniform_int(10000, 128, seed=0)
+    stop = int(0.001 * 10000 * 32)
+    ids, d2, st = pg.knn_build(dev(X), 32, S=16, max_iters=12, seed=1, stop_updates=stop)
+    rid, rd2, _, rst = _knn_oracle(oracle, X, 32, 16, 12, 1, stop)
+    log("c1 iters", st["iters"], st["updates"])
+    assert st["updates"] == rst["updates"]
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d2), rd2.astype(np.float32))
+
+
+def test_nndescent_float_statistical(pg, oracle, datagen):
+    X, _ = datagen.unit_mixture(4000, 0, d=96, n_clusters=40, seed=4)
+    ids, d2, st = pg.knn_build(dev(X), 16, S=8, max_iters=10, seed=2)
+    rid, rd2, _, rst = oracle.nndescent(X, 16, 8, 10, 2, stop_updates=int(0.001 * 4000 * 16))
+    gt, _ = oracle.exact_knn(X, X, 16, exclude=np.arange(4000))
+    g = host(ids)
+
+    def rec(a):
+        return np.mean([len(set(x) & set(y)) / 16 for x, y in zip(a, gt)])
+    rg, ro = rec(g), rec(rid)
+    log("float knn recall gpu", rg, "oracle", ro)
+    assert abs(rg - ro) < 0.01 and rg > 0.9
+    # stored distances are the float32 distances of the listed pairs
+    Xd = X.astype(np.float64)
+    for u in range(0, 4000, 97):
+        true = ((Xd[g[u]] - Xd[u]) ** 2).sum(1)
+        assert np.max(np.abs(host(d2)[u] - true) / np.maximum(true, 1e-30)) < 1e-5
+
+
+# ---------------------------------------------------------------- prune
+def _exact_lists(oracle, X, K):
+    ids, _ = oracle.exact_knn(X, X, K, exclude=np.arange(len(X)))
+    return ids
+
+
+@pytest.mark.parametrize("alpha,strict", [(60.0, False), (60.0, True)])
+def test_prune_stage_bit_exact(pg, oracle, datagen, alpha, strict):
+    X = datagen.uniform_int(1200, 32, seed=2)
+    cand = _exact_lists(oracle, X, 24)
+    g = pg.prune(dev(X), dev(cand), 12, alpha_deg=alpha, strict_ties=strict, stages=pg.STAGE_PRUNE)
+    r = oracle.refine(X, cand, 12, alpha_deg=alpha, strict_ties=strict, stages=oracle.STAGE_PRUNE)
+    assert np.array_equal(host(g["deg"]), r["deg"])
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert np.array_equal(host(g["d2"]), r["d2"].astype(np.float32))
+
+
+def test_prune_candidates_with_repeats_self_and_padding(pg, oracle, datagen):
+    X = datagen.uniform_int(500, 8, seed=4)
+    cand = datagen.random_candidates(500, 40, seed=4)
+    cand[:, 5] = np.arange(500)          # self
+    cand[:, 7] = cand[:, 6]              # repeat
+    cand[::3, 9] = -1                    # padding
+    g = pg.prune(dev(X), dev(cand), 10, stages=pg.STAGE_PRUNE)
+    r = oracle.refine(X, cand, 10, stages=oracle.STAGE_PRUNE)
+    assert np.array_equal(host(g["ids"]), r["ids"])
+
+
+def test_full_refine_bit_exact(pg, oracle, datagen):
+    # clustered integer data: the pruned graph is disconnected, connect must add edges
+    X, _ = datagen.sift_like(3000, 0, d=32, n_clusters=20, sigma=6.0, seed=8)
+    cand = _exact_lists(oracle, X, 32)
+    g = pg.prune(dev(X), dev(cand), 16)
+    r = oracle.refine(X, cand, 16)
+    log("roots gpu", len(g["roots"]), "oracle", len(r["roots"]))
+    assert int(host(g["ep"])[0]) == r["ep"]
+    assert np.array_equal(host(g["roots"]), r["roots"])
+    assert np.array_equal(host(g["deg"]), r["deg"])
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert len(r["roots"]) > 0
+
+
+def test_prune_table_hook_float_bit_exact(pg, oracle, datagen):
+    # identical candidate lists and identical float32 distances -> identical edges
+    X, _ = datagen.unit_mixture(400, 0, d=16, n_clusters=5, seed=6)
+    C = 20
+    cand = datagen.random_candidates(400, C, seed=6)
+    for u in range(400):  # distinct ids, not u
+        row = np.unique(cand[u][cand[u] != u])
+        extra = np.setdiff1d(np.arange(400), np.append(row, u))[: C - len(row)]
+        cand[u] = np.concatenate([row, extra])[:C]
+    pos = np.concatenate([np.arange(400)[:, None], cand], 1)
+    P = X.astype(np.float64)[pos]
+    tab = ((P[:, :, None, :] - P[:, None, :, :]) ** 2).sum(-1).astype(np.float32)
+    g = pg.prune(dev(X), dev(cand), 8, stages=pg.STAGE_PRUNE, pair_d2=dev(tab))
+    r_ids, r_d2, r_deg = oracle.prune_table(cand, tab, 8)
+    assert np.array_equal(host(g["deg"]), r_deg)
+    assert np.array_equal(host(g["ids"]), r_ids)
+
+
+def test_prune_alpha_float_decisions(pg, oracle, datagen):
+    # alpha > 60: the angle test is decided in float32 on the GPU and in double
+    # in the oracle; rows may differ only through a near-threshold decision
+    X = datagen.uniform_int(800, 16, seed=12)
+    cand = _exact_lists(oracle, X, 24)
+    g = pg.prune(dev(X), dev(cand), 12, alpha_deg=67.0, stages=pg.STAGE_PRUNE)
+    r = oracle.refine(X, cand, 12, alpha_deg=67.0, stages=oracle.STAGE_PRUNE)
+    same = (host(g["ids"]) == r["ids"]).all(1)
+    log("alpha rows identical", same.mean())
+    assert same.mean() > 0.995
+
+
+# ---------------------------------------------------------------- search
+def test_search_bit_exact(pg, oracle, datagen):
+    X, Q = datagen.sift_like(4000, 300, d=32, n_clusters=10, sigma=10.0, seed=9)
+    cand = _exact_lists(oracle, X, 24)
+    r = oracle.refine(X, cand, 12)
+    entries = np.concatenate([[r["ep"]], r["roots"]]).astype(np.int32)
+    for L in (10, 37, 128):
+        ids, d2 = pg.search(dev(X), dev(r["ids"]), dev(r["deg"]), dev(Q), dev(entries), 10, L)
+        rid, rd2, _ = oracle.search(X, r["ids"], r["deg"], Q, entries, 10, L)
+        assert np.array_equal(host(ids), rid), L
+        assert np.array_equal(host(d2), rd2.astype(np.float32)), L
+
+
+def test_search_edge_cases(pg, oracle):
+    X = np.arange(12, dtype=np.float32).repeat(4).reshape(12, 4)
+    g = np.full((12, 2), -1, np.int32)
+    deg = np.zeros(12, np.int32)
+    for i in range(11):
+        g[i, 0] = i + 1
+        deg[i] = 1
+    Q = np.array([[7.2] * 4, [0.0] * 4], np.float32)
+    ent = np.array([0, 0, -1, 3], np.int32)  # repeats and padding
+    ids, d2 = pg.search(dev(X), dev(g), dev(deg), dev(Q), dev(ent), 3, 3)
+    rid, _, _ = oracle.search(X, g, deg, Q, ent, 3, 3)
+    assert np.array_equal(host(ids), rid)
+    # L larger than the reachable set: padded output
+    ids, d2 = pg.search(dev(X), dev(g), dev(deg), dev(Q), dev(np.array([10], np.int32)), 5, 8)
+    assert list(host(ids)[0]) == [10, 11, -1, -1, -1]
+    assert np.isinf(host(d2)[0, 2:]).all()
+
+
+def test_errors_are_reported(pg, datagen):
+    X = dev(datagen.uniform_int(50, 8, seed=1))
+    with pytest.raises(pg.PgError) as e:
+        pg.knn_build(X, 50)  # K >= n
+    assert e.value.status == -1
+    with pytest.raises(pg.PgError):
+        pg.knn_build(X, 8, S=40)
+    Xodd = dev(np.zeros((50, 6), np.float32))
+    with pytest.raises(pg.PgError) as e:
+        pg.knn_build(Xodd, 4)
+    assert e.value.status == -4
+
+
+# ---------------------------------------------------------------- end to end
+def test_end_to_end_recall_matches_oracle(pg, oracle, datagen):
+    X, Q = datagen.sift_like(6000, 200, d=64, n_clusters=12, seed=21)
+    g = pg.build_graph(dev(X), 32, 16, S=16, max_iters=12, seed=4)
+    ids_o, _, _, _ = oracle.nndescent(X, 32, 16, 12, 4, stop_updates=int(0.001 * 6000 * 32))
+    assert np.array_equal(host(g["knn_ids"]), ids_o)
+    r = oracle.refine(X, ids_o, 16)
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    entries = np.concatenate([[r["ep"]], r["roots"]]).astype(np.int32)
+    gt, _ = oracle.exact_knn(X, Q, 10)
+    ids, _ = pg.search(dev(X), g["ids"], g["deg"], dev(Q), dev(entries), 10, 64)
+    rid, _, _ = oracle.search(X, r["ids"], r["deg"], Q, entries, 10, 64)
+    rg, ro = oracle.recall_at_k(host(ids), gt), oracle.recall_at_k(rid, gt)
+    log("search recall gpu", rg, "oracle", ro)
+    assert abs(rg - ro) <= 0.005

@@ -53,7 +53,7 @@ def _py_nndescent(X, K, S, T, seed):
         nf, of = [], []
         for u in range(n):
             news = sorted((v for v, (_, f) in snap[u].items() if f),
-                          key=lambda v: (_h(seed, 3 * t, u, v), v))[:S]
+                          key=lambda v: (_h(seed, 3 * t, u, v) >> 32, v))[:S]
             nf.append(set(news))
             of.append({v for v, (_, f) in snap[u].items() if not f})
             for v in news:
@@ -67,8 +67,8 @@ def _py_nndescent(X, K, S, T, seed):
                 ro[v].append(u)
         new, old = [], []
         for u in range(n):
-            a = set(sorted(rn[u], key=lambda w: (_h(seed, 3 * t + 1, u, w), w))[:S])
-            b = set(sorted(ro[u], key=lambda w: (_h(seed, 3 * t + 2, u, w), w))[:S])
+            a = set(sorted(rn[u], key=lambda w: (_h(seed, 3 * t + 1, u, w) >> 32, w))[:S])
+            b = set(sorted(ro[u], key=lambda w: (_h(seed, 3 * t + 2, u, w) >> 32, w))[:S])
             new.append(nf[u] | a)
             old.append((of[u] | b) - new[u])
         kth = [max((d, v) for v, (d, _) in snap[v].items()) for v in range(n)]
