@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sift1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=10_000)
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -113,7 +113,9 @@ def main():
         ids, st, g = build()
         torch.cuda.synchronize()
         log(f"[bench] warmup {i}: {time.perf_counter() - t0:.3f} s, iters {st['iters']}, "
-            f"updates {st['updates']}, roots {len(g['roots'])}")
+            f"roots {len(g['roots'])}, retries {st['retries']}, spilled {st['spilled']}")
+        log(f"[bench]   updates {st['updates']}\n[bench]   pairs {st['pairs']}\n"
+            f"[bench]   proposals {st['proposals']}")
     entries = torch.cat([g["ep"], g["roots"]]).contiguous()
     gt, _ = pg.exact_knn(Xd, Qd, 10, ctx=ctx)
     gt = gt.cpu().numpy()

@@ -119,7 +119,8 @@ typedef struct {
     int64_t updates[64];   /* list entries changed in iteration t (index t-1) */
     int64_t pairs[64];     /* local-join pairs evaluated in iteration t */
     int64_t proposals[64]; /* proposals that passed the K-th filter at emission */
-    int64_t retries;       /* extra join passes caused by full proposal buckets */
+    int64_t retries;       /* extra join passes: a node's bucket and the spill list were full */
+    int64_t spilled;       /* proposals that went past their node's bucket to the spill list */
 } pg_knn_stats;
 
 /* Workspace bytes needed by pg_knn_build for these sizes (host output). */

@@ -783,9 +783,11 @@ static int64_t bfs_mark(int64_t n, const int32_t *g, int32_t R, const int32_t *d
  *            parallel" loop does not say; we read a snapshot);
  *   CONNECT: the paper finds connected components by DFS and adds edges
  *            between them.  Reading: mark what is reachable from ep; while a
- *            node is unreached, take the smallest unreached id r, add the edge
- *            p -> r from the reached node p closest to r (by (d2, id)) whose
- *            degree is below R, and mark what r reaches.  Extra edges are
+ *            node is unreached, take the smallest unreached id r and add the
+ *            edge p -> r, where p is the reached node with degree below R that
+ *            is closest to r (by (d2, id)) among r's own candidates C(r); only
+ *            when no candidate qualifies, p is the closest such node among all
+ *            reached nodes.  Then mark what r reaches.  Extra edges are
  *            appended after the pruned ones.
  * Outputs: g_ids/g_d2 (n x R, padded with -1 / +inf), g_deg (n), *ep, and the
  * restart roots r in order (roots, capacity n) with their count *n_roots.
@@ -910,7 +912,18 @@ int orc_refine(const float *X, int64_t n, int32_t d, int64_t ldx,
             int32_t r = scan;
             int32_t best = -1;
             double bd = INFINITY;
-            for (int64_t p = 0; p < n; ++p) {
+            for (int32_t j = 0; j < C; ++j) { /* r's candidates first */
+                int32_t p = cand[(int64_t)r * C + j];
+                if (p < 0 || p >= n || p == r || !seen[p] || g_deg[p] >= R)
+                    continue;
+                double s = sqdist(X + (int64_t)p * ldx, X + (int64_t)r * ldx, d);
+                if (s < bd || (s == bd && p < best)) {
+                    bd = s;
+                    best = p;
+                }
+            }
+            const int from_cand = best >= 0;
+            for (int64_t p = 0; !from_cand && p < n; ++p) { /* no candidate qualifies */
                 if (!seen[p] || g_deg[p] >= R)
                     continue;
                 double s = sqdist(X + p * ldx, X + (int64_t)r * ldx, d);

@@ -36,7 +36,7 @@
 
 namespace pgi {
 
-enum { C_UPDATES = 0, C_PROPOSALS = 1, C_OVF = 2, C_PAIRS = 3, C_NCOUNTERS = 8 };
+enum { C_UPDATES = 0, C_PROPOSALS = 1, C_OVF = 2, C_PAIRS = 3, C_SPILL = 4, C_NCOUNTERS = 8 };
 
 // ---------------------------------------------------------------------------
 // init: K distinct random neighbours, hash4(seed, 0, u, attempt) mod (n-1)
@@ -262,169 +262,256 @@ __device__ __forceinline__ bool list_has(const uint64_t *__restrict__ row, int K
     return lo < K && row[lo] == key;
 }
 
-constexpr int JT = 256;          // threads per source
-constexpr int JDC = 32;          // dims per LDS chunk
-constexpr int JSTR = JDC + 4;    // LDS row stride (floats)
-constexpr int JMAXB = 4;         // 4x4 micro-tiles per thread per pass
-
-static size_t join_lds_bytes(int maxm) {
-    const int mp = (maxm + 3) & ~3;
-    return (size_t)mp * (4 + 8 + 4 + 4 + 4) + (size_t)mp * JSTR * 4 + 64;
+// Proposals beyond their node's bucket go to the shared spill list (a
+// range reserved per member of the join set); when that is full too, the
+// node is marked for a repeat pass.
+__device__ __forceinline__ void spill_put(int32_t t, uint64_t key, int64_t pos,
+                                          int32_t *__restrict__ spill_t,
+                                          uint64_t *__restrict__ spill_k, int64_t cap,
+                                          uint8_t *__restrict__ ovf_next,
+                                          unsigned long long *__restrict__ counters) {
+    if (pos < cap) {
+        spill_t[pos] = t;
+        spill_k[pos] = key;
+    } else {
+        ovf_next[t] = 1;
+        atomicAdd(&counters[C_OVF], 1ull);
+    }
 }
 
+__global__ void k_spill_count(const int32_t *__restrict__ spill_t, int64_t cnt,
+                              int32_t *__restrict__ scnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) atomicAdd(&scnt[spill_t[i]], 1);
+}
+
+__global__ void k_spill_scatter(const int32_t *__restrict__ spill_t,
+                                const uint64_t *__restrict__ spill_k, int64_t cnt,
+                                const int64_t *__restrict__ soff, int32_t *__restrict__ scur,
+                                uint64_t *__restrict__ sorted) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) {
+        const int32_t t = spill_t[i];
+        sorted[soff[t] + atomicAdd(&scur[t], 1)] = spill_k[i];
+    }
+}
+
+constexpr int JW = 2;            // sources (waves) per workgroup
+constexpr int JT = JW * PG_WAVE;
+constexpr int JDC = 16;          // dims per LDS chunk
+constexpr int TRW = 4, TCL = 8;  // micro-tile: 4 new members x 8 members
+
+// LDS column stride (floats) for a join set of at most maxm members: a
+// multiple of 4 (16-byte reads), padded off a multiple of 8.
+__host__ __device__ __forceinline__ int join_mps(int maxm) {
+    const int mp = (maxm + TCL - 1) / TCL * TCL;
+    return mp + 4;
+}
+
+// LDS bytes of one wave's region
+__host__ __device__ __forceinline__ size_t join_wave_lds(int maxm) {
+    const int mps = join_mps(maxm);
+    return (size_t)JDC * mps * 4 + (size_t)mps * (8 + 8 + 4 + 4 + 4 + 4);
+}
+
+static size_t join_lds_bytes(int maxm) { return JW * join_wave_lds(maxm); }
+
+// Local join, one wave per source u.  The join set (new members first, then
+// old) is staged dim-major in the wave's LDS region, tile[k][i] = x_i[c0 + k],
+// JDC dims at a time: a lane's 8 consecutive members at one dim are two
+// conflict-free 16-byte reads and its 4 new members one (shared by the lanes
+// of the same row block).  The pair set is covered by micro-tiles of 4 new
+// members x 8 members, one per lane per round; every pair's squared distance
+// accumulates in registers in the canonical order (dims ascending, one fma
+// per dim).  Proposals are counted per (lane, member), ranges are reserved
+// per member in the node's bucket (then the spill list), and written.
 __global__ __launch_bounds__(JT) void k_join(
     const float *__restrict__ X, int64_t ldx, int d, int K, const int32_t *__restrict__ jn,
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
     const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
     int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
-    const uint8_t *__restrict__ mark, int64_t u0, int maxm,
-    unsigned long long *__restrict__ counters) {
+    int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t spill_cap,
+    uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, int64_t u0, int64_t u1,
+    int maxm, unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int mp_max = (maxm + 3) & ~3;
-    float *tile = reinterpret_cast<float *>(smem);
-    uint64_t *kth = reinterpret_cast<uint64_t *>(tile + (size_t)mp_max * JSTR);
-    int32_t *ids = reinterpret_cast<int32_t *>(kth + mp_max);
-    int32_t *cnt = ids + mp_max;
-    int32_t *base = cnt + mp_max;
-    int32_t *mk = base + mp_max;
+    const int MPS = join_mps(maxm);
+    const int lane = lane_id();
+    const int wv = threadIdx.x / PG_WAVE;
+    const int64_t u = u0 + (int64_t)blockIdx.x * JW + wv;
+    if (u >= u1) return;
+    unsigned char *region = smem + (size_t)wv * join_wave_lds(maxm);
+    float *tile = reinterpret_cast<float *>(region);
+    uint64_t *kth = reinterpret_cast<uint64_t *>(tile + (size_t)JDC * MPS);
+    int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
+    int32_t *ids = reinterpret_cast<int32_t *>(sbase + MPS);
+    int32_t *cnt = ids + MPS;
+    int32_t *base = cnt + MPS;
+    int32_t *mk = base + MPS;
 
-    const int tid = threadIdx.x;
-    const int64_t u = u0 + blockIdx.x;
     const int nn = jn_c[u], no = jo_c[u];
     const int m = nn + no;
     if (nn == 0 || m < 2) return;
-    const int mp = (m + 3) & ~3;
-    int anymark = 0;
-    for (int i = tid; i < mp; i += JT) {
+    const int mp = (m + TCL - 1) / TCL * TCL;
+    bool anymark = false;
+    for (int i = lane; i < mp; i += PG_WAVE) {
         const int32_t id = i < nn ? jn[u * JN + i] : (i < m ? jo[u * JO + (i - nn)] : -1);
         ids[i] = id;
         kth[i] = id >= 0 ? keys[(int64_t)id * K + (K - 1)] : 0ull;
         cnt[i] = 0;
         const int mkv = (mark && id >= 0) ? (int)mark[id] : (mark ? 0 : 1);
         mk[i] = mkv;
-        anymark |= (id >= 0 && mkv);
+        anymark |= (id >= 0 && mkv != 0);
     }
-    if (!__syncthreads_or(anymark)) return;
+    if (__ballot(anymark) == 0) return;  // a repeat pass serves none of this source's members
+    __builtin_amdgcn_wave_barrier();
 
-    const int RB = (nn + 3) >> 2, CB = mp >> 2;
-    const int T = RB * CB - RB * (RB - 1) / 2;  // micro-tiles with cb >= rb
+    const int RB = (nn + TRW - 1) / TRW, CB = mp / TCL;
+    // micro-tiles (rb, cb) that hold a pair with col > row: cb >= rb / 2
+    int T = 0;
+    for (int rb = 0; rb < RB; ++rb) T += CB - (rb >> 1);
     unsigned long long local_props = 0;
-    for (int pass0 = 0; pass0 < T; pass0 += JT * JMAXB) {
-        float acc[JMAXB][4][4];
-        int brb[JMAXB], bcb[JMAXB];
-#pragma unroll
-        for (int i = 0; i < JMAXB; ++i) {
-            int b = pass0 + tid + JT * i;
-            brb[i] = -1;
-            bcb[i] = 0;
+    for (int round0 = 0; round0 < T; round0 += PG_WAVE) {
+        float acc[TRW][TCL];
+        int brb = -1, bcb = 0;
+        {
+            int b = round0 + lane;
             if (b < T) {
                 int rb = 0;
-                while (b >= CB - rb) {
-                    b -= CB - rb;
+                while (b >= CB - (rb >> 1)) {
+                    b -= CB - (rb >> 1);
                     ++rb;
                 }
-                brb[i] = rb;
-                bcb[i] = rb + b;
+                brb = rb;
+                bcb = (rb >> 1) + b;
             }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[i][a][c] = 0.0f;
         }
+#pragma unroll
+        for (int a = 0; a < TRW; ++a)
+#pragma unroll
+            for (int c = 0; c < TCL; ++c) acc[a][c] = 0.0f;
         for (int c0 = 0; c0 < d; c0 += JDC) {
-            __syncthreads();
-            for (int e = tid; e < mp * (JDC / 4); e += JT) {
-                const int r = e / (JDC / 4), q = e % (JDC / 4);
-                const int32_t id = ids[r];
+            const int dl = min(JDC, d - c0);
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < mp * (JDC / 4); e += PG_WAVE) {
+                const int q = e % (JDC / 4), i = e / (JDC / 4);
+                const int32_t id = ids[i];
                 float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (id >= 0 && c0 + 4 * q < d)
+                if (id >= 0 && 4 * q < dl)
                     val = *reinterpret_cast<const float4 *>(X + (int64_t)id * ldx + c0 + 4 * q);
-                *reinterpret_cast<float4 *>(tile + r * JSTR + 4 * q) = val;
+                tile[(4 * q + 0) * MPS + i] = val.x;
+                tile[(4 * q + 1) * MPS + i] = val.y;
+                tile[(4 * q + 2) * MPS + i] = val.z;
+                tile[(4 * q + 3) * MPS + i] = val.w;
             }
-            __syncthreads();
-            const int dlim = min(JDC, d - c0);
+            __builtin_amdgcn_wave_barrier();
+            if (brb >= 0) {
+                const float *rp = tile + TRW * brb;
+                const float *cp = tile + TCL * bcb;
+                for (int k = 0; k < dl; ++k) {
+                    const float4 r4 = *reinterpret_cast<const float4 *>(rp + k * MPS);
+                    const float4 ca = *reinterpret_cast<const float4 *>(cp + k * MPS);
+                    const float4 cb = *reinterpret_cast<const float4 *>(cp + k * MPS + 4);
+                    const float rv[TRW] = {r4.x, r4.y, r4.z, r4.w};
+                    const float cv[TCL] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
-            for (int i = 0; i < JMAXB; ++i) {
-                if (brb[i] < 0) continue;
-                const float *rp = tile + (4 * brb[i]) * JSTR;
-                const float *cp = tile + (4 * bcb[i]) * JSTR;
-                for (int dd = 0; dd < dlim; dd += 4) {
-                    float4 r4[4], c4[4];
+                    for (int a = 0; a < TRW; ++a)
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) r4[a] = *reinterpret_cast<const float4 *>(rp + a * JSTR + dd);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) c4[c] = *reinterpret_cast<const float4 *>(cp + c * JSTR + dd);
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            float s = acc[i][a][c], t;
-                            t = r4[a].x - c4[c].x;
-                            s = fmaf(t, t, s);
-                            t = r4[a].y - c4[c].y;
-                            s = fmaf(t, t, s);
-                            t = r4[a].z - c4[c].z;
-                            s = fmaf(t, t, s);
-                            t = r4[a].w - c4[c].w;
-                            s = fmaf(t, t, s);
-                            acc[i][a][c] = s;
+                        for (int c = 0; c < TCL; ++c) {
+                            const float t = rv[a] - cv[c];
+                            acc[a][c] = fmaf(t, t, acc[a][c]);
                         }
                 }
             }
         }
-        // emission: count per member, reserve bucket ranges, write
-        for (int phase = 0; phase < 2; ++phase) {
+        // ---- emission: decide every pair once (bit masks), one LDS offset per
+        // (lane, member), reserve ranges per member, write
+        uint32_t to_row = 0, to_col = 0;  // bit a*8+c
+        int off_row[TRW], off_col[TCL];
+        if (brb >= 0) {
 #pragma unroll
-            for (int i = 0; i < JMAXB; ++i) {
-                if (brb[i] < 0) continue;
+            for (int a = 0; a < TRW; ++a) {
+                const int r = TRW * brb + a;
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int r = 4 * brb[i] + a, col = 4 * bcb[i] + c;
-                        if (r >= nn || col >= m || (col < nn && col <= r)) continue;
-                        const float d2 = acc[i][a][c];
-                        const int32_t v = ids[r], w = ids[col];
-                        const uint64_t kw = pack_key(d2, w), kv = pack_key(d2, v);
-                        // a repeat pass (mark != null) skips keys already listed, so
-                        // every repeat inserts at least one new key into each node it serves
-                        const bool to_v = mk[r] && kw < kth[r] &&
-                                          !(mark && list_has(keys + (int64_t)v * K, K, kw));
-                        const bool to_w = mk[col] && kv < kth[col] &&
-                                          !(mark && list_has(keys + (int64_t)w * K, K, kv));
-                        if (to_v) {
-                            if (phase == 0) {
-                                atomicAdd(&cnt[r], 1);
-                            } else {
-                                const int slot = base[r] + atomicAdd(&cnt[r], 1);
-                                if (slot < B) bucket[(int64_t)v * B + slot] = kw;
-                            }
-                        }
-                        if (to_w) {
-                            if (phase == 0) {
-                                atomicAdd(&cnt[col], 1);
-                            } else {
-                                const int slot = base[col] + atomicAdd(&cnt[col], 1);
-                                if (slot < B) bucket[(int64_t)w * B + slot] = kv;
-                            }
-                        }
-                    }
-            }
-            __syncthreads();
-            if (phase == 0) {
-                for (int i = tid; i < m; i += JT) {
-                    const int c = cnt[i];
-                    if (c > 0) {
-                        base[i] = atomicAdd(&pcnt[ids[i]], c);
-                        local_props += (unsigned long long)c;
-                    }
-                    cnt[i] = 0;
+                for (int c = 0; c < TCL; ++c) {
+                    const int col = TCL * bcb + c;
+                    if (r >= nn || col >= m || (col < nn && col <= r)) continue;
+                    const float d2 = acc[a][c];
+                    const uint64_t kw = pack_key(d2, ids[col]), kv = pack_key(d2, ids[r]);
+                    // a repeat pass (mark != null) skips keys already listed, so
+                    // every repeat inserts at least one new key into each node it serves
+                    if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
+                        to_row |= 1u << (a * TCL + c);
+                    if (mk[col] && kv < kth[col] && !(mark && list_has(keys + (int64_t)ids[col] * K, K, kv)))
+                        to_col |= 1u << (a * TCL + c);
                 }
-                __syncthreads();
+            }
+#pragma unroll
+            for (int a = 0; a < TRW; ++a) {
+                const int c_r = __popc((to_row >> (a * TCL)) & 0xFFu);
+                off_row[a] = c_r ? atomicAdd(&cnt[TRW * brb + a], c_r) : 0;
+            }
+#pragma unroll
+            for (int c = 0; c < TCL; ++c) {
+                const int c_c = __popc(to_col & (0x01010101u << c));
+                off_col[c] = c_c ? atomicAdd(&cnt[TCL * bcb + c], c_c) : 0;
             }
         }
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < m; i += PG_WAVE) {
+            const int c = cnt[i];
+            if (c > 0) {
+                const int b0 = atomicAdd(&pcnt[ids[i]], c);
+                base[i] = b0;
+                const int over = b0 + c - max(b0, B);  // entries past the bucket
+                if (over > 0)
+                    sbase[i] = (int64_t)atomicAdd(&counters[C_SPILL], (unsigned long long)over);
+                local_props += (unsigned long long)c;
+            }
+            cnt[i] = 0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (brb >= 0) {
+#pragma unroll
+            for (int a = 0; a < TRW; ++a) {
+                const int r = TRW * brb + a;
+#pragma unroll
+                for (int c = 0; c < TCL; ++c) {
+                    const int col = TCL * bcb + c;
+                    const uint32_t bit = 1u << (a * TCL + c);
+                    if (!((to_row | to_col) & bit)) continue;
+                    const float d2 = acc[a][c];
+                    if (to_row & bit) {
+                        const int32_t v = ids[r];
+                        const int slot = base[r] + off_row[a]++;
+                        const uint64_t kw = pack_key(d2, ids[col]);
+                        if (slot < B)
+                            bucket[(int64_t)v * B + slot] = kw;
+                        else
+                            spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k,
+                                      spill_cap, ovf_next, counters);
+                    }
+                    if (to_col & bit) {
+                        const int32_t w = ids[col];
+                        const int slot = base[col] + off_col[c]++;
+                        const uint64_t kv = pack_key(d2, ids[r]);
+                        if (slot < B)
+                            bucket[(int64_t)w * B + slot] = kv;
+                        else
+                            spill_put(w, kv, sbase[col] + (slot - max(base[col], B)), spill_t, spill_k,
+                                      spill_cap, ovf_next, counters);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
+    // one atomic per wave
+#pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1) {
+        const unsigned long long t = __shfl_xor((long long)local_props, o, PG_WAVE);
+        local_props += t;
+    }
+    if (lane == 0 && local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
 }
 
 // ---------------------------------------------------------------------------
@@ -436,8 +523,8 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
                                                uint64_t *__restrict__ insm, int64_t n, int K,
                                                int32_t *__restrict__ pcnt,
                                                const uint64_t *__restrict__ bucket, int B,
-                                               uint8_t *__restrict__ ovf_next,
-                                               unsigned long long *__restrict__ counters) {
+                                               const int64_t *__restrict__ soff,
+                                               const uint64_t *__restrict__ spilled) {
     const int lane = lane_id();
     const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (v >= n) return;
@@ -447,9 +534,16 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
     const uint64_t nm = newm[v], im = insm[v];
     int fl = lane < K ? (int)(((nm >> lane) & 1ull) | (((im >> lane) & 1ull) << 1)) : 0;
     const int cc = min(c, B);
-    for (int b0 = 0; b0 < cc; b0 += PG_WAVE) {
+    const int64_t s0 = soff ? soff[v] : 0;
+    const int sc = soff ? (int)(soff[v + 1] - s0) : 0;
+    for (int b0 = 0; b0 < cc + sc; b0 += PG_WAVE) {
         const uint64_t kth = shfl64(a, K - 1);
-        uint64_t bk = (b0 + lane < cc) ? bucket[v * B + b0 + lane] : KEY_INF;
+        const int e = b0 + lane;
+        uint64_t bk = KEY_INF;
+        if (e < cc)
+            bk = bucket[v * B + e];
+        else if (e < cc + sc)
+            bk = spilled[s0 + (e - cc)];
         if (bk >= kth) bk = KEY_INF;
         if (__ballot(bk != KEY_INF) == 0) continue;
         int pb = 3;
@@ -472,10 +566,6 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
         newm[v] = nmo;
         insm[v] = imo;
         pcnt[v] = 0;
-        if (c > B) {
-            ovf_next[v] = 1;
-            atomicAdd(&counters[C_OVF], 1ull);
-        }
     }
 }
 
@@ -625,8 +715,10 @@ __global__ __launch_bounds__(256) void k_exact_knn(const float *__restrict__ X, 
 // ---------------------------------------------------------------------------
 struct KnnLayout {
     size_t keys, newm, insm, nf, nf_c, of, of_c, rn_cnt, ro_cnt, rn_off, ro_off, rn_list, ro_list,
-        jn, jn_c, jo, jo_c, pcnt, bucket, mark, mark_next, counters, scan_tmp, total;
+        jn, jn_c, jo, jo_c, pcnt, bucket, mark, mark_next, counters, scan_tmp, spill_t, spill_k,
+        spill_s, total;
     int B, JN, JO;
+    int64_t spill_cap;
 };
 
 static int default_bucket(int K) { return 4 * K; }
@@ -666,6 +758,10 @@ static KnnLayout knn_layout(const pg_knn_params *p, int64_t n) {
     L.mark_next = take(n);
     L.counters = take(sizeof(unsigned long long) * C_NCOUNTERS);
     L.scan_tmp = take(scan_tmp_bytes(n + 1));
+    L.spill_cap = std::max<int64_t>(1 << 16, n * K / 4);
+    L.spill_t = take(sizeof(int32_t) * L.spill_cap);
+    L.spill_k = take(sizeof(uint64_t) * L.spill_cap);
+    L.spill_s = take(sizeof(uint64_t) * L.spill_cap);
     L.total = o;
     return L;
 }
@@ -798,6 +894,8 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
     int64_t *rn_off = (int64_t *)(w + L.rn_off), *ro_off = (int64_t *)(w + L.ro_off);
     uint64_t *bucket = (uint64_t *)(w + L.bucket);
     uint8_t *mark = (uint8_t *)(w + L.mark), *mark_next = (uint8_t *)(w + L.mark_next);
+    int32_t *spill_t = (int32_t *)(w + L.spill_t);
+    uint64_t *spill_k = (uint64_t *)(w + L.spill_k), *spill_s = (uint64_t *)(w + L.spill_s);
     unsigned long long *counters = (unsigned long long *)(w + L.counters);
     void *scan_tmp = w + L.scan_tmp;
     hipStream_t st = ctx->stream;
@@ -870,23 +968,40 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
             for (int attempt = 0;; ++attempt) {
                 {
                     TimedLaunch tl(ctx, K_JOIN, -1.0);
-                    hipLaunchKernelGGL(k_join, dim3((unsigned)cnt), dim3(JT), lds, st, X, ldx, d, K, jn,
-                                       jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt, bucket, L.B, mk, u0,
+                    hipLaunchKernelGGL(k_join, dim3((unsigned)((cnt + JW - 1) / JW)), dim3(JT), lds, st,
+                                       X, ldx, d, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt, bucket,
+                                       L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, u0, u0 + cnt,
                                        maxm, counters);
                     PG_HIP(hipGetLastError());
+                }
+                unsigned long long hc2[C_NCOUNTERS];
+                PG_HIP(hipMemcpyAsync(hc2, counters, sizeof(hc2), hipMemcpyDeviceToHost, st));
+                PG_HIP(hipStreamSynchronize(st));
+                const int64_t nsp = std::min<int64_t>((int64_t)hc2[C_SPILL], L.spill_cap);
+                const int64_t *soff = nullptr;
+                if (nsp > 0) {
+                    // group the spilled proposals by node (counting sort)
+                    const unsigned sb = (unsigned)((nsp + 255) / 256);
+                    PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
+                    hipLaunchKernelGGL(k_spill_count, dim3(sb), dim3(256), 0, st, spill_t, nsp, rn_cnt);
+                    PG_TRY(scan_exclusive(ctx, rn_cnt, rn_off, n, scan_tmp));
+                    PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
+                    hipLaunchKernelGGL(k_spill_scatter, dim3(sb), dim3(256), 0, st, spill_t, spill_k, nsp,
+                                       rn_off, rn_cnt, spill_s);
+                    PG_HIP(hipGetLastError());
+                    PG_HIP(hipMemsetAsync(counters + C_SPILL, 0, sizeof(unsigned long long), st));
+                    soff = rn_off;
+                    if (stats) stats->spilled += nsp;
                 }
                 {
                     TimedLaunch tl(ctx, K_MERGE, -1.0);
                     hipLaunchKernelGGL(k_merge, dim3(wave_blocks), dim3(256), 0, st, keys, newm, insm,
-                                       n, K, pcnt, bucket, L.B, mark_next, counters);
+                                       n, K, pcnt, bucket, L.B, soff, spill_s);
                     PG_HIP(hipGetLastError());
                 }
-                unsigned long long ovf = 0;
-                PG_HIP(hipMemcpyAsync(&ovf, counters + C_OVF, sizeof(ovf), hipMemcpyDeviceToHost, st));
-                PG_HIP(hipStreamSynchronize(st));
-                if (ovf == 0) break;
+                if (hc2[C_OVF] == 0) break;
                 if (attempt >= 1000) {
-                    set_error("pg_knn_build: proposal buckets kept overflowing");
+                    set_error("pg_knn_build: proposal buffers kept overflowing");
                     return PG_EOVERFLOW;
                 }
                 if (stats) stats->retries++;

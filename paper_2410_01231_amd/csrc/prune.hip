@@ -313,12 +313,111 @@ __global__ __launch_bounds__(256) void k_argmin_final(const double *__restrict__
 // ---------------------------------------------------------------------------
 struct ConnState {
     int32_t fcount[2];
-    int32_t first_unreached;
+    int32_t first_unreached;  // root waiting for the global nearest-node scan
     int32_t n_roots;
     int32_t overflow;
-    int32_t pad;
+    int32_t idx;              // next position in the list of unreached ids
+    int32_t bfs_head;         // > 0: the wave handed a BFS queue[bfs_head, bfs_tail)
+    int32_t bfs_tail;         //      over to the multi-block BFS
     unsigned long long nearest;
 };
+
+// a BFS that grows past this many queued nodes continues on the multi-block path
+constexpr int CONNECT_WAVE_BFS = 2048;
+
+// loads that must see stores made earlier in the same kernel (bypass L1)
+__device__ __forceinline__ int32_t ld_fresh(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_flag_unreached(const int32_t *__restrict__ visited, int64_t n,
+                                 int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = visited[i] == 0;
+}
+
+__global__ void k_scatter_unreached(const int32_t *__restrict__ visited, int64_t n,
+                                    const int64_t *__restrict__ off, int32_t *__restrict__ U) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && visited[i] == 0) U[off[i]] = (int32_t)i;
+}
+
+// The connect loop of the refinement, one wave: unreached ids in increasing
+// order; each still-unreached r gets the edge p -> r from its closest reached
+// candidate p with degree < R, then a BFS from r marks what r reaches.  When no
+// candidate of r qualifies the wave stops and leaves r in first_unreached for
+// the global scan on the host side.
+__global__ __launch_bounds__(64) void k_connect_loop(const float *__restrict__ X, int64_t ldx, int d,
+                                                     int64_t n, int R, const int32_t *__restrict__ cand,
+                                                     int C, int32_t *g, float *gd, int32_t *deg,
+                                                     int32_t *visited, const int32_t *__restrict__ U,
+                                                     int32_t nu, int32_t *queue, int32_t *roots,
+                                                     ConnState *cs) {
+    const int lane = lane_id();
+    for (int32_t idx = cs->idx; idx < nu; ++idx) {
+        const int32_t r = U[idx];
+        if (ld_fresh(&visited[r])) continue;
+        uint64_t key = KEY_INF;
+        if (lane < C) {
+            const int32_t p = cand[(int64_t)r * C + lane];
+            if (p >= 0 && p < n && p != r && ld_fresh(&visited[p]) && ld_fresh(&deg[p]) < R)
+                key = pack_key(dist_chain(X + (int64_t)r * ldx, X + (int64_t)p * ldx, d), p);
+        }
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) {
+            const uint64_t t = shfl_xor64(key, o);
+            key = t < key ? t : key;
+        }
+        if (key == KEY_INF) {
+            if (lane == 0) {
+                cs->idx = idx;
+                cs->first_unreached = r;
+            }
+            return;
+        }
+        const int32_t p = key_id(key);
+        if (lane == 0) {
+            const int j = ld_fresh(&deg[p]);
+            g[(int64_t)p * R + j] = r;
+            gd[(int64_t)p * R + j] = key_d2(key);
+            deg[p] = j + 1;
+            roots[cs->n_roots] = r;
+            cs->n_roots += 1;
+            visited[r] = 1;
+            queue[0] = r;
+        }
+        __threadfence();
+        int head = 0, tail = 1;
+        while (head < tail) {
+            if (tail - head > CONNECT_WAVE_BFS) {
+                if (lane == 0) {
+                    cs->idx = idx + 1;
+                    cs->bfs_head = head;
+                    cs->bfs_tail = tail;
+                    cs->first_unreached = -1;
+                }
+                return;
+            }
+            const int32_t x = ld_fresh(&queue[head]);
+            ++head;
+            const int dx = min(ld_fresh(&deg[x]), R);
+            bool push = false;
+            int32_t y = -1;
+            if (lane < dx) {
+                y = ld_fresh(&g[(int64_t)x * R + lane]);
+                if (y >= 0 && y < n && atomicExch(&visited[y], 1) == 0) push = true;
+            }
+            const uint64_t m = __ballot(push);
+            if (push) queue[tail + __popcll(m & lanemask_lt())] = y;
+            tail += __popcll(m);
+            __threadfence();
+        }
+    }
+    if (lane == 0) {
+        cs->idx = nu;
+        cs->first_unreached = -1;
+    }
+}
 
 __global__ void k_bfs_seed(int32_t *__restrict__ visited, int32_t *__restrict__ frontier,
                            ConnState *__restrict__ cs, const int32_t *__restrict__ src_dev, int32_t src) {
@@ -352,14 +451,6 @@ __global__ __launch_bounds__(256) void k_bfs_step(const int32_t *__restrict__ g,
     if (lane_id() == leader) base = atomicAdd(nout, __popcll(m));
     base = __shfl(base, leader, PG_WAVE);
     if (push) fout[base + __popcll(m & lanemask_lt())] = y;
-}
-
-__global__ void k_first_unreached(const int32_t *__restrict__ visited, int64_t n,
-                                  int32_t *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool un = i < n && visited[i] == 0;
-    const uint64_t m = __ballot(un);
-    if (m && lane_id() == __ffsll((long long)m) - 1) atomicMin(out, (int32_t)i);
 }
 
 __global__ __launch_bounds__(256) void k_nearest_reached(const float *__restrict__ X, int64_t ldx,
@@ -482,13 +573,22 @@ static pg_status check_prune(const pg_prune_params *p, int64_t n, int32_t C) {
     return PG_OK;
 }
 
+// Level-synchronous BFS over out-edges.  With src_dev or src >= 0 the
+// search starts there; otherwise from the nin0 nodes already queued at fin0
+// (and already marked).
 static pg_status bfs_from(pg_ctx *ctx, const int32_t *g, int64_t n, int R, const int32_t *deg, int32_t *visited,
-                          int32_t *fa, int32_t *fb, ConnState *cs, const int32_t *src_dev, int32_t src) {
+                          int32_t *fa, int32_t *fb, ConnState *cs, const int32_t *src_dev, int32_t src,
+                          int32_t *fin0 = nullptr, int32_t nin0 = 0) {
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, st, visited, fa, cs, src_dev, src);
-    PG_HIP(hipGetLastError());
     int32_t nin = 1;
     int32_t *fin = fa, *fout = fb;
+    if (fin0) {
+        nin = nin0;
+        fin = fin0;
+    } else {
+        hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, st, visited, fa, cs, src_dev, src);
+        PG_HIP(hipGetLastError());
+    }
     int parity = 0;
     while (nin > 0) {
         PG_HIP(hipMemsetAsync(&cs->fcount[parity ^ 1], 0, sizeof(int32_t), st));
@@ -498,7 +598,8 @@ static pg_status bfs_from(pg_ctx *ctx, const int32_t *g, int64_t n, int R, const
         PG_HIP(hipGetLastError());
         PG_HIP(hipMemcpyAsync(&nin, &cs->fcount[parity ^ 1], sizeof(int32_t), hipMemcpyDeviceToHost, st));
         PG_HIP(hipStreamSynchronize(st));
-        std::swap(fin, fout);
+        fin = fout;
+        fout = (fout == fb) ? fa : fb;
         parity ^= 1;
     }
     return PG_OK;
@@ -594,16 +695,33 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         PG_HIP(hipMemsetAsync(cs, 0, sizeof(ConnState), st));
         PG_TRY(bfs_from(ctx, g_ids, n, R, g_deg, visited, fa, fb, cs, ep, 0));
         const unsigned nb = (unsigned)((n + 255) / 256);
-        for (int64_t restart = 0;; ++restart) {
-            const int32_t big = 0x7fffffff;
-            PG_HIP(hipMemcpyAsync(&cs->first_unreached, &big, sizeof(int32_t), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(k_first_unreached, dim3(nb), dim3(256), 0, st, visited, n,
-                               &cs->first_unreached);
+        // unreached ids in increasing order
+        hipLaunchKernelGGL(k_flag_unreached, dim3(nb), dim3(256), 0, st, visited, n, cnt);
+        PG_TRY(scan_exclusive(ctx, cnt, off, n, w + L.scan_tmp));
+        hipLaunchKernelGGL(k_scatter_unreached, dim3(nb), dim3(256), 0, st, visited, n, off, rev);
+        PG_HIP(hipGetLastError());
+        int64_t nu64 = 0;
+        PG_HIP(hipMemcpyAsync(&nu64, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        PG_HIP(hipStreamSynchronize(st));
+        const int32_t nu = (int32_t)nu64;
+        for (int64_t restart = 0; nu > 0; ++restart) {
+            hipLaunchKernelGGL(k_connect_loop, dim3(1), dim3(64), 0, st, X, ldx, d, n, R, cand_ids, C,
+                               g_ids, g_d2, g_deg, visited, rev, nu, fa, roots ? roots : fb, cs);
             PG_HIP(hipGetLastError());
             ConnState h;
             PG_HIP(hipMemcpyAsync(&h, cs, sizeof(h), hipMemcpyDeviceToHost, st));
             PG_HIP(hipStreamSynchronize(st));
-            if (h.first_unreached == big) break;
+            if (h.bfs_head > 0) {
+                // a large component: finish its BFS level-synchronously, then resume
+                const int32_t hb = h.bfs_head, tb = h.bfs_tail;
+                const int32_t zero2[2] = {0, 0};
+                PG_HIP(hipMemcpyAsync(&cs->bfs_head, zero2, sizeof(zero2), hipMemcpyHostToDevice, st));
+                PG_TRY(bfs_from(ctx, g_ids, n, R, g_deg, visited, fa + tb, fb, cs, nullptr, -1, fa + hb,
+                                tb - hb));
+                continue;
+            }
+            if (h.idx >= nu) break;
+            // no candidate of r qualifies: nearest reached node over all of X
             const unsigned long long inf = KEY_INF;
             PG_HIP(hipMemcpyAsync(&cs->nearest, &inf, sizeof(inf), hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL(k_nearest_reached, dim3(nb), dim3(256), 0, st, X, ldx, d, n, R, visited,
@@ -618,6 +736,8 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
                 return PG_EOVERFLOW;
             }
             PG_TRY(bfs_from(ctx, g_ids, n, R, g_deg, visited, fa, fb, cs, &cs->first_unreached, 0));
+            const int32_t next = h.idx + 1;
+            PG_HIP(hipMemcpyAsync(&cs->idx, &next, sizeof(int32_t), hipMemcpyHostToDevice, st));
         }
         if (n_roots) {
             int32_t nr = 0;

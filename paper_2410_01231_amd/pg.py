@@ -36,7 +36,8 @@ class KnnParams(ctypes.Structure):
 
 class KnnStats(ctypes.Structure):
     _fields_ = [("iters_run", c_int32), ("reserved", c_int32), ("updates", c_int64 * 64),
-                ("pairs", c_int64 * 64), ("proposals", c_int64 * 64), ("retries", c_int64)]
+                ("pairs", c_int64 * 64), ("proposals", c_int64 * 64), ("retries", c_int64),
+                ("spilled", c_int64)]
 
 
 class PruneParams(ctypes.Structure):
@@ -185,7 +186,8 @@ def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001
                             ws_bytes.value, _ptr(ids), _ptr(d2), ctypes.byref(st)), "pg_knn_build")
     it = st.iters_run
     stats = {"iters": it, "updates": list(st.updates[:it]), "pairs": list(st.pairs[:it]),
-             "proposals": list(st.proposals[:it]), "retries": st.retries}
+             "proposals": list(st.proposals[:it]), "retries": st.retries,
+             "spilled": st.spilled}
     return ids, d2, stats
 
 

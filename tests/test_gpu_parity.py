@@ -89,7 +89,7 @@ def test_nndescent_tuning_knobs_do_not_change_result(pg, datagen):
         assert torch.equal(ids, base[0]) and torch.equal(d2, base[1]), (cap, ch)
         assert st["updates"] == base[2]["updates"]
         if cap == 32:
-            assert st["retries"] > 0
+            assert st["spilled"] > 0
 
 
 def test_nndescent_c1_config(pg, oracle, datagen):

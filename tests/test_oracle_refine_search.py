@@ -120,3 +120,36 @@ def test_multiple_entries_and_padding(oracle):
     got, d2, _ = oracle.search(X, ids, deg, np.array([[4.4]], np.float32), [1, 4, 4, 0], 5, 8)
     assert list(got[0]) == [4, 1, 0, -1, -1]
     assert np.isinf(d2[0, 3:]).all()
+
+
+def _py_connect(X, g_ids, g_deg, ep, cand, R):
+    """Restatement of the connect reading: smallest unreached root r gets an
+    edge from its closest reached candidate with spare degree (else the closest
+    such reached node overall); then everything r reaches is marked."""
+    ids, deg = g_ids.copy(), g_deg.copy()
+    Xd = X.astype(np.float64)
+    seen = _reach(ids, deg, ep)
+    roots = []
+    while len(seen) < len(X):
+        r = min(set(range(len(X))) - seen)
+        elig = [int(p) for p in cand[r] if p >= 0 and p != r and p in seen and deg[p] < R]
+        if not elig:
+            elig = [p for p in sorted(seen) if deg[p] < R]
+        p = min(elig, key=lambda q: (float(((Xd[q] - Xd[r]) ** 2).sum()), q))
+        ids[p, deg[p]] = r
+        deg[p] += 1
+        roots.append(r)
+        seen |= _reach(ids, deg, r)
+    return ids, deg, roots
+
+
+def test_connect_matches_restatement(oracle, datagen):
+    X, _ = datagen.sift_like(900, 0, d=8, n_clusters=9, sigma=3.0, seed=13)
+    cand = _knn_input(oracle, X, 8)
+    base = oracle.refine(X, cand, 6, stages=oracle.STAGE_PRUNE | oracle.STAGE_REVERSE)
+    full = oracle.refine(X, cand, 6)
+    ids, deg, roots = _py_connect(X, base["ids"], base["deg"], base["ep"], cand, 6)
+    assert len(roots) > 0
+    assert list(full["roots"]) == roots
+    assert np.array_equal(full["deg"], deg)
+    assert np.array_equal(full["ids"], ids)
