@@ -53,7 +53,17 @@ typedef enum {
     PG_EOVERFLOW = -5      /* a bounded structure could not hold the result */
 } pg_status;
 
-typedef enum { PG_FP32 = 0, PG_FP16 = 1, PG_BF16 = 2 } pg_precision;
+/* Arithmetic of the NN-Descent distance tiles.  PG_FP32: float32; on data
+ * where it is provably exact (integer values, squared norms <= 2^23) the tiles
+ * run as FP32 MFMA norm expansions, otherwise as the FP32 direct form on the
+ * vector ALUs.  PG_FP32_VALU: always the direct form.  PG_FP16 / PG_BF16:
+ * 16-bit MFMA tiles with FP32 accumulation, accepted only where they are
+ * exact (integer data with |x| <= 2048 for FP16, <= 256 for BF16, squared
+ * norms <= 2^23), so every precision returns the same lists. */
+typedef enum { PG_FP32 = 0, PG_FP16 = 1, PG_BF16 = 2, PG_FP32_VALU = 3 } pg_precision;
+
+/* Join path a build used (pg_knn_stats.join_path). */
+enum { PG_JOIN_VALU = 0, PG_JOIN_MFMA_FP32 = 1, PG_JOIN_MFMA_FP16 = 2, PG_JOIN_MFMA_BF16 = 3 };
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int pg_version(void);
@@ -107,15 +117,15 @@ typedef struct {
     int32_t exact;        /* nonzero: brute-force exact lists, other fields unused */
     int64_t stop_updates; /* stop when an iteration changes <= this many entries */
     uint64_t seed;
-    int32_t precision;    /* pg_precision of the join tiles; PG_FP32 only for now */
-    float margin_rel;     /* reserved for the mixed-precision recheck margin */
+    int32_t precision;    /* pg_precision of the join tiles */
+    float margin_rel;     /* reserved (must be 0) */
     int32_t bucket_cap;   /* proposal slots per node per pass (>= 2K); 0 = default */
     int32_t chunks;       /* source passes in the first iteration; 0 = default */
 } pg_knn_params;
 
 typedef struct {
     int32_t iters_run;
-    int32_t reserved;
+    int32_t join_path;     /* PG_JOIN_* used for the local joins */
     int64_t updates[64];   /* list entries changed in iteration t (index t-1) */
     int64_t pairs[64];     /* local-join pairs evaluated in iteration t */
     int64_t proposals[64]; /* proposals that passed the K-th filter at emission */

@@ -279,6 +279,46 @@ __device__ __forceinline__ void spill_put(int32_t t, uint64_t key, int64_t pos,
     }
 }
 
+// Reserve this wave's bucket ranges for members i = lane + 64 j: one global
+// atomic per member on its proposal counter, and one per wave and j on the
+// spill counter for the parts that do not fit in the buckets.
+__device__ __forceinline__ unsigned long long reserve_ranges(
+    int m, const int32_t *__restrict__ ids, int32_t *__restrict__ cnt, int32_t *__restrict__ base,
+    int64_t *__restrict__ sbase, int32_t *__restrict__ pcnt, int B,
+    unsigned long long *__restrict__ counters) {
+    const int lane = lane_id();
+    unsigned long long props = 0;
+    for (int j0 = 0; j0 < m; j0 += PG_WAVE) {
+        const int i = j0 + lane;
+        int over = 0;
+        if (i < m) {
+            const int c = cnt[i];
+            if (c > 0) {
+                const int b0 = atomicAdd(&pcnt[ids[i]], c);
+                base[i] = b0;
+                over = max(0, b0 + c - max(b0, B));  // entries past the bucket
+                props += (unsigned long long)c;
+            }
+            cnt[i] = 0;
+        }
+        // exclusive prefix of `over` across the wave, one atomic for the total
+        int incl = over;
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) {
+            const int t = __shfl_up(incl, o, PG_WAVE);
+            if (lane >= o) incl += t;
+        }
+        const int total = __shfl(incl, PG_WAVE - 1, PG_WAVE);
+        unsigned long long sb = 0;
+        if (total > 0) {
+            if (lane == PG_WAVE - 1) sb = atomicAdd(&counters[C_SPILL], (unsigned long long)total);
+            sb = (unsigned long long)__shfl((long long)sb, PG_WAVE - 1, PG_WAVE);
+        }
+        if (over > 0) sbase[i] = (int64_t)(sb + (unsigned long long)(incl - over));
+    }
+    return props;
+}
+
 __global__ void k_spill_count(const int32_t *__restrict__ spill_t, int64_t cnt,
                               int32_t *__restrict__ scnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -457,18 +497,7 @@ __global__ __launch_bounds__(JT) void k_join(
             }
         }
         __builtin_amdgcn_wave_barrier();
-        for (int i = lane; i < m; i += PG_WAVE) {
-            const int c = cnt[i];
-            if (c > 0) {
-                const int b0 = atomicAdd(&pcnt[ids[i]], c);
-                base[i] = b0;
-                const int over = b0 + c - max(b0, B);  // entries past the bucket
-                if (over > 0)
-                    sbase[i] = (int64_t)atomicAdd(&counters[C_SPILL], (unsigned long long)over);
-                local_props += (unsigned long long)c;
-            }
-            cnt[i] = 0;
-        }
+        local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, counters);
         __builtin_amdgcn_wave_barrier();
         if (brb >= 0) {
 #pragma unroll
@@ -512,6 +541,231 @@ __global__ __launch_bounds__(JT) void k_join(
         local_props += t;
     }
     if (lane == 0 && local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
+}
+
+// ---------------------------------------------------------------------------
+// Stage and precision prep: 16-bit copies, canonical norms, exactness test.
+// For integer-valued data with every squared norm <= 2^23, each product and
+// every partial sum of a dot product is an integer below 2^24, so the MFMA
+// norm expansion n_x + n_y - 2 x.y (FP32 accumulation, any summation order)
+// equals the canonical chain distance exactly.  The test needs |x| <= 2048
+// for FP16 operands and |x| <= 256 for BF16 operands to be exact.
+// ---------------------------------------------------------------------------
+enum { EX_NONINT = 0, EX_MAXABS = 1, EX_MAXNORM = 2 };
+
+__global__ __launch_bounds__(256) void k_prep(const float *__restrict__ X, int64_t ldx, int d, int d16,
+                                              int64_t n, int mode, _Float16 *__restrict__ xh,
+                                              __bf16 *__restrict__ xb, float *__restrict__ norms,
+                                              unsigned int *__restrict__ ex) {
+    // one wave per row
+    const int lane = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const float *x = X + i * ldx;
+    bool nonint = false;
+    float mabs = 0.f;
+    for (int k = lane; k < d16; k += PG_WAVE) {
+        const float v = k < d ? x[k] : 0.f;
+        nonint |= (v != rintf(v));
+        mabs = fmaxf(mabs, fabsf(v));
+        if (mode == PG_FP16) xh[i * d16 + k] = (_Float16)v;
+        if (mode == PG_BF16) xb[i * d16 + k] = (__bf16)v;
+    }
+    const uint64_t ni = __ballot(nonint);
+#pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, o, PG_WAVE));
+    if (lane == 0) {
+        float s = 0.f;  // canonical chain of x against the origin
+        for (int k = 0; k < d; ++k) s = fmaf(x[k], x[k], s);
+        norms[i] = s;
+        if (ni) atomicOr(&ex[EX_NONINT], 1u);
+        atomicMax(&ex[EX_MAXABS], __float_as_uint(mabs));
+        atomicMax(&ex[EX_MAXNORM], __float_as_uint(s));
+    }
+}
+
+typedef float mf_f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 mf_f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
+
+// 32 x 32 block of x_r . x_c over all d for member rows (ra[lane%32]) and
+// columns (ca[lane%32]); result in the MFMA accumulator layout: lane l,
+// register g holds row 8*(g/4) + 4*(l/32) + g%4, column l%32.
+template <int P>
+__device__ __forceinline__ mf_f32x16 gram_tile(const float *__restrict__ X, int64_t ldx,
+                                               const void *__restrict__ X16, int d, int d16,
+                                               int32_t rid, int32_t cid) {
+    const int h = lane_id() >> 5;
+    mf_f32x16 acc;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) acc[g] = 0.f;
+    if (P == PG_FP32) {
+        // float4 chunk t: lane half h takes dims 4t+2h and 4t+2h+1 in two steps
+        const float *ra = X + (int64_t)rid * ldx + 2 * h;
+        const float *ca = X + (int64_t)cid * ldx + 2 * h;
+        for (int t = 0; t < d; t += 4) {
+            const float2 a = *reinterpret_cast<const float2 *>(ra + t);
+            const float2 b = *reinterpret_cast<const float2 *>(ca + t);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+        }
+    } else if (P == PG_FP16) {
+        const _Float16 *ra = reinterpret_cast<const _Float16 *>(X16) + (int64_t)rid * d16 + 8 * h;
+        const _Float16 *ca = reinterpret_cast<const _Float16 *>(X16) + (int64_t)cid * d16 + 8 * h;
+        for (int t = 0; t < d16; t += 16) {
+            const mf_f16x8 a = *reinterpret_cast<const mf_f16x8 *>(ra + t);
+            const mf_f16x8 b = *reinterpret_cast<const mf_f16x8 *>(ca + t);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+        }
+    } else {
+        const __bf16 *ra = reinterpret_cast<const __bf16 *>(X16) + (int64_t)rid * d16 + 8 * h;
+        const __bf16 *ca = reinterpret_cast<const __bf16 *>(X16) + (int64_t)cid * d16 + 8 * h;
+        for (int t = 0; t < d16; t += 16) {
+            const mf_bf16x8 a = *reinterpret_cast<const mf_bf16x8 *>(ra + t);
+            const mf_bf16x8 b = *reinterpret_cast<const mf_bf16x8 *>(ca + t);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+constexpr int MW = 4;  // sources (waves) per workgroup in the MFMA join
+
+// MFMA local join for data on which the norm expansion is exact (see k_prep):
+// one wave per source, 32 x 32 Gram tiles of (new members) x (all members),
+// d2 = n_r + n_c - 2 x_r.x_c, then the same decisions and reservations as the
+// FP32 join.  Offsets of the proposals to a tile's row member come from
+// ballots (the 32 lanes of a half share the row), so only one LDS atomic per
+// (row, tile half) and one per (lane, column) are needed.
+template <int P>
+__global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
+    const float *__restrict__ X, int64_t ldx, const void *__restrict__ X16, int d, int d16,
+    const float *__restrict__ norms, int K, const int32_t *__restrict__ jn,
+    const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
+    const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
+    int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
+    int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t spill_cap,
+    uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, int64_t u0, int64_t u1,
+    int maxm, unsigned long long *__restrict__ counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int MPS = (maxm + 31) / 32 * 32;
+    const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
+    const int wv = threadIdx.x / PG_WAVE;
+    const int64_t u = u0 + (int64_t)blockIdx.x * MW + wv;
+    if (u >= u1) return;
+    unsigned char *region = smem + (size_t)wv * MPS * (8 + 8 + 4 + 4 + 4 + 4 + 4);
+    uint64_t *kth = reinterpret_cast<uint64_t *>(region);
+    int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
+    int32_t *ids = reinterpret_cast<int32_t *>(sbase + MPS);
+    int32_t *cnt = ids + MPS;
+    int32_t *base = cnt + MPS;
+    int32_t *mk = base + MPS;
+    float *nrm = reinterpret_cast<float *>(mk + MPS);
+
+    const int nn = jn_c[u], no = jo_c[u];
+    const int m = nn + no;
+    if (nn == 0 || m < 2) return;
+    const int mp = (m + 31) / 32 * 32;
+    bool anymark = false;
+    for (int i = lane; i < mp; i += PG_WAVE) {
+        const int32_t id = i < nn ? jn[u * JN + i] : (i < m ? jo[u * JO + (i - nn)] : -1);
+        ids[i] = id;
+        kth[i] = id >= 0 ? keys[(int64_t)id * K + (K - 1)] : 0ull;
+        nrm[i] = id >= 0 ? norms[id] : 0.f;
+        cnt[i] = 0;
+        const int mkv = (mark && id >= 0) ? (int)mark[id] : (mark ? 0 : 1);
+        mk[i] = mkv;
+        anymark |= (id >= 0 && mkv != 0);
+    }
+    if (__ballot(anymark) == 0) return;
+    __builtin_amdgcn_wave_barrier();
+    const int RB = (nn + 31) / 32, CB = mp / 32;
+    const int32_t id0 = ids[0];
+    unsigned long long local_props = 0;
+    for (int rb = 0; rb < RB; ++rb) {
+        for (int cb = rb; cb < CB; ++cb) {
+            // member of this lane's column and of the tile rows it loads
+            const int cm = 32 * cb + l32;
+            const int rm = 32 * rb + l32;
+            const int32_t cid = cm < m ? ids[cm] : id0;
+            const int32_t rid = rm < nn ? ids[rm] : id0;
+            const mf_f32x16 g = gram_tile<P>(X, ldx, X16, d, d16, rid, cid);
+            // decisions (bit g of each mask = accumulator register g)
+            uint32_t to_row = 0, to_col = 0;
+            const float nc = nrm[cm < mp ? cm : 0];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
+                if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
+                const float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                const uint64_t kw = pack_key(d2, ids[cm]), kv = pack_key(d2, ids[r]);
+                if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
+                    to_row |= 1u << q;
+                if (mk[cm] && kv < kth[cm] && !(mark && list_has(keys + (int64_t)ids[cm] * K, K, kv)))
+                    to_col |= 1u << q;
+            }
+            // offsets: rows by ballot (one LDS atomic per row and half), columns per lane
+            int off_row[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const uint64_t bm = __ballot((to_row >> q) & 1u);
+                const uint64_t mine = h ? (bm >> 32) : (bm & 0xFFFFFFFFull);
+                const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
+                int b0 = 0;
+                if (l32 == 0 && mine) b0 = atomicAdd(&cnt[r], __popcll(mine));
+                b0 = __shfl(b0, lane & 32, PG_WAVE);
+                const uint64_t below = (lanemask_lt() >> (32 * h)) & 0xFFFFFFFFull;
+                off_row[q] = b0 + __popcll(mine & below);
+            }
+            int off_col = 0;
+            {
+                const int c_c = __popc(to_col);
+                if (c_c) off_col = atomicAdd(&cnt[cm], c_c);
+            }
+            __builtin_amdgcn_wave_barrier();
+            local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, counters);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const uint32_t bit = 1u << q;
+                if (!((to_row | to_col) & bit)) continue;
+                const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
+                const float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                if (to_row & bit) {
+                    const int32_t v = ids[r];
+                    const int slot = base[r] + off_row[q];
+                    const uint64_t kw = pack_key(d2, ids[cm]);
+                    if (slot < B)
+                        bucket[(int64_t)v * B + slot] = kw;
+                    else
+                        spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k, spill_cap,
+                                  ovf_next, counters);
+                }
+                if (to_col & bit) {
+                    const int32_t w = ids[cm];
+                    const int slot = base[cm] + off_col++;
+                    const uint64_t kv = pack_key(d2, ids[r]);
+                    if (slot < B)
+                        bucket[(int64_t)w * B + slot] = kv;
+                    else
+                        spill_put(w, kv, sbase[cm] + (slot - max(base[cm], B)), spill_t, spill_k, spill_cap,
+                                  ovf_next, counters);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1) {
+        const unsigned long long t = __shfl_xor((long long)local_props, o, PG_WAVE);
+        local_props += t;
+    }
+    if (lane == 0 && local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
+}
+
+static size_t join_mfma_lds_bytes(int maxm) {
+    const int mps = (maxm + 31) / 32 * 32;
+    return (size_t)MW * mps * (8 + 8 + 4 + 4 + 4 + 4 + 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -716,15 +970,16 @@ __global__ __launch_bounds__(256) void k_exact_knn(const float *__restrict__ X, 
 struct KnnLayout {
     size_t keys, newm, insm, nf, nf_c, of, of_c, rn_cnt, ro_cnt, rn_off, ro_off, rn_list, ro_list,
         jn, jn_c, jo, jo_c, pcnt, bucket, mark, mark_next, counters, scan_tmp, spill_t, spill_k,
-        spill_s, total;
-    int B, JN, JO;
+        spill_s, x16, norms, exflags, total;
+    int B, JN, JO, d16;
     int64_t spill_cap;
 };
 
 static int default_bucket(int K) { return 4 * K; }
 
-static KnnLayout knn_layout(const pg_knn_params *p, int64_t n) {
+static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d) {
     KnnLayout L{};
+    L.d16 = (d + 15) / 16 * 16;
     const int64_t K = p->K, S = p->S;
     L.B = p->bucket_cap > 0 ? p->bucket_cap : default_bucket(p->K);
     L.JN = (int)(2 * S);
@@ -758,10 +1013,14 @@ static KnnLayout knn_layout(const pg_knn_params *p, int64_t n) {
     L.mark_next = take(n);
     L.counters = take(sizeof(unsigned long long) * C_NCOUNTERS);
     L.scan_tmp = take(scan_tmp_bytes(n + 1));
-    L.spill_cap = std::max<int64_t>(1 << 16, n * K / 4);
+    L.spill_cap = std::max<int64_t>(1 << 16, n * K / 2);
     L.spill_t = take(sizeof(int32_t) * L.spill_cap);
     L.spill_k = take(sizeof(uint64_t) * L.spill_cap);
     L.spill_s = take(sizeof(uint64_t) * L.spill_cap);
+    const bool half = p->precision == PG_FP16 || p->precision == PG_BF16;
+    L.x16 = take(half ? (size_t)2 * n * L.d16 : 0);
+    L.norms = take(sizeof(float) * n);
+    L.exflags = take(sizeof(unsigned int) * 4);
     L.total = o;
     return L;
 }
@@ -792,9 +1051,9 @@ static pg_status check_knn(const pg_knn_params *p, int64_t n, int32_t d) {
         set_error("pg_knn_build: max_iters=%d out of [0, 64]", p->max_iters);
         return PG_EINVAL;
     }
-    if (p->precision != PG_FP32) {
-        set_error("pg_knn_build: precision %d not supported", p->precision);
-        return PG_EUNSUPPORTED;
+    if (p->precision < PG_FP32 || p->precision > PG_FP32_VALU) {
+        set_error("pg_knn_build: unknown precision %d", p->precision);
+        return PG_EINVAL;
     }
     if (p->bucket_cap != 0 && p->bucket_cap < 2 * p->K) {
         set_error("pg_knn_build: bucket_cap=%d must be 0 or >= 2K", p->bucket_cap);
@@ -818,7 +1077,7 @@ extern "C" pg_status pg_knn_build_workspace(const pg_knn_params *p, int64_t n, i
         set_error("pg_knn_build_workspace: bytes is NULL");
         return PG_EINVAL;
     }
-    *bytes = p->exact ? 0 : knn_layout(p, n).total;
+    *bytes = p->exact ? 0 : knn_layout(p, n, d).total;
     return PG_OK;
 }
 
@@ -876,7 +1135,7 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
     }
     if (stats) memset(stats, 0, sizeof(*stats));
     if (p->exact) return knn_exact_lists(ctx, X, n, d, ldx, p->K, knn_ids, knn_d2);
-    const KnnLayout L = knn_layout(p, n);
+    const KnnLayout L = knn_layout(p, n, d);
     if (!ws || ws_bytes < L.total) {
         set_error("pg_knn_build: workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
                   L.total);
@@ -910,8 +1169,45 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                            keys, newm, insm);
         PG_HIP(hipGetLastError());
     }
+    // ---- a1: precision prep and exactness test; choose the join path
+    _Float16 *xh = (_Float16 *)(w + L.x16);
+    __bf16 *xb = (__bf16 *)(w + L.x16);
+    float *norms = (float *)(w + L.norms);
+    unsigned int *exf = (unsigned int *)(w + L.exflags);
+    int path = PG_JOIN_VALU;
+    if (p->precision != PG_FP32_VALU) {
+        PG_HIP(hipMemsetAsync(exf, 0, sizeof(unsigned int) * 4, st));
+        hipLaunchKernelGGL(k_prep, dim3(wave_blocks), dim3(256), 0, st, X, ldx, d, L.d16, n, p->precision, xh,
+                           xb, norms, exf);
+        PG_HIP(hipGetLastError());
+        unsigned int he[4];
+        PG_HIP(hipMemcpyAsync(he, exf, sizeof(he), hipMemcpyDeviceToHost, st));
+        PG_HIP(hipStreamSynchronize(st));
+        float maxabs, maxnorm;
+        memcpy(&maxabs, &he[EX_MAXABS], 4);
+        memcpy(&maxnorm, &he[EX_MAXNORM], 4);
+        const bool ints = he[EX_NONINT] == 0 && maxnorm <= 8388608.0f;
+        if (p->precision == PG_FP32 && ints) path = PG_JOIN_MFMA_FP32;
+        if (p->precision == PG_FP16) {
+            if (!(ints && maxabs <= 2048.0f)) {
+                set_error("pg_knn_build: FP16 tiles need integer data with |x| <= 2048 and "
+                          "squared norms <= 2^23 (exact); use PG_FP32 for this data");
+                return PG_EUNSUPPORTED;
+            }
+            path = PG_JOIN_MFMA_FP16;
+        }
+        if (p->precision == PG_BF16) {
+            if (!(ints && maxabs <= 256.0f)) {
+                set_error("pg_knn_build: BF16 tiles need integer data with |x| <= 256 and "
+                          "squared norms <= 2^23 (exact); use PG_FP32 for this data");
+                return PG_EUNSUPPORTED;
+            }
+            path = PG_JOIN_MFMA_BF16;
+        }
+    }
+    if (stats) stats->join_path = path;
     const int maxm = 3 * S + K;
-    const size_t lds = join_lds_bytes(maxm);
+    const size_t lds = path == PG_JOIN_VALU ? join_lds_bytes(maxm) : join_mfma_lds_bytes(maxm);
     int iters = 0;
     int64_t prev_props = -1;
     for (int t = 1; t <= p->max_iters; ++t) {
@@ -938,11 +1234,18 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         // source passes: many in the first iteration (random lists accept almost
         // every proposal), fewer once the lists are good; the count never
         // changes the result
-        // first iteration: pass sizes n/c, n/c, 2n/c, 4n/c, ... (each merge
-        // tightens every K-th key, so later passes emit fewer proposals)
+        // pass sizes n/c, n/c, 2n/c, 4n/c, ...: each merge tightens every K-th
+        // key, so later (larger) passes emit fewer proposals.  c grows with the
+        // proposals the previous iteration emitted (many passes while the
+        // lists are still poor); it never changes the result.
         std::vector<int64_t> bounds{0};
-        if (prev_props < 0) {
-            const int64_t c0 = p->chunks > 0 ? p->chunks : 64;
+        {
+            int64_t c0;
+            if (prev_props < 0)
+                c0 = p->chunks > 0 ? p->chunks : 64;
+            else
+                c0 = (int64_t)std::min<double>(
+                    64.0, std::max<double>(1.0, std::ceil(4.0 * (double)prev_props / ((double)L.B * n))));
             int64_t sz = std::max<int64_t>(1, n / c0), at = 0;
             bool first = true;
             while (at < n) {
@@ -950,15 +1253,6 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                 bounds.push_back(at);
                 if (!first) sz *= 2;
                 first = false;
-            }
-        } else {
-            const double cap = 0.5 * (double)L.B * (double)n;
-            const int nch = (int)std::min<double>(
-                64.0, std::max<double>(1.0, std::ceil((double)prev_props / cap)));
-            const int64_t step = (n + nch - 1) / nch;
-            for (int64_t at = step; ; at += step) {
-                bounds.push_back(std::min(at, n));
-                if (at >= n) break;
             }
         }
         for (size_t ci = 0; ci + 1 < bounds.size(); ++ci) {
@@ -968,10 +1262,28 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
             for (int attempt = 0;; ++attempt) {
                 {
                     TimedLaunch tl(ctx, K_JOIN, -1.0);
-                    hipLaunchKernelGGL(k_join, dim3((unsigned)((cnt + JW - 1) / JW)), dim3(JT), lds, st,
-                                       X, ldx, d, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt, bucket,
-                                       L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, u0, u0 + cnt,
-                                       maxm, counters);
+                    const unsigned mg = (unsigned)((cnt + MW - 1) / MW);
+                    const void *x16 = (const void *)(w + L.x16);
+                    if (path == PG_JOIN_VALU)
+                        hipLaunchKernelGGL(k_join, dim3((unsigned)((cnt + JW - 1) / JW)), dim3(JT), lds, st,
+                                           X, ldx, d, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt, bucket,
+                                           L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, u0, u0 + cnt,
+                                           maxm, counters);
+                    else if (path == PG_JOIN_MFMA_FP32)
+                        hipLaunchKernelGGL(k_join_mfma<PG_FP32>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
+                                           x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
+                                           pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
+                                           u0, u0 + cnt, maxm, counters);
+                    else if (path == PG_JOIN_MFMA_FP16)
+                        hipLaunchKernelGGL(k_join_mfma<PG_FP16>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
+                                           x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
+                                           pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
+                                           u0, u0 + cnt, maxm, counters);
+                    else
+                        hipLaunchKernelGGL(k_join_mfma<PG_BF16>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
+                                           x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
+                                           pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
+                                           u0, u0 + cnt, maxm, counters);
                     PG_HIP(hipGetLastError());
                 }
                 unsigned long long hc2[C_NCOUNTERS];

@@ -66,11 +66,18 @@ def _knn_oracle(oracle, X, K, S, T, seed, stop):
     return oracle.nndescent(X, K, S, T, seed, stop_updates=stop)
 
 
-@pytest.mark.parametrize("n,d,K,S,T", [(1500, 32, 16, 8, 5), (700, 12, 8, 4, 6), (90, 8, 64, 32, 3)])
-def test_nndescent_bit_exact(pg, oracle, datagen, n, d, K, S, T):
-    log("nndescent", n, d, K, S, T)
+PATHS = {0: "fp32-mfma", 3: "fp32-valu", 1: "fp16-mfma", 2: "bf16-mfma"}
+
+
+@pytest.mark.parametrize("prec", [0, 3, 1, 2], ids=lambda p: PATHS[p])
+@pytest.mark.parametrize("n,d,K,S,T", [(1500, 32, 16, 8, 5), (700, 12, 8, 4, 6), (90, 8, 64, 32, 3),
+                                       (600, 40, 24, 12, 4)])
+def test_nndescent_bit_exact(pg, oracle, datagen, n, d, K, S, T, prec):
+    # integer data in [0, 255]: FP32, FP16 and BF16 MFMA norm expansions are all exact
+    log("nndescent", n, d, K, S, T, PATHS[prec])
     X = datagen.uniform_int(n, d, seed=7)
-    ids, d2, st = pg.knn_build(dev(X), K, S=S, max_iters=T, seed=5, stop_updates=-1)
+    ids, d2, st = pg.knn_build(dev(X), K, S=S, max_iters=T, seed=5, stop_updates=-1, precision=prec)
+    assert st["join_path"] == PATHS[prec]
     rid, rd2, _, rst = _knn_oracle(oracle, X, K, S, T, 5, -1)
     assert st["updates"] == rst["updates"]
     assert st["pairs"] == rst["pairs"]
@@ -78,14 +85,15 @@ def test_nndescent_bit_exact(pg, oracle, datagen, n, d, K, S, T):
     assert np.array_equal(host(d2), rd2.astype(np.float32))
 
 
-def test_nndescent_tuning_knobs_do_not_change_result(pg, datagen):
+@pytest.mark.parametrize("prec", [0, 3, 1], ids=lambda p: PATHS[p])
+def test_nndescent_tuning_knobs_do_not_change_result(pg, datagen, prec):
     # bucket capacity and pass boundaries change speed only: tiny buckets force
-    # the overflow-retry path, many passes split every iteration
+    # the spill list and the repeat passes, many passes split every iteration
     X = datagen.uniform_int(2000, 16, seed=11)
-    base = pg.knn_build(dev(X), 16, S=8, max_iters=6, seed=3, stop_updates=-1)
-    for cap, ch in [(32, 1), (32, 7), (64, 200), (512, 2)]:
+    base = pg.knn_build(dev(X), 16, S=8, max_iters=6, seed=3, stop_updates=-1, precision=prec)
+    for cap, ch in [(32, 1), (32, 7), (64, 200), (512, 2), (128, 1)]:
         ids, d2, st = pg.knn_build(dev(X), 16, S=8, max_iters=6, seed=3, stop_updates=-1,
-                                   bucket_cap=cap, chunks=ch)
+                                   bucket_cap=cap, chunks=ch, precision=prec)
         assert torch.equal(ids, base[0]) and torch.equal(d2, base[1]), (cap, ch)
         assert st["updates"] == base[2]["updates"]
         if cap == 32:
@@ -107,6 +115,10 @@ def test_nndescent_c1_config(pg, oracle, datagen):
 def test_nndescent_float_statistical(pg, oracle, datagen):
     X, _ = datagen.unit_mixture(4000, 0, d=96, n_clusters=40, seed=4)
     ids, d2, st = pg.knn_build(dev(X), 16, S=8, max_iters=10, seed=2)
+    assert st["join_path"] == "fp32-valu"  # norm expansion is not exact on this data
+    with pytest.raises(pg.PgError) as e:
+        pg.knn_build(dev(X), 16, S=8, max_iters=2, seed=2, precision=pg.FP16)
+    assert e.value.status == -4
     rid, rd2, _, rst = oracle.nndescent(X, 16, 8, 10, 2, stop_updates=int(0.001 * 4000 * 16))
     gt, _ = oracle.exact_knn(X, X, 16, exclude=np.arange(4000))
     g = host(ids)
