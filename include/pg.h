@@ -83,7 +83,8 @@ pg_status pg_ctx_destroy(pg_ctx *ctx);
  * of launches, and the summed algorithmic work of those launches (flops for
  * the distance kernels, bytes for the others, as documented per kernel).
  * Reading the times synchronises the stream.  Names: "join", "merge", "init",
- * "sample", "prune", "search", "exact_knn". */
+ * "sample", "prune", "search", "exact_knn", and "connect" (the whole connect
+ * step of pg_prune as one region: several launches and host synchronisations). */
 pg_status pg_ctx_set_timing(pg_ctx *ctx, int enable);
 pg_status pg_ctx_kernel_time(pg_ctx *ctx, const char *name, double *total_ms,
                              int64_t *launches, double *work);

@@ -171,7 +171,7 @@ pg_status scan_exclusive(pg_ctx *ctx, const int32_t *in, int64_t *out, int64_t n
     return PG_OK;
 }
 
-static const char *kNames[K_COUNT] = {"join", "merge", "init", "sample", "prune", "search", "exact_knn"};
+static const char *kNames[K_COUNT] = {"join", "merge", "init", "sample", "prune", "search", "exact_knn", "connect"};
 
 }  // namespace pgi
 

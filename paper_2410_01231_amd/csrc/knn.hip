@@ -553,34 +553,53 @@ __global__ __launch_bounds__(JT) void k_join(
 // ---------------------------------------------------------------------------
 enum { EX_NONINT = 0, EX_MAXABS = 1, EX_MAXNORM = 2 };
 
+// Grid-stride over rows, one wave per row.  The norm is a lane-parallel tree
+// sum: it is only used where the data pass the exactness test, and there
+// every order gives the same value (and a norm above 2^23 cannot come out at
+// or below 2^23).  One atomic per block and flag.
 __global__ __launch_bounds__(256) void k_prep(const float *__restrict__ X, int64_t ldx, int d, int d16,
                                               int64_t n, int mode, _Float16 *__restrict__ xh,
                                               __bf16 *__restrict__ xb, float *__restrict__ norms,
                                               unsigned int *__restrict__ ex) {
-    // one wave per row
-    const int lane = lane_id();
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    const float *x = X + i * ldx;
+    __shared__ unsigned int red[4][3];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
     bool nonint = false;
-    float mabs = 0.f;
-    for (int k = lane; k < d16; k += PG_WAVE) {
-        const float v = k < d ? x[k] : 0.f;
-        nonint |= (v != rintf(v));
-        mabs = fmaxf(mabs, fabsf(v));
-        if (mode == PG_FP16) xh[i * d16 + k] = (_Float16)v;
-        if (mode == PG_BF16) xb[i * d16 + k] = (__bf16)v;
+    float mabs = 0.f, mnorm = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < n; i += (int64_t)gridDim.x * 4) {
+        const float *x = X + i * ldx;
+        float s = 0.f;
+        for (int k = lane; k < d16; k += PG_WAVE) {
+            const float v = k < d ? x[k] : 0.f;
+            nonint |= (v != rintf(v));
+            mabs = fmaxf(mabs, fabsf(v));
+            s = fmaf(v, v, s);
+            if (mode == PG_FP16) xh[i * d16 + k] = (_Float16)v;
+            if (mode == PG_BF16) xb[i * d16 + k] = (__bf16)v;
+        }
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) s += __shfl_xor(s, o, PG_WAVE);
+        if (lane == 0) norms[i] = s;
+        mnorm = fmaxf(mnorm, s);
     }
-    const uint64_t ni = __ballot(nonint);
+    const unsigned int ni = __ballot(nonint) != 0 ? 1u : 0u;
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, o, PG_WAVE));
     if (lane == 0) {
-        float s = 0.f;  // canonical chain of x against the origin
-        for (int k = 0; k < d; ++k) s = fmaf(x[k], x[k], s);
-        norms[i] = s;
-        if (ni) atomicOr(&ex[EX_NONINT], 1u);
-        atomicMax(&ex[EX_MAXABS], __float_as_uint(mabs));
-        atomicMax(&ex[EX_MAXNORM], __float_as_uint(s));
+        red[wv][0] = ni;
+        red[wv][1] = __float_as_uint(mabs);
+        red[wv][2] = __float_as_uint(mnorm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int a = 0, b = 0, c = 0;
+        for (int w = 0; w < 4; ++w) {
+            a |= red[w][0];
+            b = max(b, red[w][1]);
+            c = max(c, red[w][2]);
+        }
+        if (a) atomicOr(&ex[EX_NONINT], 1u);
+        atomicMax(&ex[EX_MAXABS], b);
+        atomicMax(&ex[EX_MAXNORM], c);
     }
 }
 
@@ -1177,7 +1196,8 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
     int path = PG_JOIN_VALU;
     if (p->precision != PG_FP32_VALU) {
         PG_HIP(hipMemsetAsync(exf, 0, sizeof(unsigned int) * 4, st));
-        hipLaunchKernelGGL(k_prep, dim3(wave_blocks), dim3(256), 0, st, X, ldx, d, L.d16, n, p->precision, xh,
+        hipLaunchKernelGGL(k_prep, dim3((unsigned)std::min<int64_t>(wave_blocks, 4096)), dim3(256), 0, st, X, ldx,
+                           d, L.d16, n, p->precision, xh,
                            xb, norms, exf);
         PG_HIP(hipGetLastError());
         unsigned int he[4];

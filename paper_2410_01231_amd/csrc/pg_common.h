@@ -210,7 +210,7 @@ struct pg_ctx {
 };
 
 namespace pgi {
-enum KernelId { K_JOIN = 0, K_MERGE, K_INIT, K_SAMPLE, K_PRUNE, K_SEARCH, K_EXACT, K_COUNT };
+enum KernelId { K_JOIN = 0, K_MERGE, K_INIT, K_SAMPLE, K_PRUNE, K_SEARCH, K_EXACT, K_CONNECT, K_COUNT };
 // Record the start/stop of a timed launch on the context stream.
 struct TimedLaunch {
     pg_ctx *ctx;

@@ -309,23 +309,41 @@ __global__ __launch_bounds__(256) void k_argmin_final(const double *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// connectivity: level-synchronous BFS over out-edges + nearest reachable node
+// connectivity
+//
+// The connect step visits the nodes the entry point does not reach in
+// increasing id order.  Each one still unreached at its turn (a root) gets one
+// edge p -> r from a node p reached by then, and everything r reaches counts
+// as reached from then on.  Added edges only leave reached nodes, so which
+// nodes are roots and when each node becomes reached depend on the pruned
+// graph alone:
+//   * an unreached v is a root iff no smaller unreached node reaches v;
+//   * a node p counts as reached from the turn of the smallest root reaching
+//     it, and that root is the smallest unreached node reaching p.
+// The roots and every node's turn ("reach time") therefore come from a
+// parallel min-ancestor label propagation, every root's sorted candidate list
+// from one parallel pass, and only the degree bookkeeping (a node at degree R
+// accepts no edge) runs in root order, in one wave.
 // ---------------------------------------------------------------------------
 struct ConnState {
     int32_t fcount[2];
-    int32_t first_unreached;  // root waiting for the global nearest-node scan
-    int32_t n_roots;
+    int32_t changed;    // label propagation: some label dropped in this round
+    int32_t idx;        // next root (global index) for the matching wave
+    int32_t stop_root;  // >= 0: root waiting for the exact scan of all nodes
+    int32_t stop_turn;  //       and its 1-based turn
+    int32_t n_empty;    // roots of the current batch with no usable candidate
     int32_t overflow;
-    int32_t idx;              // next position in the list of unreached ids
-    int32_t bfs_head;         // > 0: the wave handed a BFS queue[bfs_head, bfs_tail)
-    int32_t bfs_tail;         //      over to the multi-block BFS
     unsigned long long nearest;
 };
 
-// a BFS that grows past this many queued nodes continues on the multi-block path
-constexpr int CONNECT_WAVE_BFS = 2048;
+// roots handled per batch of candidate lists
+constexpr int32_t CONNECT_BATCH = 16384;
+// roots per step of the matching wave
+constexpr int MATCH_STEP = 16;
+// roots per block of the all-nodes scan
+constexpr int GQ = 16;
 
-// loads that must see stores made earlier in the same kernel (bypass L1)
+// loads that must see stores and atomics made earlier in the same kernel
 __device__ __forceinline__ int32_t ld_fresh(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -342,86 +360,219 @@ __global__ void k_scatter_unreached(const int32_t *__restrict__ visited, int64_t
     if (i < n && visited[i] == 0) U[off[i]] = (int32_t)i;
 }
 
-// The connect loop of the refinement, one wave: unreached ids in increasing
-// order; each still-unreached r gets the edge p -> r from its closest reached
-// candidate p with degree < R, then a BFS from r marks what r reaches.  When no
-// candidate of r qualifies the wave stops and leaves r in first_unreached for
-// the global scan on the host side.
-__global__ __launch_bounds__(64) void k_connect_loop(const float *__restrict__ X, int64_t ldx, int d,
-                                                     int64_t n, int R, const int32_t *__restrict__ cand,
-                                                     int C, int32_t *g, float *gd, int32_t *deg,
-                                                     int32_t *visited, const int32_t *__restrict__ U,
-                                                     int32_t nu, int32_t *queue, int32_t *roots,
-                                                     ConnState *cs) {
-    const int lane = lane_id();
-    for (int32_t idx = cs->idx; idx < nu; ++idx) {
-        const int32_t r = U[idx];
-        if (ld_fresh(&visited[r])) continue;
-        uint64_t key = KEY_INF;
-        if (lane < C) {
-            const int32_t p = cand[(int64_t)r * C + lane];
-            if (p >= 0 && p < n && p != r && ld_fresh(&visited[p]) && ld_fresh(&deg[p]) < R)
-                key = pack_key(dist_chain(X + (int64_t)r * ldx, X + (int64_t)p * ldx, d), p);
+__global__ void k_label_init(const int32_t *__restrict__ U, int32_t nu, int32_t *__restrict__ lab) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nu) lab[U[i]] = U[i];
+}
+
+// One round of min-ancestor labels over the unreached nodes U: every edge
+// u -> v inside U lowers lab[v] to lab[u], and lab[u] drops to lab[lab[u]]
+// (an ancestor of an ancestor).  Labels stay ancestors and only decrease;
+// a round without a change leaves each node its smallest ancestor.
+__global__ __launch_bounds__(256) void k_label_round(const int32_t *__restrict__ g,
+                                                     const int32_t *__restrict__ deg, int R, int64_t n,
+                                                     const int32_t *__restrict__ visited,
+                                                     const int32_t *__restrict__ U, int32_t nu,
+                                                     int32_t *lab, int32_t *changed) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nu * R) return;
+    const int32_t u = U[t / R];
+    const int j = (int)(t % R);
+    bool ch = false;
+    if (j == 0) {
+        const int32_t a = lab[u];
+        const int32_t b = lab[a];
+        if (b < a && atomicMin(&lab[u], b) > b) ch = true;
+    }
+    if (j < min(deg[u], R)) {
+        const int32_t v = g[(int64_t)u * R + j];
+        if (v >= 0 && v < n && !visited[v]) {
+            const int32_t l = lab[u];
+            if (l < lab[v] && atomicMin(&lab[v], l) > l) ch = true;
         }
+    }
+    if (ch) *changed = 1;
+}
+
+__global__ void k_flag_roots(const int32_t *__restrict__ U, int32_t nu, const int32_t *__restrict__ lab,
+                             int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nu) flag[i] = lab[U[i]] == U[i];
+}
+
+// roots in increasing id order; tt[root] = its 1-based turn
+__global__ void k_scatter_roots(const int32_t *__restrict__ U, int32_t nu, const int32_t *__restrict__ lab,
+                                const int64_t *__restrict__ pos, int32_t *__restrict__ roots,
+                                int32_t *__restrict__ tt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nu) return;
+    const int32_t v = U[i];
+    if (lab[v] == v) {
+        roots[pos[i]] = v;
+        tt[v] = (int32_t)pos[i] + 1;
+    }
+}
+
+// tt[p] = turn from which p counts as reached (0: reached from the entry
+// point).  Only root entries are read, and those do not change here.
+__global__ void k_reach_time(const int32_t *__restrict__ U, int32_t nu, const int32_t *__restrict__ lab,
+                             int32_t *tt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nu) return;
+    const int32_t v = U[i], a = lab[v];
+    if (a != v) tt[v] = tt[a];
+}
+
+// Sorted keys (d2, p) of the candidates of roots [b0, b1) that count as
+// reached at the root's turn and are below degree R now (degrees only grow,
+// so a node dropped here could not be chosen later).  Roots left with no key
+// are queued for the scan over all nodes.
+__global__ __launch_bounds__(256) void k_root_lists(const float *__restrict__ X, int64_t ldx, int d,
+                                                    int64_t n, int R, const int32_t *__restrict__ cand,
+                                                    int C, const int32_t *__restrict__ roots, int32_t b0,
+                                                    int32_t b1, const int32_t *__restrict__ tt,
+                                                    const int32_t *__restrict__ deg,
+                                                    uint64_t *__restrict__ keys,
+                                                    int32_t *__restrict__ empty, ConnState *cs) {
+    const int lane = lane_id();
+    const int32_t b = b0 + (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+    if (b >= b1) return;
+    const int32_t r = roots[b];
+    uint64_t key = KEY_INF;
+    if (lane < C) {
+        const int32_t p = cand[(int64_t)r * C + lane];
+        if (p >= 0 && p < n && p != r && tt[p] <= b && deg[p] < R)
+            key = pack_key(dist_chain(X + (int64_t)r * ldx, X + (int64_t)p * ldx, d), p);
+    }
+    int pay = 0;
+    wave_sort(key, pay);
+    if (lane < C) keys[(int64_t)(b - b0) * C + lane] = key;
+    const uint64_t first = shfl64(key, 0);
+    if (lane == 0 && first == KEY_INF) empty[atomicAdd(&cs->n_empty, 1)] = b;
+}
+
+// For each queued root b = empty[q]: the smallest (d2, p) over all nodes p
+// that count as reached at its turn and are below degree R now, into slot 0 of
+// its key list.  A block covers 256 nodes and GQ queued roots; each thread
+// keeps the canonical distance chains of its node to those roots.
+__global__ __launch_bounds__(256) void k_global_nearest(const float *__restrict__ X, int64_t ldx, int d,
+                                                        int64_t n, int R, const int32_t *__restrict__ roots,
+                                                        const int32_t *__restrict__ tt,
+                                                        const int32_t *__restrict__ deg,
+                                                        const int32_t *__restrict__ empty, int32_t n_empty,
+                                                        int32_t b0, uint64_t *keys, int C) {
+    __shared__ unsigned long long red[4][GQ];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int q0 = (int)blockIdx.y * GQ;
+    const int nq = min(GQ, n_empty - q0);
+    int32_t rq[GQ];
+    float acc[GQ];
+#pragma unroll
+    for (int q = 0; q < GQ; ++q) {
+        rq[q] = q < nq ? roots[empty[q0 + q]] : 0;
+        acc[q] = 0.f;
+    }
+    const int64_t pc = p < n ? p : n - 1;
+    const float *xp = X + pc * ldx;
+    for (int k = 0; k < d; k += 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(xp + k);
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+            if (q < nq) {
+                const float4 y = *reinterpret_cast<const float4 *>(X + (int64_t)rq[q] * ldx + k);
+                float t;
+                t = x.x - y.x;
+                acc[q] = fmaf(t, t, acc[q]);
+                t = x.y - y.y;
+                acc[q] = fmaf(t, t, acc[q]);
+                t = x.z - y.z;
+                acc[q] = fmaf(t, t, acc[q]);
+                t = x.w - y.w;
+                acc[q] = fmaf(t, t, acc[q]);
+            }
+        }
+    }
+    const int32_t tp = p < n ? tt[p] : INT32_MAX;
+    const bool free_p = p < n && deg[p] < R;
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < GQ; ++q) {
+        uint64_t key = KEY_INF;
+        if (q < nq && free_p && tp <= empty[q0 + q]) key = pack_key(acc[q], (int32_t)p);
 #pragma unroll
         for (int o = 1; o < PG_WAVE; o <<= 1) {
             const uint64_t t = shfl_xor64(key, o);
             key = t < key ? t : key;
         }
-        if (key == KEY_INF) {
-            if (lane == 0) {
-                cs->idx = idx;
-                cs->first_unreached = r;
+        if (lane_id() == 0) red[wv][q] = key;
+    }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        unsigned long long m = red[0][threadIdx.x];
+        for (int w = 1; w < 4; ++w) m = red[w][threadIdx.x] < m ? red[w][threadIdx.x] : m;
+        if (m != KEY_INF) atomicMin((unsigned long long *)&keys[(int64_t)(empty[q0 + threadIdx.x] - b0) * C], m);
+    }
+}
+
+// Roots in turn order, MATCH_STEP at a time: each takes the first key of its
+// list whose node is still below degree R and appends the edge p -> r there.
+// Degrees are read once per step (after the previous step's atomics have
+// landed) and corrected by the picks made earlier in the same step.  A root
+// whose list has no such node stops the wave; the host then runs the exact
+// scan over all nodes for it and restarts the wave after it.
+__global__ __launch_bounds__(64) void k_match(const int32_t *__restrict__ roots, int32_t b0, int32_t b1,
+                                              const uint64_t *__restrict__ keys, int C, int R, int32_t *g,
+                                              float *gd, int32_t *deg, ConnState *cs) {
+    const int lane = lane_id();
+    for (int32_t b = cs->idx; b < b1; b += MATCH_STEP) {
+        uint64_t kk[MATCH_STEP];
+        int32_t dv[MATCH_STEP], pick[MATCH_STEP];
+#pragma unroll
+        for (int k = 0; k < MATCH_STEP; ++k)
+            kk[k] = (lane < C && b + k < b1) ? keys[(int64_t)(b + k - b0) * C + lane] : KEY_INF;
+#pragma unroll
+        for (int k = 0; k < MATCH_STEP; ++k) dv[k] = kk[k] != KEY_INF ? ld_fresh(&deg[key_id(kk[k])]) : R;
+#pragma unroll
+        for (int k = 0; k < MATCH_STEP; ++k) {
+            pick[k] = -1;
+            if (b + k < b1) {
+                const int32_t pk = kk[k] != KEY_INF ? key_id(kk[k]) : -1;
+                int cur = dv[k];
+#pragma unroll
+                for (int j = 0; j < k; ++j) cur += (pk == pick[j]) ? 1 : 0;
+                const uint64_t ok = __ballot(pk >= 0 && cur < R);
+                if (ok == 0) {
+                    __threadfence();
+                    if (lane == 0) {
+                        cs->idx = b + k;
+                        cs->stop_root = roots[b + k];
+                        cs->stop_turn = b + k + 1;
+                    }
+                    return;
+                }
+                const int f = __ffsll((long long)ok) - 1;
+                const int32_t pp = __shfl(pk, f, PG_WAVE);
+                const int slot = __shfl(cur, f, PG_WAVE);
+                const uint64_t key = shfl64(kk[k], f);
+                pick[k] = pp;
+                if (lane == 0) {
+                    g[(int64_t)pp * R + slot] = roots[b + k];
+                    gd[(int64_t)pp * R + slot] = key_d2(key);
+                    atomicAdd(&deg[pp], 1);
+                }
             }
-            return;
-        }
-        const int32_t p = key_id(key);
-        if (lane == 0) {
-            const int j = ld_fresh(&deg[p]);
-            g[(int64_t)p * R + j] = r;
-            gd[(int64_t)p * R + j] = key_d2(key);
-            deg[p] = j + 1;
-            roots[cs->n_roots] = r;
-            cs->n_roots += 1;
-            visited[r] = 1;
-            queue[0] = r;
         }
         __threadfence();
-        int head = 0, tail = 1;
-        while (head < tail) {
-            if (tail - head > CONNECT_WAVE_BFS) {
-                if (lane == 0) {
-                    cs->idx = idx + 1;
-                    cs->bfs_head = head;
-                    cs->bfs_tail = tail;
-                    cs->first_unreached = -1;
-                }
-                return;
-            }
-            const int32_t x = ld_fresh(&queue[head]);
-            ++head;
-            const int dx = min(ld_fresh(&deg[x]), R);
-            bool push = false;
-            int32_t y = -1;
-            if (lane < dx) {
-                y = ld_fresh(&g[(int64_t)x * R + lane]);
-                if (y >= 0 && y < n && atomicExch(&visited[y], 1) == 0) push = true;
-            }
-            const uint64_t m = __ballot(push);
-            if (push) queue[tail + __popcll(m & lanemask_lt())] = y;
-            tail += __popcll(m);
-            __threadfence();
-        }
     }
     if (lane == 0) {
-        cs->idx = nu;
-        cs->first_unreached = -1;
+        cs->idx = b1;
+        cs->stop_root = -1;
     }
 }
 
 __global__ void k_bfs_seed(int32_t *__restrict__ visited, int32_t *__restrict__ frontier,
-                           ConnState *__restrict__ cs, const int32_t *__restrict__ src_dev, int32_t src) {
-    const int32_t r = src_dev ? *src_dev : src;
+                           ConnState *__restrict__ cs, const int32_t *__restrict__ src) {
+    const int32_t r = *src;
     visited[r] = 1;
     frontier[0] = r;
     cs->fcount[0] = 1;
@@ -453,15 +604,16 @@ __global__ __launch_bounds__(256) void k_bfs_step(const int32_t *__restrict__ g,
     if (push) fout[base + __popcll(m & lanemask_lt())] = y;
 }
 
-__global__ __launch_bounds__(256) void k_nearest_reached(const float *__restrict__ X, int64_t ldx,
-                                                         int d, int64_t n, int R,
-                                                         const int32_t *__restrict__ visited,
-                                                         const int32_t *__restrict__ deg,
-                                                         ConnState *__restrict__ cs) {
+// exact scan for the stopped root: nearest node reached at its turn and below
+// degree R now
+__global__ __launch_bounds__(256) void k_nearest_at(const float *__restrict__ X, int64_t ldx, int d,
+                                                    int64_t n, int R, const int32_t *__restrict__ tt,
+                                                    const int32_t *__restrict__ deg,
+                                                    ConnState *__restrict__ cs) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t r = cs->first_unreached;
+    const int32_t r = cs->stop_root, turn = cs->stop_turn;
     uint64_t key = KEY_INF;
-    if (p < n && visited[p] && deg[p] < R)
+    if (p < n && tt[p] < turn && deg[p] < R)
         key = pack_key(dist_chain(X + (int64_t)r * ldx, X + p * ldx, d), (int32_t)p);
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) {
@@ -472,8 +624,8 @@ __global__ __launch_bounds__(256) void k_nearest_reached(const float *__restrict
 }
 
 __global__ void k_attach(int32_t *__restrict__ g, float *__restrict__ gd, int32_t *__restrict__ deg,
-                         int R, int32_t *__restrict__ roots, ConnState *__restrict__ cs) {
-    const int32_t r = cs->first_unreached;
+                         int R, ConnState *__restrict__ cs) {
+    const int32_t r = cs->stop_root;
     const unsigned long long key = cs->nearest;
     if (key == KEY_INF) {
         cs->overflow = 1;
@@ -484,27 +636,15 @@ __global__ void k_attach(int32_t *__restrict__ g, float *__restrict__ gd, int32_
     g[(int64_t)p * R + j] = r;
     gd[(int64_t)p * R + j] = key_d2(key);
     deg[p] = j + 1;
-    if (roots) roots[cs->n_roots] = r;
-    cs->n_roots += 1;
-}
-
-__global__ void k_copy_graph(const int32_t *__restrict__ si, const float *__restrict__ sd,
-                             const int32_t *__restrict__ sdeg, int64_t n, int R,
-                             int32_t *__restrict__ di, float *__restrict__ dd,
-                             int32_t *__restrict__ ddeg) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * R) return;
-    di[i] = si[i];
-    dd[i] = sd[i];
-    if (i % R == 0) ddeg[i / R] = sdeg[i / R];
+    cs->idx = cs->stop_turn;  // the next root
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 struct PruneLayout {
-    size_t p_ids, p_d2, p_deg, cnt, off, rev, visited, fa, fb, cs, cpart, cen, apd, api, scan_tmp,
-        total;
+    size_t p_ids, p_d2, p_deg, cnt, off, rev, visited, fa, fb, cs, keys, empty, cpart, cen, apd, api,
+        scan_tmp, total;
     int64_t ncb, nab;
 };
 
@@ -529,6 +669,9 @@ static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d_max) 
     L.fa = take(sizeof(int32_t) * n);
     L.fb = take(sizeof(int32_t) * n);
     L.cs = take(sizeof(ConnState));
+    const int64_t nb = std::min<int64_t>(n, CONNECT_BATCH);
+    L.keys = take(sizeof(uint64_t) * 64 * nb);
+    L.empty = take(sizeof(int32_t) * nb);
     L.cpart = take(sizeof(double) * L.ncb * d_max);
     L.cen = take(sizeof(double) * d_max);
     L.apd = take(sizeof(double) * L.nab);
@@ -573,22 +716,14 @@ static pg_status check_prune(const pg_prune_params *p, int64_t n, int32_t C) {
     return PG_OK;
 }
 
-// Level-synchronous BFS over out-edges.  With src_dev or src >= 0 the
-// search starts there; otherwise from the nin0 nodes already queued at fin0
-// (and already marked).
+// Level-synchronous BFS over out-edges from the node *src (device).
 static pg_status bfs_from(pg_ctx *ctx, const int32_t *g, int64_t n, int R, const int32_t *deg, int32_t *visited,
-                          int32_t *fa, int32_t *fb, ConnState *cs, const int32_t *src_dev, int32_t src,
-                          int32_t *fin0 = nullptr, int32_t nin0 = 0) {
+                          int32_t *fa, int32_t *fb, ConnState *cs, const int32_t *src) {
     hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, st, visited, fa, cs, src);
+    PG_HIP(hipGetLastError());
     int32_t nin = 1;
     int32_t *fin = fa, *fout = fb;
-    if (fin0) {
-        nin = nin0;
-        fin = fin0;
-    } else {
-        hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, st, visited, fa, cs, src_dev, src);
-        PG_HIP(hipGetLastError());
-    }
     int parity = 0;
     while (nin > 0) {
         PG_HIP(hipMemsetAsync(&cs->fcount[parity ^ 1], 0, sizeof(int32_t), st));
@@ -602,6 +737,107 @@ static pg_status bfs_from(pg_ctx *ctx, const int32_t *g, int64_t n, int R, const
         fout = (fout == fb) ? fa : fb;
         parity ^= 1;
     }
+    return PG_OK;
+}
+
+template <typename T>
+static pg_status read_back(pg_ctx *ctx, T *host, const T *dev) {
+    PG_HIP(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+    PG_HIP(hipStreamSynchronize(ctx->stream));
+    return PG_OK;
+}
+
+template <typename T>
+static pg_status write_to(pg_ctx *ctx, T *dev, T value) {
+    PG_HIP(hipMemcpyAsync(dev, &value, sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    PG_HIP(hipStreamSynchronize(ctx->stream));
+    return PG_OK;
+}
+
+// The connect step (see the comment above ConnState).
+static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float *X, int64_t n, int d,
+                         int64_t ldx, const int32_t *cand, int C, int R, int32_t *g_ids, float *g_d2,
+                         int32_t *g_deg, const int32_t *ep, int32_t *roots, int32_t *n_roots) {
+    hipStream_t st = ctx->stream;
+    int32_t *cnt = (int32_t *)(w + L.cnt), *U = (int32_t *)(w + L.rev), *visited = (int32_t *)(w + L.visited),
+            *fa = (int32_t *)(w + L.fa), *fb = (int32_t *)(w + L.fb), *empty = (int32_t *)(w + L.empty);
+    int64_t *off = (int64_t *)(w + L.off);
+    uint64_t *keys = (uint64_t *)(w + L.keys);
+    ConnState *cs = (ConnState *)(w + L.cs);
+    int32_t *rts = roots ? roots : (int32_t *)(w + L.p_ids);
+    const unsigned nbn = (unsigned)((n + 255) / 256);
+
+    PG_HIP(hipMemsetAsync(visited, 0, sizeof(int32_t) * n, st));
+    PG_HIP(hipMemsetAsync(cs, 0, sizeof(ConnState), st));
+    PG_TRY(bfs_from(ctx, g_ids, n, R, g_deg, visited, fa, fb, cs, ep));
+    // unreached ids in increasing order
+    hipLaunchKernelGGL(k_flag_unreached, dim3(nbn), dim3(256), 0, st, visited, n, cnt);
+    PG_TRY(scan_exclusive(ctx, cnt, off, n, w + L.scan_tmp));
+    hipLaunchKernelGGL(k_scatter_unreached, dim3(nbn), dim3(256), 0, st, visited, n, off, U);
+    PG_HIP(hipGetLastError());
+    int64_t nu64 = 0;
+    PG_TRY(read_back(ctx, &nu64, off + n));
+    const int32_t nu = (int32_t)nu64;
+    if (nu == 0) return PG_OK;
+
+    // min-ancestor labels (fa), roots and reach turns (fb)
+    int32_t *lab = fa, *tt = fb;
+    const unsigned nbu = (unsigned)((nu + 255) / 256);
+    hipLaunchKernelGGL(k_label_init, dim3(nbu), dim3(256), 0, st, U, nu, lab);
+    PG_HIP(hipGetLastError());
+    for (;;) {
+        PG_HIP(hipMemsetAsync(&cs->changed, 0, sizeof(int32_t), st));
+        const int64_t threads = (int64_t)nu * R;
+        hipLaunchKernelGGL(k_label_round, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, g_ids, g_deg,
+                           R, n, visited, U, nu, lab, &cs->changed);
+        PG_HIP(hipGetLastError());
+        int32_t ch = 0;
+        PG_TRY(read_back(ctx, &ch, &cs->changed));
+        if (!ch) break;
+    }
+    hipLaunchKernelGGL(k_flag_roots, dim3(nbu), dim3(256), 0, st, U, nu, lab, cnt);
+    PG_TRY(scan_exclusive(ctx, cnt, off, nu, w + L.scan_tmp));
+    PG_HIP(hipMemsetAsync(tt, 0, sizeof(int32_t) * n, st));
+    hipLaunchKernelGGL(k_scatter_roots, dim3(nbu), dim3(256), 0, st, U, nu, lab, off, rts, tt);
+    hipLaunchKernelGGL(k_reach_time, dim3(nbu), dim3(256), 0, st, U, nu, lab, tt);
+    PG_HIP(hipGetLastError());
+    int64_t m64 = 0;
+    PG_TRY(read_back(ctx, &m64, off + nu));
+    const int32_t m = (int32_t)m64;
+
+    for (int32_t b0 = 0; b0 < m; b0 += CONNECT_BATCH) {
+        const int32_t b1 = std::min<int32_t>(m, b0 + CONNECT_BATCH);
+        PG_HIP(hipMemsetAsync(&cs->n_empty, 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_root_lists, dim3((unsigned)((b1 - b0 + 3) / 4)), dim3(256), 0, st, X, ldx, d, n, R,
+                           cand, C, rts, b0, b1, tt, g_deg, keys, empty, cs);
+        PG_HIP(hipGetLastError());
+        int32_t ne = 0;
+        PG_TRY(read_back(ctx, &ne, &cs->n_empty));
+        if (ne > 0) {
+            hipLaunchKernelGGL(k_global_nearest, dim3(nbn, (unsigned)((ne + GQ - 1) / GQ)), dim3(256), 0, st, X,
+                               ldx, d, n, R, rts, tt, g_deg, empty, ne, b0, keys, C);
+            PG_HIP(hipGetLastError());
+        }
+        PG_TRY(write_to(ctx, &cs->idx, b0));
+        for (;;) {
+            hipLaunchKernelGGL(k_match, dim3(1), dim3(64), 0, st, rts, b0, b1, keys, C, R, g_ids, g_d2, g_deg, cs);
+            PG_HIP(hipGetLastError());
+            int32_t stop = -1;
+            PG_TRY(read_back(ctx, &stop, &cs->stop_root));
+            if (stop < 0) break;
+            PG_TRY(write_to(ctx, &cs->nearest, (unsigned long long)KEY_INF));
+            hipLaunchKernelGGL(k_nearest_at, dim3(nbn), dim3(256), 0, st, X, ldx, d, n, R, tt, g_deg, cs);
+            hipLaunchKernelGGL(k_attach, dim3(1), dim3(1), 0, st, g_ids, g_d2, g_deg, R, cs);
+            PG_HIP(hipGetLastError());
+            int32_t ovf = 0;
+            PG_TRY(read_back(ctx, &ovf, &cs->overflow));
+            if (ovf) {
+                set_error("pg_prune: connect found every reachable node at degree R=%d", R);
+                return PG_EOVERFLOW;
+            }
+        }
+    }
+    if (n_roots) *n_roots = m;
     return PG_OK;
 }
 
@@ -691,60 +927,8 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
     PG_HIP(hipGetLastError());
     if (n_roots) *n_roots = 0;
     if (p->stages & PG_STAGE_CONNECT) {
-        PG_HIP(hipMemsetAsync(visited, 0, sizeof(int32_t) * n, st));
-        PG_HIP(hipMemsetAsync(cs, 0, sizeof(ConnState), st));
-        PG_TRY(bfs_from(ctx, g_ids, n, R, g_deg, visited, fa, fb, cs, ep, 0));
-        const unsigned nb = (unsigned)((n + 255) / 256);
-        // unreached ids in increasing order
-        hipLaunchKernelGGL(k_flag_unreached, dim3(nb), dim3(256), 0, st, visited, n, cnt);
-        PG_TRY(scan_exclusive(ctx, cnt, off, n, w + L.scan_tmp));
-        hipLaunchKernelGGL(k_scatter_unreached, dim3(nb), dim3(256), 0, st, visited, n, off, rev);
-        PG_HIP(hipGetLastError());
-        int64_t nu64 = 0;
-        PG_HIP(hipMemcpyAsync(&nu64, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        PG_HIP(hipStreamSynchronize(st));
-        const int32_t nu = (int32_t)nu64;
-        for (int64_t restart = 0; nu > 0; ++restart) {
-            hipLaunchKernelGGL(k_connect_loop, dim3(1), dim3(64), 0, st, X, ldx, d, n, R, cand_ids, C,
-                               g_ids, g_d2, g_deg, visited, rev, nu, fa, roots ? roots : fb, cs);
-            PG_HIP(hipGetLastError());
-            ConnState h;
-            PG_HIP(hipMemcpyAsync(&h, cs, sizeof(h), hipMemcpyDeviceToHost, st));
-            PG_HIP(hipStreamSynchronize(st));
-            if (h.bfs_head > 0) {
-                // a large component: finish its BFS level-synchronously, then resume
-                const int32_t hb = h.bfs_head, tb = h.bfs_tail;
-                const int32_t zero2[2] = {0, 0};
-                PG_HIP(hipMemcpyAsync(&cs->bfs_head, zero2, sizeof(zero2), hipMemcpyHostToDevice, st));
-                PG_TRY(bfs_from(ctx, g_ids, n, R, g_deg, visited, fa + tb, fb, cs, nullptr, -1, fa + hb,
-                                tb - hb));
-                continue;
-            }
-            if (h.idx >= nu) break;
-            // no candidate of r qualifies: nearest reached node over all of X
-            const unsigned long long inf = KEY_INF;
-            PG_HIP(hipMemcpyAsync(&cs->nearest, &inf, sizeof(inf), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(k_nearest_reached, dim3(nb), dim3(256), 0, st, X, ldx, d, n, R, visited,
-                               g_deg, cs);
-            hipLaunchKernelGGL(k_attach, dim3(1), dim3(1), 0, st, g_ids, g_d2, g_deg, R, roots, cs);
-            PG_HIP(hipGetLastError());
-            int32_t ovf = 0;
-            PG_HIP(hipMemcpyAsync(&ovf, &cs->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            PG_HIP(hipStreamSynchronize(st));
-            if (ovf) {
-                set_error("pg_prune: connect found every reachable node at degree R=%d", R);
-                return PG_EOVERFLOW;
-            }
-            PG_TRY(bfs_from(ctx, g_ids, n, R, g_deg, visited, fa, fb, cs, &cs->first_unreached, 0));
-            const int32_t next = h.idx + 1;
-            PG_HIP(hipMemcpyAsync(&cs->idx, &next, sizeof(int32_t), hipMemcpyHostToDevice, st));
-        }
-        if (n_roots) {
-            int32_t nr = 0;
-            PG_HIP(hipMemcpyAsync(&nr, &cs->n_roots, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            PG_HIP(hipStreamSynchronize(st));
-            *n_roots = nr;
-        }
+        TimedLaunch tl(ctx, K_CONNECT, -1.0);
+        PG_TRY(connect(ctx, L, w, X, n, d, ldx, cand_ids, C, R, g_ids, g_d2, g_deg, ep, roots, n_roots));
     }
     return PG_OK;
 }

@@ -177,6 +177,33 @@ def test_full_refine_bit_exact(pg, oracle, datagen):
     assert len(r["roots"]) > 0
 
 
+@pytest.mark.parametrize("nn,d,nc,sigma,C,R,seed", [
+    (1200, 16, 12, 4.0, 10, 3, 14),   # small R: many candidates saturate, exact scans
+    (2500, 8, 40, 1.5, 6, 4, 21),     # many tight clusters: roots with no reached candidate
+])
+def test_connect_saturation_bit_exact(pg, oracle, datagen, nn, d, nc, sigma, C, R, seed):
+    X, _ = datagen.sift_like(nn, 0, d=d, n_clusters=nc, sigma=sigma, seed=seed)
+    cand = _exact_lists(oracle, X, C)
+    g = pg.prune(dev(X), dev(cand), R)
+    r = oracle.refine(X, cand, R)
+    log("roots gpu", len(g["roots"]), "oracle", len(r["roots"]))
+    assert len(r["roots"]) > 20
+    assert np.array_equal(host(g["roots"]), r["roots"])
+    assert np.array_equal(host(g["deg"]), r["deg"])
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert np.array_equal(host(g["d2"]), r["d2"].astype(np.float32))
+
+
+def test_connect_overflow_is_reported(pg, oracle, datagen):
+    # R = 2 on tight clusters: at some turn every reached node has degree R
+    X, _ = datagen.sift_like(1500, 0, d=8, n_clusters=30, sigma=2.0, seed=15)
+    cand = _exact_lists(oracle, X, 6)
+    with pytest.raises(RuntimeError):
+        oracle.refine(X, cand, 2)
+    with pytest.raises(pg.PgError, match="degree"):
+        pg.prune(dev(X), dev(cand), 2)
+
+
 def test_prune_table_hook_float_bit_exact(pg, oracle, datagen):
     # identical candidate lists and identical float32 distances -> identical edges
     X, _ = datagen.unit_mixture(400, 0, d=16, n_clusters=5, seed=6)
