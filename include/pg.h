@@ -120,8 +120,8 @@ typedef struct {
     uint64_t seed;
     int32_t precision;    /* pg_precision of the join tiles */
     float margin_rel;     /* reserved (must be 0) */
-    int32_t bucket_cap;   /* proposal slots per node per pass (>= 2K); 0 = default */
-    int32_t chunks;       /* source passes in the first iteration; 0 = default */
+    int32_t bucket_cap;   /* proposal slots per node per pass (>= 2K); 0 = 8K */
+    int32_t chunks;       /* source passes in the first iteration (<= 64); 0 = 64 */
 } pg_knn_params;
 
 typedef struct {

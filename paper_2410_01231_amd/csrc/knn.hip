@@ -30,6 +30,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "pg_common.h"
@@ -371,14 +372,16 @@ __global__ __launch_bounds__(JT) void k_join(
     const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
     int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
     int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t spill_cap,
-    uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, int64_t u0, int64_t u1,
-    int maxm, unsigned long long *__restrict__ counters) {
+    uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, const int32_t *__restrict__ order,
+    int64_t n, PassRange pr, int maxm, unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int MPS = join_mps(maxm);
     const int lane = lane_id();
     const int wv = threadIdx.x / PG_WAVE;
-    const int64_t u = u0 + (int64_t)blockIdx.x * JW + wv;
-    if (u >= u1) return;
+    const int64_t nlog = (pr.items + JW - 1) / JW;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nlog);
+    const int64_t u = lb < nlog ? pass_source(order, n, pr, lb * JW + wv) : -1;
+    if (u < 0) return;
     unsigned char *region = smem + (size_t)wv * join_wave_lds(maxm);
     float *tile = reinterpret_cast<float *>(region);
     uint64_t *kth = reinterpret_cast<uint64_t *>(tile + (size_t)JDC * MPS);
@@ -618,31 +621,48 @@ __device__ __forceinline__ mf_f32x16 gram_tile(const float *__restrict__ X, int6
     mf_f32x16 acc;
 #pragma unroll
     for (int g = 0; g < 16; ++g) acc[g] = 0.f;
+    // Operands are loaded in batches of GK k-steps before their MFMAs, so a
+    // tile waits for memory once per batch instead of once per step.
     if (P == PG_FP32) {
         // float4 chunk t: lane half h takes dims 4t+2h and 4t+2h+1 in two steps
+        constexpr int GK = 16;
         const float *ra = X + (int64_t)rid * ldx + 2 * h;
         const float *ca = X + (int64_t)cid * ldx + 2 * h;
-        for (int t = 0; t < d; t += 4) {
-            const float2 a = *reinterpret_cast<const float2 *>(ra + t);
-            const float2 b = *reinterpret_cast<const float2 *>(ca + t);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
-        }
-    } else if (P == PG_FP16) {
-        const _Float16 *ra = reinterpret_cast<const _Float16 *>(X16) + (int64_t)rid * d16 + 8 * h;
-        const _Float16 *ca = reinterpret_cast<const _Float16 *>(X16) + (int64_t)cid * d16 + 8 * h;
-        for (int t = 0; t < d16; t += 16) {
-            const mf_f16x8 a = *reinterpret_cast<const mf_f16x8 *>(ra + t);
-            const mf_f16x8 b = *reinterpret_cast<const mf_f16x8 *>(ca + t);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+        for (int t0 = 0; t0 < d; t0 += 4 * GK) {
+            float2 a[GK], b[GK];
+#pragma unroll
+            for (int j = 0; j < GK; ++j) {
+                const bool in = t0 + 4 * j < d;
+                a[j] = in ? *reinterpret_cast<const float2 *>(ra + t0 + 4 * j) : make_float2(0.f, 0.f);
+                b[j] = in ? *reinterpret_cast<const float2 *>(ca + t0 + 4 * j) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < GK; ++j) {
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j].x, b[j].x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j].y, b[j].y, acc, 0, 0, 0);
+            }
         }
     } else {
-        const __bf16 *ra = reinterpret_cast<const __bf16 *>(X16) + (int64_t)rid * d16 + 8 * h;
-        const __bf16 *ca = reinterpret_cast<const __bf16 *>(X16) + (int64_t)cid * d16 + 8 * h;
-        for (int t = 0; t < d16; t += 16) {
-            const mf_bf16x8 a = *reinterpret_cast<const mf_bf16x8 *>(ra + t);
-            const mf_bf16x8 b = *reinterpret_cast<const mf_bf16x8 *>(ca + t);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        constexpr int GK = 8;
+        typedef typename std::conditional<P == PG_FP16, mf_f16x8, mf_bf16x8>::type vec8;
+        typedef typename std::conditional<P == PG_FP16, _Float16, __bf16>::type elem;
+        const elem *ra = reinterpret_cast<const elem *>(X16) + (int64_t)rid * d16 + 8 * h;
+        const elem *ca = reinterpret_cast<const elem *>(X16) + (int64_t)cid * d16 + 8 * h;
+        for (int t0 = 0; t0 < d16; t0 += 16 * GK) {
+            vec8 a[GK], b[GK];
+#pragma unroll
+            for (int j = 0; j < GK; ++j) {
+                const bool in = t0 + 16 * j < d16;
+                a[j] = in ? *reinterpret_cast<const vec8 *>(ra + t0 + 16 * j) : vec8{};
+                b[j] = in ? *reinterpret_cast<const vec8 *>(ca + t0 + 16 * j) : vec8{};
+            }
+#pragma unroll
+            for (int j = 0; j < GK; ++j) {
+                if (P == PG_FP16)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[j], b[j], acc, 0, 0, 0);
+                else
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[j], acc, 0, 0, 0);
+            }
         }
     }
     return acc;
@@ -664,14 +684,16 @@ __global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
     const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
     int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
     int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t spill_cap,
-    uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, int64_t u0, int64_t u1,
-    int maxm, unsigned long long *__restrict__ counters) {
+    uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, const int32_t *__restrict__ order,
+    int64_t n, PassRange pr, int maxm, unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int MPS = (maxm + 31) / 32 * 32;
     const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
     const int wv = threadIdx.x / PG_WAVE;
-    const int64_t u = u0 + (int64_t)blockIdx.x * MW + wv;
-    if (u >= u1) return;
+    const int64_t nlog = (pr.items + MW - 1) / MW;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nlog);
+    const int64_t u = lb < nlog ? pass_source(order, n, pr, lb * MW + wv) : -1;
+    if (u < 0) return;
     unsigned char *region = smem + (size_t)wv * MPS * (8 + 8 + 4 + 4 + 4 + 4 + 4);
     uint64_t *kth = reinterpret_cast<uint64_t *>(region);
     int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
@@ -984,17 +1006,35 @@ __global__ __launch_bounds__(256) void k_exact_knn(const float *__restrict__ X, 
 }
 
 // ---------------------------------------------------------------------------
+// locality order of the join sources: nodes grouped by their nearest pivot
+// (pivots = every step-th row), so that sources sharing join-set members run
+// close together in time.  Any order gives the same lists.
+// ---------------------------------------------------------------------------
+__global__ void k_iota(int32_t *__restrict__ order, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) order[i] = (int32_t)i;
+}
+
+__global__ void k_order_scatter(const int32_t *__restrict__ piv, int64_t n, const int64_t *__restrict__ off,
+                                int32_t *__restrict__ cur, int32_t *__restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g = piv[i];
+    order[off[g] + atomicAdd(&cur[g], 1)] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 struct KnnLayout {
     size_t keys, newm, insm, nf, nf_c, of, of_c, rn_cnt, ro_cnt, rn_off, ro_off, rn_list, ro_list,
         jn, jn_c, jo, jo_c, pcnt, bucket, mark, mark_next, counters, scan_tmp, spill_t, spill_k,
-        spill_s, x16, norms, exflags, total;
+        spill_s, x16, norms, exflags, order, total;
     int B, JN, JO, d16;
     int64_t spill_cap;
 };
 
-static int default_bucket(int K) { return 4 * K; }
+static int default_bucket(int K) { return 8 * K; }
 
 static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d) {
     KnnLayout L{};
@@ -1040,6 +1080,7 @@ static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d) {
     L.x16 = take(half ? (size_t)2 * n * L.d16 : 0);
     L.norms = take(sizeof(float) * n);
     L.exflags = take(sizeof(unsigned int) * 4);
+    L.order = take(sizeof(int32_t) * n);
     L.total = o;
     return L;
 }
@@ -1226,6 +1267,27 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         }
     }
     if (stats) stats->join_path = path;
+    // ---- locality order of the join sources (nearest of P pivot rows)
+    int32_t *order = (int32_t *)(w + L.order);
+    {
+        const int64_t P = std::min<int64_t>(1024, n / 4096);
+        if (P <= 1) {
+            hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, order, n);
+        } else {
+            const int64_t step = n / P;
+            int32_t *piv = jn;          // free until the first iteration
+            float *pd2 = (float *)jo;
+            PG_TRY(launch_exact(ctx, X, P, d, step * ldx, X, n, ldx, nullptr, 0, 1, piv, pd2));
+            PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * P, st));
+            hipLaunchKernelGGL(k_spill_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, piv, n,
+                               rn_cnt);
+            PG_TRY(scan_exclusive(ctx, rn_cnt, rn_off, P, scan_tmp));
+            PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * P, st));
+            hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, piv, n,
+                               rn_off, rn_cnt, order);
+        }
+        PG_HIP(hipGetLastError());
+    }
     const int maxm = 3 * S + K;
     const size_t lds = path == PG_JOIN_VALU ? join_lds_bytes(maxm) : join_mfma_lds_bytes(maxm);
     int iters = 0;
@@ -1251,59 +1313,60 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                            (uint64_t)(3 * t + 1), (uint64_t)(3 * t + 2), nf, nf_c, of, of_c, rn_off,
                            rn_list, ro_off, ro_list, jn, jn_c, L.JN, jo, jo_c, L.JO, counters);
         PG_HIP(hipGetLastError());
-        // source passes: many in the first iteration (random lists accept almost
-        // every proposal), fewer once the lists are good; the count never
-        // changes the result
-        // pass sizes n/c, n/c, 2n/c, 4n/c, ...: each merge tightens every K-th
-        // key, so later (larger) passes emit fewer proposals.  c grows with the
-        // proposals the previous iteration emitted (many passes while the
-        // lists are still poor); it never changes the result.
-        std::vector<int64_t> bounds{0};
+        // Source passes: residue classes of the order positions mod 64, sized
+        // r, r, 2r, 4r, ... (r = 64 / c).  Each merge tightens every K-th key,
+        // so later (larger) passes emit fewer proposals; c grows with the
+        // proposals of the previous iteration.  The passes never change the
+        // result.
+        std::vector<int> rbnd{0};
         {
             int64_t c0;
             if (prev_props < 0)
-                c0 = p->chunks > 0 ? p->chunks : 64;
+                c0 = p->chunks > 0 ? std::min(p->chunks, PG_PASS_PERIOD) : PG_PASS_PERIOD;
             else
                 c0 = (int64_t)std::min<double>(
-                    64.0, std::max<double>(1.0, std::ceil(4.0 * (double)prev_props / ((double)L.B * n))));
-            int64_t sz = std::max<int64_t>(1, n / c0), at = 0;
+                    PG_PASS_PERIOD,
+                    std::max<double>(1.0, std::ceil(4.0 * (double)prev_props / ((double)L.B * n))));
+            int sz = std::max<int>(1, PG_PASS_PERIOD / (int)c0), at = 0;
             bool first = true;
-            while (at < n) {
-                at = std::min<int64_t>(n, at + sz);
-                bounds.push_back(at);
+            while (at < PG_PASS_PERIOD) {
+                at = std::min(PG_PASS_PERIOD, at + sz);
+                rbnd.push_back(at);
                 if (!first) sz *= 2;
                 first = false;
             }
         }
-        for (size_t ci = 0; ci + 1 < bounds.size(); ++ci) {
-            const int64_t u0 = bounds[ci];
-            const int64_t cnt = bounds[ci + 1] - u0;
+        for (size_t ci = 0; ci + 1 < rbnd.size(); ++ci) {
+            PassRange pr;
+            pr.lo = rbnd[ci];
+            pr.w = rbnd[ci + 1] - rbnd[ci];
+            pr.items = (n + PG_PASS_PERIOD - 1) / PG_PASS_PERIOD * pr.w;
             const uint8_t *mk = nullptr;
             for (int attempt = 0;; ++attempt) {
                 {
                     TimedLaunch tl(ctx, K_JOIN, -1.0);
-                    const unsigned mg = (unsigned)((cnt + MW - 1) / MW);
+                    const unsigned mg = xcd_grid((pr.items + MW - 1) / MW);
                     const void *x16 = (const void *)(w + L.x16);
                     if (path == PG_JOIN_VALU)
-                        hipLaunchKernelGGL(k_join, dim3((unsigned)((cnt + JW - 1) / JW)), dim3(JT), lds, st,
+                        hipLaunchKernelGGL(k_join, dim3(xcd_grid((pr.items + JW - 1) / JW)), dim3(JT), lds, st,
                                            X, ldx, d, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt, bucket,
-                                           L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, u0, u0 + cnt,
+                                           L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
                                            maxm, counters);
                     else if (path == PG_JOIN_MFMA_FP32)
                         hipLaunchKernelGGL(k_join_mfma<PG_FP32>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
                                            x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
                                            pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
-                                           u0, u0 + cnt, maxm, counters);
+                                           order, n, pr, maxm, counters);
                     else if (path == PG_JOIN_MFMA_FP16)
                         hipLaunchKernelGGL(k_join_mfma<PG_FP16>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
                                            x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
                                            pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
-                                           u0, u0 + cnt, maxm, counters);
+                                           order, n, pr, maxm, counters);
                     else
                         hipLaunchKernelGGL(k_join_mfma<PG_BF16>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
                                            x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
                                            pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
-                                           u0, u0 + cnt, maxm, counters);
+                                           order, n, pr, maxm, counters);
                     PG_HIP(hipGetLastError());
                 }
                 unsigned long long hc2[C_NCOUNTERS];

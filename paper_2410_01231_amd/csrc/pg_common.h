@@ -178,6 +178,41 @@ __device__ __forceinline__ int wave_count_less(uint64_t sorted, uint64_t x) {
 }
 
 // ---------------------------------------------------------------------------
+// source passes over a locality order, XCD-aware
+//
+// A pass covers the positions p of the order array whose residue p % 64 lies
+// in [lo, lo + w); its items are i = q * w + (r - lo) for p = 64 q + r, so
+// consecutive items are neighbouring positions.  Workgroups of a launch are
+// spread over the 8 XCDs round-robin (workgroup b on XCD b % 8); the logical
+// block of physical block b walks a contiguous range per XCD, so blocks that
+// share an L2 work on neighbouring sources.
+// ---------------------------------------------------------------------------
+constexpr int PG_NXCD = 8;
+constexpr int PG_PASS_PERIOD = 64;
+
+struct PassRange {
+    int lo, w;       // residues [lo, lo + w) of position % PG_PASS_PERIOD
+    int64_t items;   // ceil(n / PG_PASS_PERIOD) * w
+};
+
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nlogical) {
+    const int64_t per = (nlogical + PG_NXCD - 1) / PG_NXCD;
+    return (b % PG_NXCD) * per + b / PG_NXCD;
+}
+
+static inline unsigned xcd_grid(int64_t nlogical) {
+    return (unsigned)(((nlogical + PG_NXCD - 1) / PG_NXCD) * PG_NXCD);
+}
+
+// source node of item i of a pass, or -1 past the end
+__device__ __forceinline__ int64_t pass_source(const int32_t *__restrict__ order, int64_t n, PassRange pr,
+                                               int64_t i) {
+    if (i >= pr.items) return -1;
+    const int64_t p = (i / pr.w) * PG_PASS_PERIOD + pr.lo + (i % pr.w);
+    return p < n ? (int64_t)order[p] : -1;
+}
+
+// ---------------------------------------------------------------------------
 // canonical squared distance (one lane, full vectors, float4 loads)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float dist_chain(const float *__restrict__ a,
