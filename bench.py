@@ -170,7 +170,7 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
     def build():
         ids, d2, st = pg.knn_build(Xd, K, S=S, max_iters=w["iters"], seed=1, delta=0.001,
                                    precision=prec, ctx=ctx)
-        g = pg.prune(Xd, ids, R, ctx=ctx)
+        g = pg.prune(Xd, ids, R, cand_d2=d2, ctx=ctx)
         return ids, st, g
 
     # ---- warm-up and recall calibration (untimed)

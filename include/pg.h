@@ -168,28 +168,44 @@ typedef struct {
                              cand_ids[u][0..C-1]; all distances are read from it */
 } pg_prune_params;
 
-/* Workspace bytes needed by pg_prune (host output). */
-pg_status pg_prune_workspace(const pg_prune_params *p, int64_t n, int32_t C,
+/* Workspace bytes needed by pg_prune for n points of dimension d and C
+ * candidates per point (host output). */
+pg_status pg_prune_workspace(const pg_prune_params *p, int64_t n, int32_t d, int32_t C,
                              size_t *bytes);
 
 /*
+ * Refinement of Alg. 2 (Phase 3) and its entry point.
+ *
  * cand_ids: n x C candidate lists (C <= 64; -1, u itself and repeats are
- * skipped).  Stage PRUNE: N(u) <- Prune(u, C(u), R) for every u (Alg. 3 and,
- * for alpha > 60, the alpha test).  Stage REVERSE: N(u) <- Prune(u, N(u) U
- * {v : u in N(v)}, R), every node reading the PRUNE result.  Entry point:
- * the node closest to the centroid of X (argmin of (d2, id); centroid summed
- * in double).  Stage CONNECT: from ep, while some node is unreachable, the
- * smallest unreachable id r gets the edge p -> r from the reachable node p
- * nearest to r with degree < R; extra edges are appended.
+ * skipped).  cand_d2 (optional, n x C): d2(u, cand_ids[u][j]) as the
+ * canonical FP32 chain computes it (pg_knn_build's knn_d2 qualifies); when
+ * NULL the distances are computed here.  Results are the same either way.
+ *
+ * Stage PRUNE: N(u) <- Prune(u, C(u), R) for every u (Alg. 3 and, for
+ * alpha > 60, the alpha test of Section 4.1).  Stage REVERSE:
+ * N(u) <- Prune(u, N(u) U {v : u in N(v)}, R), every node reading the PRUNE
+ * result.  Entry point: the node closest to the centroid of X (argmin of
+ * (d2, id); centroid summed in double).  Stage CONNECT: with ep as the start,
+ * while some node is unreached, the smallest unreached id r gets the edge
+ * p -> r, where p is the reached node below degree R closest to r among r's
+ * own candidates cand_ids[r], or, when none qualifies, among all reached
+ * nodes; then everything r reaches counts as reached.  Extra edges are
+ * appended after the pruned ones.
+ *
+ * When X holds integers with |x| <= 2048 and squared norms <= 2^23 (tested
+ * on the device), the pairwise distances of PRUNE (given cand_d2) and
+ * REVERSE come from FP16 MFMA Gram tiles, which are exact there.
+ *
  * Outputs: g_ids / g_d2 (n x R, rows padded with -1 / +inf), g_deg (n),
- * ep (1 int), roots (optional, n ints: the restart nodes r in order) and
- * n_roots (host, optional).  PG_EOVERFLOW if CONNECT finds every reachable
- * node already at degree R.
+ * ep (1 int), roots (optional, n ints: the roots r in order) and n_roots
+ * (host, optional).  PG_EOVERFLOW if CONNECT finds every reached node at
+ * degree R.
  */
 pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
-                   const int32_t *cand_ids, int32_t C, const pg_prune_params *p,
-                   void *ws, size_t ws_bytes, int32_t *g_ids, float *g_d2,
-                   int32_t *g_deg, int32_t *ep, int32_t *roots, int32_t *n_roots);
+                   const int32_t *cand_ids, const float *cand_d2, int32_t C,
+                   const pg_prune_params *p, void *ws, size_t ws_bytes, int32_t *g_ids,
+                   float *g_d2, int32_t *g_deg, int32_t *ep, int32_t *roots,
+                   int32_t *n_roots);
 
 /* ------------------------------------------------------------------ */
 /* Beam search (Alg. 1)                                                */

@@ -34,10 +34,13 @@ __device__ __forceinline__ bool occludes(float a, float b, float c, int strict, 
     return (a + b - c) < kappa * sqrtf(a * b);
 }
 
+// Distances to u come from src1_d2 / src2_d2 when given (they must be the
+// canonical chain values, as pg_knn_build and this stage produce), else from X.
 __global__ __launch_bounds__(64) void k_prune(
     const float *__restrict__ X, int64_t ldx, int d, int64_t n, const int32_t *__restrict__ src1,
-    int C1, const int32_t *__restrict__ src1_deg, const int64_t *__restrict__ src2_off,
-    const int32_t *__restrict__ src2, int R, float kappa, int use_angle, int strict,
+    const float *__restrict__ src1_d2, int C1, const int32_t *__restrict__ src1_deg,
+    const int64_t *__restrict__ src2_off, const int32_t *__restrict__ src2, const float *__restrict__ src2_d2,
+    int R, float kappa, int use_angle, int strict,
     const float *__restrict__ tab, int32_t *__restrict__ out_ids, float *__restrict__ out_d2,
     int32_t *__restrict__ out_deg) {
     __shared__ __align__(16) float rows[PRG * PSTR];
@@ -65,13 +68,17 @@ __global__ __launch_bounds__(64) void k_prune(
         for (int b = 0; b < m; b += PG_WAVE) {
             const int idx = b + lane;
             int32_t id = -1;
-            if (idx < c1)
+            float dgiven = -1.0f;
+            if (idx < c1) {
                 id = src1[u * C1 + idx];
-            else if (idx < m)
+                if (src1_d2) dgiven = src1_d2[u * C1 + idx];
+            } else if (idx < m) {
                 id = src2[off2 + (idx - c1)];
+                if (src2_d2) dgiven = src2_d2[off2 + (idx - c1)];
+            }
             uint64_t key = KEY_INF;
             if (id >= 0 && id < n && id != (int32_t)u) {
-                const float dd = tu ? tu[idx + 1] : dist_chain(xu, X + (int64_t)id * ldx, d);
+                const float dd = tu ? tu[idx + 1] : (dgiven >= 0.0f ? dgiven : dist_chain(xu, X + (int64_t)id * ldx, d));
                 key = pack_key(dd, id);
                 if (!first && key <= last) key = KEY_INF;
             }
@@ -190,6 +197,243 @@ __global__ __launch_bounds__(64) void k_prune(
 }
 
 // ---------------------------------------------------------------------------
+// Exact 16-bit path.  For integer-valued X with |x| <= 2048 and squared norms
+// <= 2^23, FP16 holds every coordinate exactly and every product and partial
+// sum of a dot product is an integer below 2^24, so with FP32 accumulation
+// d2(v, w) = n_v + n_w - 2 v.w equals the canonical chain bit for bit.  The
+// prune then takes the pairwise distances of a round from 32 x 32 MFMA Gram
+// tiles over rows staged once in LDS.
+// ---------------------------------------------------------------------------
+enum { PX_NONINT = 0, PX_MAXABS = 1, PX_MAXNORM = 2 };
+
+typedef float pm_f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 pm_f16x8 __attribute__((ext_vector_type(8)));
+
+// grid-stride over rows, one wave per row: FP16 copy (zero padded to d16),
+// norms (lane-parallel sum: only used when the data pass the test, where any
+// order is exact) and the exactness flags, one atomic per block and flag
+__global__ __launch_bounds__(256) void k_prune_prep(const float *__restrict__ X, int64_t ldx, int d, int d16,
+                                                    int64_t n, _Float16 *__restrict__ x16,
+                                                    float *__restrict__ norms, unsigned int *__restrict__ ex) {
+    __shared__ unsigned int red[4][3];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    bool nonint = false;
+    float mabs = 0.f, mnorm = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < n; i += (int64_t)gridDim.x * 4) {
+        const float *x = X + i * ldx;
+        float s = 0.f;
+        for (int k = lane; k < d16; k += PG_WAVE) {
+            const float v = k < d ? x[k] : 0.f;
+            nonint |= (v != rintf(v));
+            mabs = fmaxf(mabs, fabsf(v));
+            s = fmaf(v, v, s);
+            x16[i * d16 + k] = (_Float16)v;
+        }
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) s += __shfl_xor(s, o, PG_WAVE);
+        if (lane == 0) norms[i] = s;
+        mnorm = fmaxf(mnorm, s);
+    }
+    const unsigned int ni = __ballot(nonint) != 0 ? 1u : 0u;
+#pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, o, PG_WAVE));
+    if (lane == 0) {
+        red[wv][0] = ni;
+        red[wv][1] = __float_as_uint(mabs);
+        red[wv][2] = __float_as_uint(mnorm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int a = 0, b = 0, c = 0;
+        for (int w = 0; w < 4; ++w) {
+            a |= red[w][0];
+            b = max(b, red[w][1]);
+            c = max(c, red[w][2]);
+        }
+        if (a) atomicOr(&ex[PX_NONINT], 1u);
+        atomicMax(&ex[PX_MAXABS], b);
+        atomicMax(&ex[PX_MAXNORM], c);
+    }
+}
+
+constexpr int PM_DC = 64;            // dimensions per staged chunk
+constexpr int PM_RS = PM_DC + 8;     // LDS row stride in halves (16-byte pad)
+constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept nodes
+
+// One wave per node, rounds of up to 64 candidates as in k_prune; the
+// distances to u are the given (canonical) ones, the pairwise ones come from
+// Gram tiles: candidates x candidates (upper tiles) and kept x candidates.
+// Occlusion among this round's candidates is kept per occluding row (lane i
+// holds the set of later candidates that i occludes); the greedy scan of
+// Alg. 3 ORs in the set of every candidate it keeps.
+__global__ __launch_bounds__(64) void k_prune_mfma(
+    const _Float16 *__restrict__ X16, int d16, const float *__restrict__ norms, int64_t n,
+    const int32_t *__restrict__ src1, const float *__restrict__ src1_d2, int C1,
+    const int32_t *__restrict__ src1_deg, const int64_t *__restrict__ src2_off,
+    const int32_t *__restrict__ src2, const float *__restrict__ src2_d2, int R, float kappa, int use_angle,
+    int strict, int32_t *__restrict__ out_ids, float *__restrict__ out_d2, int32_t *__restrict__ out_deg) {
+    __shared__ __align__(16) _Float16 rows[PM_ROWS * PM_RS];
+    __shared__ uint64_t kept_key[PG_WAVE];
+    __shared__ uint64_t chunk_key[PG_WAVE];
+    __shared__ float cn[PG_WAVE], kn[PG_WAVE];
+    const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
+    const int64_t u = blockIdx.x;
+    const int c1 = src1_deg ? min(src1_deg[u], C1) : C1;
+    const int64_t off2 = src2_off ? src2_off[u] : 0;
+    const int c2 = src2_off ? (int)(src2_off[u + 1] - off2) : 0;
+    const int m = c1 + c2;
+
+    int nk = 0;
+    bool first = true;
+    uint64_t last = 0;
+    while (true) {
+        // ---- next 64 smallest distinct keys above `last`
+        uint64_t top = KEY_INF;
+        int tpos = -1;
+        for (int b = 0; b < m; b += PG_WAVE) {
+            const int idx = b + lane;
+            int32_t id = -1;
+            float dd = 0.f;
+            if (idx < c1) {
+                id = src1[u * C1 + idx];
+                dd = src1_d2[u * C1 + idx];
+            } else if (idx < m) {
+                id = src2[off2 + (idx - c1)];
+                dd = src2_d2[off2 + (idx - c1)];
+            }
+            uint64_t key = KEY_INF;
+            if (id >= 0 && id < n && id != (int32_t)u) {
+                key = pack_key(dd, id);
+                if (!first && key <= last) key = KEY_INF;
+            }
+            int pos = idx;
+            wave_sort(key, pos);
+            const uint64_t prev = shfl64(key, max(lane - 1, 0));
+            const bool valid = key != KEY_INF && !(lane > 0 && prev == key);
+            const int cl = wave_count_less(top, key);
+            const uint64_t at = shfl64(top, min(cl, PG_WAVE - 1));
+            const bool in_top = key != KEY_INF && cl < PG_WAVE && at == key;
+            if (wave_compact(key, pos, valid && !in_top) == 0) continue;
+            wave_merge_lowest(top, tpos, key, pos);
+        }
+        const int cm = __popcll(__ballot(top != KEY_INF));
+        if (cm == 0) break;
+        chunk_key[lane] = top;
+        {
+            const int32_t cid = top != KEY_INF ? key_id(top) : -1;
+            cn[lane] = cid >= 0 ? norms[cid] : 0.f;
+            const int32_t kid = lane < nk ? key_id(kept_key[lane]) : -1;
+            kn[lane] = kid >= 0 ? norms[kid] : 0.f;
+        }
+        const bool two = cm > 32, withk = nk > 0;
+        pm_f32x16 t00, t01, t11, k0, k1;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) t00[g] = t01[g] = t11[g] = k0[g] = k1[g] = 0.f;
+        for (int c0 = 0; c0 < d16; c0 += PM_DC) {
+            const int dc = min(PM_DC, d16 - c0);
+            const int vpr = dc / 8;
+            __syncthreads();
+            for (int v = lane; v < PM_ROWS * vpr; v += PG_WAVE) {
+                const int r = v / vpr, c = (v - r * vpr) * 8;
+                int32_t id = -1;
+                if (r < 64)
+                    id = r < cm ? key_id(chunk_key[r]) : -1;
+                else
+                    id = r - 64 < nk ? key_id(kept_key[r - 64]) : -1;
+                pm_f16x8 x = pm_f16x8{};
+                if (id >= 0) x = *reinterpret_cast<const pm_f16x8 *>(X16 + (int64_t)id * d16 + c0 + c);
+                *reinterpret_cast<pm_f16x8 *>(rows + r * PM_RS + c) = x;
+            }
+            __syncthreads();
+            const _Float16 *r0 = rows + l32 * PM_RS + 8 * h;
+            const _Float16 *r1 = rows + (32 + l32) * PM_RS + 8 * h;
+            const _Float16 *rk = rows + (64 + l32) * PM_RS + 8 * h;
+            for (int k = 0; k < dc; k += 16) {
+                const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
+                t00 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a0, t00, 0, 0, 0);
+                if (two) {
+                    const pm_f16x8 a1 = *reinterpret_cast<const pm_f16x8 *>(r1 + k);
+                    t01 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a1, t01, 0, 0, 0);
+                    t11 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, a1, t11, 0, 0, 0);
+                    if (withk) {
+                        const pm_f16x8 ak = *reinterpret_cast<const pm_f16x8 *>(rk + k);
+                        k0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ak, a0, k0, 0, 0, 0);
+                        k1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ak, a1, k1, 0, 0, 0);
+                    }
+                } else if (withk) {
+                    const pm_f16x8 ak = *reinterpret_cast<const pm_f16x8 *>(rk + k);
+                    k0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ak, a0, k0, 0, 0, 0);
+                }
+            }
+        }
+        // ---- occlusion: kill sets per candidate row, kept-node occlusion per column
+        uint64_t killv = 0, occk = 0;
+        auto cand_tile = [&](const pm_f32x16 &t, int rb, int cb) {
+            const int j = 32 * cb + l32;
+            const float cj = key_d2(chunk_key[j]), nj = cn[j];
+#pragma unroll
+            for (int g = 0; g < 16; ++g) {
+                const int i = 32 * rb + 8 * (g / 4) + 4 * h + (g % 4);
+                bool cnd = false;
+                if (i < cm && j < cm && i < j) {
+                    const float b = fmaxf(fmaf(-2.0f, t[g], cn[i] + nj), 0.0f);
+                    cnd = occludes(key_d2(chunk_key[i]), b, cj, strict, use_angle, kappa);
+                }
+                const uint64_t bm = __ballot(cnd);
+                const int i0 = 32 * rb + 8 * (g / 4) + (g % 4);
+                if (lane == i0) killv |= (bm & 0xFFFFFFFFull) << (32 * cb);
+                if (lane == i0 + 4) killv |= (bm >> 32) << (32 * cb);
+            }
+        };
+        auto kept_tile = [&](const pm_f32x16 &t, int cb) {
+            const int j = 32 * cb + l32;
+            const float cj = key_d2(chunk_key[j]), nj = cn[j];
+#pragma unroll
+            for (int g = 0; g < 16; ++g) {
+                const int k = 8 * (g / 4) + 4 * h + (g % 4);
+                bool cnd = false;
+                if (k < nk && j < cm) {
+                    const float b = fmaxf(fmaf(-2.0f, t[g], kn[k] + nj), 0.0f);
+                    cnd = occludes(key_d2(kept_key[k]), b, cj, strict, use_angle, kappa);
+                }
+                const uint64_t bm = __ballot(cnd);
+                occk |= ((bm & 0xFFFFFFFFull) | (bm >> 32)) << (32 * cb);
+            }
+        };
+        cand_tile(t00, 0, 0);
+        if (two) {
+            cand_tile(t01, 0, 1);
+            cand_tile(t11, 1, 1);
+        }
+        if (withk) {
+            kept_tile(k0, 0);
+            if (two) kept_tile(k1, 1);
+        }
+        // ---- greedy scan of Alg. 3 over this round's candidates
+        uint64_t dead = occk;
+        for (int j = 0; j < cm; ++j) {
+            if ((dead >> j) & 1ull) continue;
+            dead |= readlane64(killv, j);
+            if (lane == 0) kept_key[nk] = chunk_key[j];
+            __builtin_amdgcn_wave_barrier();
+            ++nk;
+            if (nk == R) break;
+        }
+        if (nk == R || cm < PG_WAVE || m <= PG_WAVE) break;
+        last = readlane64(top, PG_WAVE - 1);
+        first = false;
+    }
+    __syncthreads();
+    if (lane < R) {
+        const bool have = lane < nk;
+        const uint64_t k = have ? kept_key[lane] : KEY_INF;
+        out_ids[u * R + lane] = have ? key_id(k) : -1;
+        out_d2[u * R + lane] = have ? key_d2(k) : __int_as_float(0x7f800000);
+    }
+    if (lane == 0) out_deg[u] = nk;
+}
+
+// ---------------------------------------------------------------------------
 // reverse edges (CSR of v -> u for every u -> v)
 // ---------------------------------------------------------------------------
 __global__ void k_count_indeg(const int32_t *__restrict__ g, const int32_t *__restrict__ deg,
@@ -201,16 +445,21 @@ __global__ void k_count_indeg(const int32_t *__restrict__ g, const int32_t *__re
     if (j < deg[u]) atomicAdd(&cnt[g[i]], 1);
 }
 
-__global__ void k_scatter_rev(const int32_t *__restrict__ g, const int32_t *__restrict__ deg,
-                              int64_t n, int R, const int64_t *__restrict__ off,
-                              int32_t *__restrict__ cur, int32_t *__restrict__ rev) {
+// v gets u in its reverse list for every edge u -> v, with d2(v, u) = d2(u, v)
+// (the canonical chain is symmetric bit for bit)
+__global__ void k_scatter_rev(const int32_t *__restrict__ g, const float *__restrict__ gd,
+                              const int32_t *__restrict__ deg, int64_t n, int R,
+                              const int64_t *__restrict__ off, int32_t *__restrict__ cur,
+                              int32_t *__restrict__ rev, float *__restrict__ rev_d2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * R) return;
     const int64_t u = i / R;
     const int j = (int)(i % R);
     if (j < deg[u]) {
         const int32_t v = g[i];
-        rev[off[v] + atomicAdd(&cur[v], 1)] = (int32_t)u;
+        const int64_t at = off[v] + atomicAdd(&cur[v], 1);
+        rev[at] = (int32_t)u;
+        rev_d2[at] = gd[i];
     }
 }
 
@@ -643,12 +892,13 @@ __global__ void k_attach(int32_t *__restrict__ g, float *__restrict__ gd, int32_
 // host side
 // ---------------------------------------------------------------------------
 struct PruneLayout {
-    size_t p_ids, p_d2, p_deg, cnt, off, rev, visited, fa, fb, cs, keys, empty, cpart, cen, apd, api,
-        scan_tmp, total;
+    size_t p_ids, p_d2, p_deg, cnt, off, rev, rev_d2, visited, fa, fb, cs, keys, empty, cpart, cen, apd,
+        api, scan_tmp, x16, norms, exflags, total;
+    int d16;
     int64_t ncb, nab;
 };
 
-static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d_max) {
+static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d) {
     PruneLayout L{};
     const int64_t R = p->R;
     size_t o = 0;
@@ -665,6 +915,7 @@ static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d_max) 
     L.cnt = take(sizeof(int32_t) * n);
     L.off = take(sizeof(int64_t) * (n + 1));
     L.rev = take(sizeof(int32_t) * n * R);
+    L.rev_d2 = take(sizeof(float) * n * R);
     L.visited = take(sizeof(int32_t) * n);
     L.fa = take(sizeof(int32_t) * n);
     L.fb = take(sizeof(int32_t) * n);
@@ -672,11 +923,15 @@ static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d_max) 
     const int64_t nb = std::min<int64_t>(n, CONNECT_BATCH);
     L.keys = take(sizeof(uint64_t) * 64 * nb);
     L.empty = take(sizeof(int32_t) * nb);
-    L.cpart = take(sizeof(double) * L.ncb * d_max);
-    L.cen = take(sizeof(double) * d_max);
+    L.cpart = take(sizeof(double) * L.ncb * d);
+    L.cen = take(sizeof(double) * d);
     L.apd = take(sizeof(double) * L.nab);
     L.api = take(sizeof(int32_t) * L.nab);
     L.scan_tmp = take(scan_tmp_bytes(n + 1));
+    L.d16 = (d + 15) / 16 * 16;
+    L.x16 = take(sizeof(_Float16) * n * L.d16);
+    L.norms = take(sizeof(float) * n);
+    L.exflags = take(sizeof(unsigned int) * 4);
     L.total = o;
     return L;
 }
@@ -845,19 +1100,24 @@ static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float
 
 using namespace pgi;
 
-extern "C" pg_status pg_prune_workspace(const pg_prune_params *p, int64_t n, int32_t C,
+extern "C" pg_status pg_prune_workspace(const pg_prune_params *p, int64_t n, int32_t d, int32_t C,
                                         size_t *bytes) {
     PG_TRY(check_prune(p, n, C));
     if (!bytes) {
         set_error("pg_prune_workspace: bytes is NULL");
         return PG_EINVAL;
     }
-    *bytes = prune_layout(p, n, PRUNE_MAX_D).total;
+    if (d <= 0 || d > PRUNE_MAX_D) {
+        set_error("pg_prune_workspace: d=%d must be in [1, %d]", d, PRUNE_MAX_D);
+        return PG_EINVAL;
+    }
+    *bytes = prune_layout(p, n, d).total;
     return PG_OK;
 }
 
 extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
-                              const int32_t *cand_ids, int32_t C, const pg_prune_params *p, void *ws,
+                              const int32_t *cand_ids, const float *cand_d2, int32_t C,
+                              const pg_prune_params *p, void *ws,
                               size_t ws_bytes, int32_t *g_ids, float *g_d2, int32_t *g_deg,
                               int32_t *ep, int32_t *roots, int32_t *n_roots) {
     if (!ctx || !X || !cand_ids || !g_ids || !g_d2 || !g_deg || !ep) {
@@ -873,7 +1133,7 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         set_error("pg_prune: d and ldx must be multiples of 4 and X 16-byte aligned");
         return PG_EUNSUPPORTED;
     }
-    const PruneLayout L = prune_layout(p, n, PRUNE_MAX_D);
+    const PruneLayout L = prune_layout(p, n, d);
     if (!ws || ws_bytes < L.total) {
         set_error("pg_prune: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
         return PG_ENOMEM;
@@ -894,28 +1154,60 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
     const float kappa = (a == 90.0) ? 0.0f : (float)(2.0 * cos(a * (M_PI / 180.0)));
     const bool rev_stage = (p->stages & PG_STAGE_REVERSE) != 0;
 
+    // exactness test of the 16-bit MFMA path (needs the distances to u given)
+    _Float16 *x16 = (_Float16 *)(w + L.x16);
+    float *nrm = (float *)(w + L.norms);
+    bool exact16 = false;
+    if (!p->pair_d2) {
+        unsigned int *exf = (unsigned int *)(w + L.exflags);
+        PG_HIP(hipMemsetAsync(exf, 0, sizeof(unsigned int) * 4, st));
+        hipLaunchKernelGGL(k_prune_prep, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 4096)), dim3(256), 0, st, X,
+                           ldx, d, L.d16, n, x16, nrm, exf);
+        PG_HIP(hipGetLastError());
+        unsigned int he[4];
+        PG_HIP(hipMemcpyAsync(he, exf, sizeof(he), hipMemcpyDeviceToHost, st));
+        PG_HIP(hipStreamSynchronize(st));
+        float maxabs, maxnorm;
+        memcpy(&maxabs, &he[PX_MAXABS], 4);
+        memcpy(&maxnorm, &he[PX_MAXNORM], 4);
+        exact16 = he[PX_NONINT] == 0 && maxabs <= 2048.0f && maxnorm <= 8388608.0f;
+    }
+    int32_t *s_ids = rev_stage ? p_ids : g_ids, *s_deg = rev_stage ? p_deg : g_deg;
+    float *s_d2 = rev_stage ? p_d2 : g_d2;
     {
         TimedLaunch tl(ctx, K_PRUNE, (double)n * C * C / 2.0 * 3.0 * d);
-        hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, cand_ids, C,
-                           (const int32_t *)nullptr, (const int64_t *)nullptr, (const int32_t *)nullptr, R,
-                           kappa, (int)use_angle, p->strict_ties, p->pair_d2, rev_stage ? p_ids : g_ids,
-                           rev_stage ? p_d2 : g_d2, rev_stage ? p_deg : g_deg);
+        if (exact16 && cand_d2)
+            hipLaunchKernelGGL(k_prune_mfma, dim3((unsigned)n), dim3(64), 0, st, x16, L.d16, nrm, n, cand_ids,
+                               cand_d2, C, (const int32_t *)nullptr, (const int64_t *)nullptr,
+                               (const int32_t *)nullptr, (const float *)nullptr, R, kappa, (int)use_angle,
+                               p->strict_ties, s_ids, s_d2, s_deg);
+        else
+            hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, cand_ids, cand_d2, C,
+                               (const int32_t *)nullptr, (const int64_t *)nullptr, (const int32_t *)nullptr,
+                               (const float *)nullptr, R, kappa, (int)use_angle, p->strict_ties, p->pair_d2,
+                               s_ids, s_d2, s_deg);
         PG_HIP(hipGetLastError());
     }
     if (rev_stage) {
         const int64_t tot = n * R;
+        float *rev_d2 = (float *)(w + L.rev_d2);
         PG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * n, st));
         hipLaunchKernelGGL(k_count_indeg, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p_ids,
                            p_deg, n, R, cnt);
         PG_TRY(scan_exclusive(ctx, cnt, off, n, w + L.scan_tmp));
         PG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * n, st));
-        hipLaunchKernelGGL(k_scatter_rev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p_ids,
-                           p_deg, n, R, off, cnt, rev);
+        hipLaunchKernelGGL(k_scatter_rev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p_ids, p_d2,
+                           p_deg, n, R, off, cnt, rev, rev_d2);
         PG_HIP(hipGetLastError());
         TimedLaunch tl(ctx, K_PRUNE, -1.0);
-        hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, p_ids, R, p_deg,
-                           off, rev, R, kappa, (int)use_angle, p->strict_ties, (const float *)nullptr,
-                           g_ids, g_d2, g_deg);
+        if (exact16)
+            hipLaunchKernelGGL(k_prune_mfma, dim3((unsigned)n), dim3(64), 0, st, x16, L.d16, nrm, n, p_ids, p_d2, R,
+                               p_deg, off, rev, rev_d2, R, kappa, (int)use_angle, p->strict_ties, g_ids, g_d2,
+                               g_deg);
+        else
+            hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, p_ids, p_d2, R, p_deg,
+                               off, rev, rev_d2, R, kappa, (int)use_angle, p->strict_ties, (const float *)nullptr,
+                               g_ids, g_d2, g_deg);
         PG_HIP(hipGetLastError());
     }
     // entry point

@@ -79,8 +79,9 @@ def load_library(path: str = LIB_PATH):
                                  P, P, POINTER(KnnStats)]
     lib.pg_exact_knn.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int64, c_int64, P, c_int32,
                                  P, P]
-    lib.pg_prune_workspace.argtypes = [POINTER(PruneParams), c_int64, c_int32, POINTER(c_size_t)]
-    lib.pg_prune.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, POINTER(PruneParams), P,
+    lib.pg_prune_workspace.argtypes = [POINTER(PruneParams), c_int64, c_int32, c_int32,
+                                       POINTER(c_size_t)]
+    lib.pg_prune.argtypes = [P, P, c_int64, c_int32, c_int64, P, P, c_int32, POINTER(PruneParams), P,
                              c_size_t, P, P, P, P, P, POINTER(c_int32)]
     lib.pg_search.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, P, P, c_int64, c_int64,
                               POINTER(SearchParams), P, P]
@@ -208,13 +209,20 @@ def exact_knn(X, Q, k, exclude=None, ctx=None):
 
 
 def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair_d2=None,
-          ctx=None):
-    """Refinement of Alg. 2: returns dict(ids, d2, deg, ep, roots)."""
+          cand_d2=None, ctx=None):
+    """Refinement of Alg. 2: returns dict(ids, d2, deg, ep, roots).
+
+    cand_d2 (optional, same shape as cand): the canonical squared distances of
+    the candidates, e.g. the d2 output of knn_build."""
     lib = load_library()
     X = _dev_f32(X, "X")
     cand = _dev_i32(cand, "cand")
     n, d = X.shape
     C = cand.shape[1]
+    if cand_d2 is not None:
+        cand_d2 = _dev_f32(cand_d2, "cand_d2")
+        if tuple(cand_d2.shape) != tuple(cand.shape):
+            raise ValueError("cand_d2 must have the shape of cand")
     tab = None
     if pair_d2 is not None:
         tab = pair_d2.contiguous()
@@ -223,7 +231,7 @@ def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair
     p = PruneParams(R=R, alpha_deg=float(alpha_deg), stages=stages, strict_ties=int(bool(strict_ties)),
                     pair_d2=tab.data_ptr() if tab is not None else None)
     ws_bytes = c_size_t()
-    _check(lib.pg_prune_workspace(ctypes.byref(p), n, C, ctypes.byref(ws_bytes)), "workspace")
+    _check(lib.pg_prune_workspace(ctypes.byref(p), n, d, C, ctypes.byref(ws_bytes)), "workspace")
     ws = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=X.device)
     g_ids = torch.empty((n, R), dtype=torch.int32, device=X.device)
     g_d2 = torch.empty((n, R), dtype=torch.float32, device=X.device)
@@ -232,7 +240,8 @@ def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair
     roots = torch.empty(n, dtype=torch.int32, device=X.device)
     nroots = c_int32(0)
     ctx = ctx or context(X.device.index)
-    _check(lib.pg_prune(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(cand), C, ctypes.byref(p),
+    _check(lib.pg_prune(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(cand),
+                        _ptr(cand_d2) if cand_d2 is not None else None, C, ctypes.byref(p),
                         _ptr(ws), ws_bytes.value, _ptr(g_ids), _ptr(g_d2), _ptr(g_deg), _ptr(ep),
                         _ptr(roots), ctypes.byref(nroots)), "pg_prune")
     return {"ids": g_ids, "d2": g_d2, "deg": g_deg, "ep": ep, "roots": roots[:nroots.value]}
@@ -260,6 +269,6 @@ def build_graph(X, K, R, S=None, max_iters=12, seed=0, delta=0.001, alpha_deg=60
                 **knn_kw):
     """The whole build path: NN-Descent lists, then prune, reverse, entry point, connect."""
     ids, d2, st = knn_build(X, K, S=S, max_iters=max_iters, seed=seed, delta=delta, ctx=ctx, **knn_kw)
-    g = prune(X, ids, R, alpha_deg=alpha_deg, ctx=ctx)
+    g = prune(X, ids, R, alpha_deg=alpha_deg, cand_d2=d2, ctx=ctx)
     g["knn_ids"], g["knn_d2"], g["knn_stats"] = ids, d2, st
     return g

@@ -60,9 +60,12 @@ def test_argument_errors_need_no_device(lib):
     p = pg.KnnParams(K=8, S=4, max_iters=3)
     assert lib.pg_knn_build_workspace(ctypes.byref(p), 1000, 6, ctypes.byref(sz)) == -4
     q = pg.PruneParams(R=8, alpha_deg=60.0, stages=2)
-    assert lib.pg_prune_workspace(ctypes.byref(q), 100, 8, ctypes.byref(sz)) == -1
+    assert lib.pg_prune_workspace(ctypes.byref(q), 100, 16, 8, ctypes.byref(sz)) == -1
     q = pg.PruneParams(R=8, alpha_deg=60.0, stages=pg.STAGES_ALL)
-    assert lib.pg_prune_workspace(ctypes.byref(q), 100, 8, ctypes.byref(sz)) == 0
+    assert lib.pg_prune_workspace(ctypes.byref(q), 100, 0, 8, ctypes.byref(sz)) == -1
+    assert b"d=0" in lib.pg_last_error()
+    assert lib.pg_prune_workspace(ctypes.byref(q), 100, 16, 8, ctypes.byref(sz)) == 0
+    assert sz.value > 100 * 8 * 4
 
 
 def test_struct_layouts_match_header(tmp_path):

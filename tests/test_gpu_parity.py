@@ -204,6 +204,43 @@ def test_connect_overflow_is_reported(pg, oracle, datagen):
         pg.prune(dev(X), dev(cand), 2)
 
 
+@pytest.mark.parametrize("nn,d,C,R,alpha,strict,connect", [
+    (3000, 48, 40, 12, 60.0, False, True),    # one partial dimension chunk
+    (3000, 132, 40, 12, 67.0, False, False),  # chunks of 64, 64, 16; alpha test (connect
+                                              # would overflow here, on both sides)
+    (2500, 64, 32, 10, 60.0, True, True),     # strict ties
+    (2000, 32, 64, 40, 60.0, False, True),    # reverse unions above 64: several rounds
+])
+def test_prune_mfma_exact_path_bit_exact(pg, oracle, datagen, nn, d, C, R, alpha, strict, connect):
+    # integer data and given candidate distances: pairwise distances come from
+    # FP16 MFMA Gram tiles, which are exact here
+    X, _ = datagen.sift_like(nn, 0, d=d, n_clusters=20, sigma=6.0, seed=31)
+    cand, cd2 = oracle.exact_knn(X, X, C, exclude=np.arange(nn))
+    st_g = pg.STAGES_ALL if connect else pg.STAGE_PRUNE | pg.STAGE_REVERSE
+    st_o = oracle.STAGE_PRUNE | oracle.STAGE_REVERSE | (oracle.STAGE_CONNECT if connect else 0)
+    g = pg.prune(dev(X), dev(cand), R, alpha_deg=alpha, strict_ties=strict, stages=st_g,
+                 cand_d2=dev(cd2.astype(np.float32)))
+    r = oracle.refine(X, cand, R, alpha_deg=alpha, strict_ties=strict, stages=st_o)
+    log("roots gpu", len(g["roots"]), "oracle", len(r["roots"]))
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert np.array_equal(host(g["deg"]), r["deg"])
+    assert np.array_equal(host(g["d2"]), r["d2"].astype(np.float32))
+    assert np.array_equal(host(g["roots"]), r["roots"])
+    assert int(host(g["ep"])[0]) == r["ep"]
+
+
+def test_prune_given_distances_match_computed_on_float_data(pg, datagen):
+    # non-integer data keep the canonical FP32 path; given distances from the
+    # kNN build are the same chain values, so the graphs are identical
+    X, _ = datagen.gist_like(1500, 0, d=64, n_clusters=10, seed=5)
+    Xd = dev(X)
+    ids, d2, _ = pg.knn_build(Xd, 24, S=12, max_iters=1, seed=3, exact=True)
+    a = pg.prune(Xd, ids, 12, cand_d2=d2)
+    b = pg.prune(Xd, ids, 12)
+    for k in ("ids", "d2", "deg", "roots", "ep"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_prune_table_hook_float_bit_exact(pg, oracle, datagen):
     # identical candidate lists and identical float32 distances -> identical edges
     X, _ = datagen.unit_mixture(400, 0, d=16, n_clusters=5, seed=6)
