@@ -53,17 +53,32 @@ typedef enum {
     PG_EOVERFLOW = -5      /* a bounded structure could not hold the result */
 } pg_status;
 
-/* Arithmetic of the NN-Descent distance tiles.  PG_FP32: float32; on data
- * where it is provably exact (integer values, squared norms <= 2^23) the tiles
- * run as FP32 MFMA norm expansions, otherwise as the FP32 direct form on the
- * vector ALUs.  PG_FP32_VALU: always the direct form.  PG_FP16 / PG_BF16:
- * 16-bit MFMA tiles with FP32 accumulation, accepted only where they are
- * exact (integer data with |x| <= 2048 for FP16, <= 256 for BF16, squared
- * norms <= 2^23), so every precision returns the same lists. */
+/* Arithmetic of the NN-Descent distance tiles.  Every list entry holds the
+ * FP32 direct-form distance (the canonical chain: s = fmaf(x_i - y_i,
+ * x_i - y_i, s) over i ascending), whatever the tiles compute in.
+ *   PG_FP32: on data where it is provably exact (integer values, squared
+ *     norms <= 2^23) the tiles run as FP32 MFMA norm expansions, otherwise as
+ *     the direct form on the vector ALUs.  PG_FP32_VALU: always the direct
+ *     form.
+ *   PG_FP16 / PG_BF16: 16-bit MFMA tiles with FP32 accumulation.  On integer
+ *     data where they are exact (|x| <= 2048 for FP16, <= 256 for BF16,
+ *     squared norms <= 2^23) they give the distances directly.  Otherwise
+ *     (mixed precision) the tiles run on the mean-centred data and only
+ *     prefilter: every pair whose estimate lies within the error bound
+ *     (see margin_rel) of the cut of either end is recomputed in the direct
+ *     form, and so is every value that enters a list.
+ * With the rigorous bound every precision returns the same lists. */
 typedef enum { PG_FP32 = 0, PG_FP16 = 1, PG_BF16 = 2, PG_FP32_VALU = 3 } pg_precision;
 
 /* Join path a build used (pg_knn_stats.join_path). */
-enum { PG_JOIN_VALU = 0, PG_JOIN_MFMA_FP32 = 1, PG_JOIN_MFMA_FP16 = 2, PG_JOIN_MFMA_BF16 = 3 };
+enum {
+    PG_JOIN_VALU = 0,
+    PG_JOIN_MFMA_FP32 = 1,
+    PG_JOIN_MFMA_FP16 = 2,
+    PG_JOIN_MFMA_BF16 = 3,
+    PG_JOIN_MIXED_FP16 = 4, /* FP16 prefilter + FP32 recheck */
+    PG_JOIN_MIXED_BF16 = 5  /* BF16 prefilter + FP32 recheck */
+};
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int pg_version(void);
@@ -119,7 +134,11 @@ typedef struct {
     int64_t stop_updates; /* stop when an iteration changes <= this many entries */
     uint64_t seed;
     int32_t precision;    /* pg_precision of the join tiles */
-    float margin_rel;     /* reserved (must be 0) */
+    float margin_rel;     /* mixed precision only.  >= 0: recheck margin = the
+                             rigorous per-pair error bound of the 16-bit
+                             estimate, plus margin_rel times the cut; < 0:
+                             |margin_rel| times the cut alone (not rigorous:
+                             decisions may then differ from FP32) */
     int32_t bucket_cap;   /* proposal slots per node per pass (>= 2K); 0 = 8K */
     int32_t chunks;       /* source passes in the first iteration (<= 64); 0 = 64 */
 } pg_knn_params;
@@ -132,6 +151,7 @@ typedef struct {
     int64_t proposals[64]; /* proposals that passed the K-th filter at emission */
     int64_t retries;       /* extra join passes: a node's bucket and the spill list were full */
     int64_t spilled;       /* proposals that went past their node's bucket to the spill list */
+    int64_t rechecked[64]; /* mixed precision: pairs recomputed in the direct form */
 } pg_knn_stats;
 
 /* Workspace bytes needed by pg_knn_build for these sizes (host output). */

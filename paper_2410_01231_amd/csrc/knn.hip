@@ -37,7 +37,7 @@
 
 namespace pgi {
 
-enum { C_UPDATES = 0, C_PROPOSALS = 1, C_OVF = 2, C_PAIRS = 3, C_SPILL = 4, C_NCOUNTERS = 8 };
+enum { C_UPDATES = 0, C_PROPOSALS = 1, C_OVF = 2, C_PAIRS = 3, C_SPILL = 4, C_RECHECK = 5, C_NCOUNTERS = 8 };
 
 // ---------------------------------------------------------------------------
 // init: K distinct random neighbours, hash4(seed, 0, u, attempt) mod (n-1)
@@ -606,6 +606,97 @@ __global__ __launch_bounds__(256) void k_prep(const float *__restrict__ X, int64
     }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed-precision prep: the column mean mu (double partial sums over fixed
+// row blocks, then a fixed-order final sum), the 16-bit copy of X - mu and
+// FP32 norms of the rounded rows.  Distances do not change under the shift;
+// centring shrinks the norms that the error bound of the estimates scales
+// with.
+// ---------------------------------------------------------------------------
+constexpr int MU_ROWS = 1024;
+
+__global__ __launch_bounds__(256) void k_colsum_partial(const float *__restrict__ X, int64_t ldx, int d, int64_t n,
+                                                        double *__restrict__ part) {
+    const int64_t r0 = (int64_t)blockIdx.x * MU_ROWS, r1 = min(n, r0 + MU_ROWS);
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        double s = 0.0;
+        for (int64_t r = r0; r < r1; ++r) s += (double)X[r * ldx + j];
+        part[(int64_t)blockIdx.x * d + j] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_colsum_final(const double *__restrict__ part, int64_t nb, int d, int64_t n,
+                                                      float *__restrict__ mu) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d; j += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t b = 0; b < nb; ++b) s += part[b * d + j];
+        mu[j] = (float)(s / (double)n);
+    }
+}
+
+// one wave per row (grid-stride): x16 = 16-bit(fl32(x - mu)), norms = FP32
+// sum of the rounded squares; EX_MAXABS gets max |x - mu|
+__global__ __launch_bounds__(256) void k_prep_mixed(const float *__restrict__ X, int64_t ldx, int d, int d16,
+                                                    int64_t n, int mode, const float *__restrict__ mu,
+                                                    _Float16 *__restrict__ xh, __bf16 *__restrict__ xb,
+                                                    float *__restrict__ norms, unsigned int *__restrict__ ex) {
+    __shared__ unsigned int red[4];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    float mabs = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < n; i += (int64_t)gridDim.x * 4) {
+        const float *x = X + i * ldx;
+        float s = 0.f;
+        for (int k = lane; k < d16; k += PG_WAVE) {
+            const float c = k < d ? x[k] - mu[k] : 0.f;
+            mabs = fmaxf(mabs, fabsf(c));
+            float r;
+            if (mode == PG_FP16) {
+                const _Float16 hv = (_Float16)c;
+                xh[i * d16 + k] = hv;
+                r = (float)hv;
+            } else {
+                const __bf16 bv = (__bf16)c;
+                xb[i * d16 + k] = bv;
+                r = (float)bv;
+            }
+            s = fmaf(r, r, s);
+        }
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) s += __shfl_xor(s, o, PG_WAVE);
+        if (lane == 0) norms[i] = s;
+    }
+#pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, o, PG_WAVE));
+    if (lane == 0) red[wv] = __float_as_uint(mabs);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&ex[EX_MAXABS], max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
+// Error model of the mixed join (all bounds relative to the quantities the
+// kernel has).  With x_c = x - mu, the 16-bit copy x^ satisfies
+// |x^_i - x_c,i| <= un |x_c,i| + ea (ea: half the FP16 subnormal spacing), so
+// ||e|| <= un (||x_c|| + ||y_c||) + 2 sqrt(d) ea for e = (x^ - y^) - (x_c - y_c),
+// and | ||x^ - y^||^2 - ||x_c - y_c||^2 | <= 2 ||e|| ||x_c - y_c|| + ||e||^2.
+// The estimate n^_x + n^_y - 2 x^.y^ (FP32 accumulation of exact products)
+// is within ga (n^_x + n^_y + 2 |x^.y^|) of ||x^ - y^||^2, and the direct form
+// is within gd of the exact distance.  A pair whose direct-form distance is
+// at most the cut c has ||x_c - y_c|| <= sqrt(c (1 + gd)), so its estimate is
+// at most c (1 + gd) + that bound: anything above cannot be accepted.
+struct MixedParams {
+    int on;         // 0: the tiles are exact (integer data)
+    int rigorous;   // 1: rigorous bound (+ mrel * cut); 0: mrel * cut alone
+    float un, ea, gd, ga, mrel, sqd;
+};
+
+__device__ __forceinline__ float mixed_bound(const MixedParams &mx, float cut, float nx, float ny, float g) {
+    if (!mx.rigorous) return cut * (1.0f + mx.mrel);
+    const float cg = cut * (1.0f + mx.gd);
+    const float sn = (sqrtf(nx) + sqrtf(ny)) * (1.0f + 2.0f * mx.un);
+    const float e = mx.un * sn + 2.0f * mx.sqd * mx.ea;
+    const float b = cg + 2.0f * e * sqrtf(cg) + e * e + mx.ga * (nx + ny + 2.0f * fabsf(g)) + mx.mrel * cut;
+    return b * 1.0001f + 1e-30f;  // slack for evaluating the bound itself in FP32
+}
+
 typedef float mf_f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 mf_f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
@@ -676,8 +767,8 @@ constexpr int MW = 4;  // sources (waves) per workgroup in the MFMA join
 // FP32 join.  Offsets of the proposals to a tile's row member come from
 // ballots (the 32 lanes of a half share the row), so only one LDS atomic per
 // (row, tile half) and one per (lane, column) are needed.
-template <int P>
-__global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
+template <int P, bool MIX>
+__global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
     const float *__restrict__ X, int64_t ldx, const void *__restrict__ X16, int d, int d16,
     const float *__restrict__ norms, int K, const int32_t *__restrict__ jn,
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
@@ -685,7 +776,7 @@ __global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
     int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
     int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t spill_cap,
     uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, const int32_t *__restrict__ order,
-    int64_t n, PassRange pr, int maxm, unsigned long long *__restrict__ counters) {
+    int64_t n, PassRange pr, int maxm, MixedParams mx, unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int MPS = (maxm + 31) / 32 * 32;
     const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
@@ -722,7 +813,7 @@ __global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
     __builtin_amdgcn_wave_barrier();
     const int RB = (nn + 31) / 32, CB = mp / 32;
     const int32_t id0 = ids[0];
-    unsigned long long local_props = 0;
+    unsigned long long local_props = 0, local_rechk = 0;
     for (int rb = 0; rb < RB; ++rb) {
         for (int cb = rb; cb < CB; ++cb) {
             // member of this lane's column and of the tile rows it loads
@@ -734,11 +825,20 @@ __global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
             // decisions (bit g of each mask = accumulator register g)
             uint32_t to_row = 0, to_col = 0;
             const float nc = nrm[cm < mp ? cm : 0];
+            float dx[MIX ? 16 : 1];  // mixed: direct-form distances of the rechecked pairs
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
+                if (MIX) dx[MIX ? q : 0] = __int_as_float(0x7f800000);
                 if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
-                const float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                if (MIX) {
+                    const float cut = fmaxf(mk[r] ? key_d2(kth[r]) : -1.0f, mk[cm] ? key_d2(kth[cm]) : -1.0f);
+                    if (cut < 0.0f || !(d2 <= mixed_bound(mx, cut, nrm[r], nc, g[q]))) continue;
+                    d2 = dist_chain(X + (int64_t)ids[r] * ldx, X + (int64_t)ids[cm] * ldx, d);
+                    dx[MIX ? q : 0] = d2;
+                    ++local_rechk;
+                }
                 const uint64_t kw = pack_key(d2, ids[cm]), kv = pack_key(d2, ids[r]);
                 if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
                     to_row |= 1u << q;
@@ -771,7 +871,7 @@ __global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
                 const uint32_t bit = 1u << q;
                 if (!((to_row | to_col) & bit)) continue;
                 const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
-                const float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                const float d2 = MIX ? dx[MIX ? q : 0] : fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
                 if (to_row & bit) {
                     const int32_t v = ids[r];
                     const int slot = base[r] + off_row[q];
@@ -798,10 +898,11 @@ __global__ __launch_bounds__(MW * PG_WAVE) void k_join_mfma(
     }
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) {
-        const unsigned long long t = __shfl_xor((long long)local_props, o, PG_WAVE);
-        local_props += t;
+        local_props += (unsigned long long)__shfl_xor((long long)local_props, o, PG_WAVE);
+        local_rechk += (unsigned long long)__shfl_xor((long long)local_rechk, o, PG_WAVE);
     }
     if (lane == 0 && local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
+    if (lane == 0 && local_rechk) atomicAdd(&counters[C_RECHECK], local_rechk);
 }
 
 static size_t join_mfma_lds_bytes(int maxm) {
@@ -1029,7 +1130,8 @@ __global__ void k_order_scatter(const int32_t *__restrict__ piv, int64_t n, cons
 struct KnnLayout {
     size_t keys, newm, insm, nf, nf_c, of, of_c, rn_cnt, ro_cnt, rn_off, ro_off, rn_list, ro_list,
         jn, jn_c, jo, jo_c, pcnt, bucket, mark, mark_next, counters, scan_tmp, spill_t, spill_k,
-        spill_s, x16, norms, exflags, order, total;
+        spill_s, x16, norms, exflags, order, mu, mu_part, total;
+    int64_t mu_nb;
     int B, JN, JO, d16;
     int64_t spill_cap;
 };
@@ -1081,6 +1183,9 @@ static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d) {
     L.norms = take(sizeof(float) * n);
     L.exflags = take(sizeof(unsigned int) * 4);
     L.order = take(sizeof(int32_t) * n);
+    L.mu_nb = half ? (n + MU_ROWS - 1) / MU_ROWS : 0;
+    L.mu = take(half ? sizeof(float) * d : 0);
+    L.mu_part = take(sizeof(double) * L.mu_nb * d);
     L.total = o;
     return L;
 }
@@ -1121,6 +1226,10 @@ static pg_status check_knn(const pg_knn_params *p, int64_t n, int32_t d) {
     }
     if (p->chunks < 0) {
         set_error("pg_knn_build: chunks=%d must be >= 0", p->chunks);
+        return PG_EINVAL;
+    }
+    if (!(p->margin_rel >= -1.0f && p->margin_rel <= 1.0f)) {
+        set_error("pg_knn_build: margin_rel=%g must be in [-1, 1]", (double)p->margin_rel);
         return PG_EINVAL;
     }
     return PG_OK;
@@ -1235,6 +1344,7 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
     float *norms = (float *)(w + L.norms);
     unsigned int *exf = (unsigned int *)(w + L.exflags);
     int path = PG_JOIN_VALU;
+    MixedParams mx{};
     if (p->precision != PG_FP32_VALU) {
         PG_HIP(hipMemsetAsync(exf, 0, sizeof(unsigned int) * 4, st));
         hipLaunchKernelGGL(k_prep, dim3((unsigned)std::min<int64_t>(wave_blocks, 4096)), dim3(256), 0, st, X, ldx,
@@ -1249,21 +1359,43 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         memcpy(&maxnorm, &he[EX_MAXNORM], 4);
         const bool ints = he[EX_NONINT] == 0 && maxnorm <= 8388608.0f;
         if (p->precision == PG_FP32 && ints) path = PG_JOIN_MFMA_FP32;
-        if (p->precision == PG_FP16) {
-            if (!(ints && maxabs <= 2048.0f)) {
-                set_error("pg_knn_build: FP16 tiles need integer data with |x| <= 2048 and "
-                          "squared norms <= 2^23 (exact); use PG_FP32 for this data");
-                return PG_EUNSUPPORTED;
+        MixedParams none{};
+        mx = none;
+        if (p->precision == PG_FP16 || p->precision == PG_BF16) {
+            const bool f16 = p->precision == PG_FP16;
+            if (ints && maxabs <= (f16 ? 2048.0f : 256.0f)) {
+                path = f16 ? PG_JOIN_MFMA_FP16 : PG_JOIN_MFMA_BF16;
+            } else {
+                // mixed precision: centred 16-bit prefilter, direct-form recheck
+                float *mu = (float *)(w + L.mu);
+                double *part = (double *)(w + L.mu_part);
+                hipLaunchKernelGGL(k_colsum_partial, dim3((unsigned)L.mu_nb), dim3(256), 0, st, X, ldx, d, n, part);
+                hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, part,
+                                   L.mu_nb, d, n, mu);
+                PG_HIP(hipMemsetAsync(exf, 0, sizeof(unsigned int) * 4, st));
+                hipLaunchKernelGGL(k_prep_mixed, dim3((unsigned)std::min<int64_t>(wave_blocks, 4096)), dim3(256), 0,
+                                   st, X, ldx, d, L.d16, n, p->precision, mu, xh, xb, norms, exf);
+                PG_HIP(hipGetLastError());
+                PG_HIP(hipMemcpyAsync(he, exf, sizeof(he), hipMemcpyDeviceToHost, st));
+                PG_HIP(hipStreamSynchronize(st));
+                float cmax;
+                memcpy(&cmax, &he[EX_MAXABS], 4);
+                if (!(cmax <= (f16 ? 32768.0f : 1e30f))) {
+                    set_error("pg_knn_build: centred values up to %g do not fit the 16-bit tiles; use PG_FP32",
+                              (double)cmax);
+                    return PG_EUNSUPPORTED;
+                }
+                path = f16 ? PG_JOIN_MIXED_FP16 : PG_JOIN_MIXED_BF16;
+                mx.on = 1;
+                mx.rigorous = p->margin_rel >= 0.0f;
+                mx.mrel = fabsf(p->margin_rel);
+                const double u32 = 1.0 / 16777216.0;
+                mx.un = (float)((f16 ? 1.0 / 2048.0 : 1.0 / 256.0) + 4.0 * u32);
+                mx.ea = f16 ? 2.98023224e-08f : 1e-38f;  // half the 16-bit subnormal spacing
+                mx.gd = (float)((d + 4) * u32 * 1.01);
+                mx.ga = (float)((2.0 * d + 16) * u32 * 1.01);
+                mx.sqd = sqrtf((float)d);
             }
-            path = PG_JOIN_MFMA_FP16;
-        }
-        if (p->precision == PG_BF16) {
-            if (!(ints && maxabs <= 256.0f)) {
-                set_error("pg_knn_build: BF16 tiles need integer data with |x| <= 256 and "
-                          "squared norms <= 2^23 (exact); use PG_FP32 for this data");
-                return PG_EUNSUPPORTED;
-            }
-            path = PG_JOIN_MFMA_BF16;
         }
     }
     if (stats) stats->join_path = path;
@@ -1353,20 +1485,30 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                                            L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
                                            maxm, counters);
                     else if (path == PG_JOIN_MFMA_FP32)
-                        hipLaunchKernelGGL(k_join_mfma<PG_FP32>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
+                        hipLaunchKernelGGL((k_join_mfma<PG_FP32, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
                                            x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
                                            pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
-                                           order, n, pr, maxm, counters);
+                                           order, n, pr, maxm, mx, counters);
                     else if (path == PG_JOIN_MFMA_FP16)
-                        hipLaunchKernelGGL(k_join_mfma<PG_FP16>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
-                                           x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
-                                           pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
-                                           order, n, pr, maxm, counters);
+                        hipLaunchKernelGGL((k_join_mfma<PG_FP16, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                                           ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
+                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           maxm, mx, counters);
+                    else if (path == PG_JOIN_MFMA_BF16)
+                        hipLaunchKernelGGL((k_join_mfma<PG_BF16, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                                           ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
+                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           maxm, mx, counters);
+                    else if (path == PG_JOIN_MIXED_FP16)
+                        hipLaunchKernelGGL((k_join_mfma<PG_FP16, true>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                                           ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
+                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           maxm, mx, counters);
                     else
-                        hipLaunchKernelGGL(k_join_mfma<PG_BF16>, dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
-                                           x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
-                                           pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
-                                           order, n, pr, maxm, counters);
+                        hipLaunchKernelGGL((k_join_mfma<PG_BF16, true>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                                           ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
+                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           maxm, mx, counters);
                     PG_HIP(hipGetLastError());
                 }
                 unsigned long long hc2[C_NCOUNTERS];
@@ -1419,6 +1561,7 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
             stats->updates[t - 1] = (int64_t)hc[C_UPDATES];
             stats->pairs[t - 1] = (int64_t)hc[C_PAIRS];
             stats->proposals[t - 1] = (int64_t)hc[C_PROPOSALS];
+            stats->rechecked[t - 1] = (int64_t)hc[C_RECHECK];
         }
         ctx_add_work(ctx, K_JOIN, 3.0 * (double)hc[C_PAIRS] * d);
         if ((int64_t)hc[C_UPDATES] <= p->stop_updates) break;

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libpg.so")
 STAGE_PRUNE, STAGE_REVERSE, STAGE_CONNECT = 1, 2, 4
 STAGES_ALL = STAGE_PRUNE | STAGE_REVERSE | STAGE_CONNECT
 FP32, FP16, BF16, FP32_VALU = 0, 1, 2, 3
-JOIN_PATHS = {0: "fp32-valu", 1: "fp32-mfma", 2: "fp16-mfma", 3: "bf16-mfma"}
+JOIN_PATHS = {0: "fp32-valu", 1: "fp32-mfma", 2: "fp16-mfma", 3: "bf16-mfma", 4: "fp16-mixed",
+              5: "bf16-mixed"}
 
 
 class PgError(RuntimeError):
@@ -38,7 +39,7 @@ class KnnParams(ctypes.Structure):
 class KnnStats(ctypes.Structure):
     _fields_ = [("iters_run", c_int32), ("join_path", c_int32), ("updates", c_int64 * 64),
                 ("pairs", c_int64 * 64), ("proposals", c_int64 * 64), ("retries", c_int64),
-                ("spilled", c_int64)]
+                ("spilled", c_int64), ("rechecked", c_int64 * 64)]
 
 
 class PruneParams(ctypes.Structure):
@@ -166,7 +167,7 @@ def _dev_i32(t, name):
 
 
 def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001, exact=False,
-              bucket_cap=0, chunks=0, precision=FP32, ctx=None):
+              bucket_cap=0, chunks=0, precision=FP32, margin_rel=0.0, ctx=None):
     """NN-Descent kNN lists of the rows of X: returns (ids, d2, stats dict)."""
     lib = load_library()
     X = _dev_f32(X, "X")
@@ -175,7 +176,8 @@ def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001
     if stop_updates is None:
         stop_updates = int(delta * n * K)
     p = KnnParams(K=K, S=S, max_iters=max_iters, exact=int(bool(exact)), stop_updates=stop_updates,
-                  seed=seed & (2**64 - 1), precision=precision, margin_rel=0.0, bucket_cap=bucket_cap,
+                  seed=seed & (2**64 - 1), precision=precision, margin_rel=float(margin_rel),
+                  bucket_cap=bucket_cap,
                   chunks=chunks)
     ws_bytes = c_size_t()
     _check(lib.pg_knn_build_workspace(ctypes.byref(p), n, d, ctypes.byref(ws_bytes)), "workspace")
@@ -188,7 +190,8 @@ def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001
                             ws_bytes.value, _ptr(ids), _ptr(d2), ctypes.byref(st)), "pg_knn_build")
     it = st.iters_run
     stats = {"iters": it, "updates": list(st.updates[:it]), "pairs": list(st.pairs[:it]),
-             "proposals": list(st.proposals[:it]), "retries": st.retries,
+             "proposals": list(st.proposals[:it]), "rechecked": list(st.rechecked[:it]),
+             "retries": st.retries,
              "spilled": st.spilled, "join_path": JOIN_PATHS.get(st.join_path, st.join_path)}
     return ids, d2, stats
 

@@ -112,13 +112,55 @@ def test_nndescent_c1_config(pg, oracle, datagen):
     assert np.array_equal(host(d2), rd2.astype(np.float32))
 
 
+@pytest.mark.parametrize("gen,prec", [("gist", 1), ("gist", 2), ("deep", 1), ("deep", 2)])
+def test_mixed_precision_lists_equal_fp32(pg, datagen, gen, prec):
+    # float data: 16-bit tiles on centred data only prefilter; with the
+    # rigorous margin every decision and every stored distance is the FP32
+    # direct form, so the lists equal the FP32 build bit for bit
+    if gen == "gist":
+        X, _ = datagen.gist_like(4000, 0, d=240, n_clusters=12, seed=6)
+    else:
+        X, _ = datagen.unit_mixture(4000, 0, d=96, n_clusters=40, seed=7)
+    Xd = dev(X)
+    a_ids, a_d2, a_st = pg.knn_build(Xd, 24, S=12, max_iters=6, seed=5, precision=prec)
+    b_ids, b_d2, b_st = pg.knn_build(Xd, 24, S=12, max_iters=6, seed=5, precision=pg.FP32)
+    log(gen, a_st["join_path"], "rechecked", a_st["rechecked"], "pairs", a_st["pairs"])
+    assert a_st["join_path"] == ("fp16-mixed" if prec == 1 else "bf16-mixed")
+    assert b_st["join_path"] == "fp32-valu"
+    assert torch.equal(a_ids, b_ids)
+    assert torch.equal(a_d2, b_d2)
+    assert a_st["updates"] == b_st["updates"]
+    assert 0 < sum(a_st["rechecked"]) < sum(a_st["pairs"])
+
+
+def test_mixed_precision_stated_margin_keeps_direct_distances(pg, datagen):
+    # margin_rel < 0: the stated relative margin alone (not rigorous).  Stored
+    # distances are still the direct form, so each entry's d2 equals the FP32
+    # build's value for the same pair wherever both lists hold it.
+    X, _ = datagen.gist_like(3000, 0, d=240, n_clusters=12, seed=8)
+    Xd = dev(X)
+    a_ids, a_d2, a_st = pg.knn_build(Xd, 16, S=8, max_iters=5, seed=2, precision=pg.FP16,
+                                     margin_rel=-1e-3)
+    b_ids, b_d2, _ = pg.knn_build(Xd, 16, S=8, max_iters=5, seed=2, precision=pg.FP32)
+    ai, ad, bi, bd = host(a_ids), host(a_d2), host(b_ids), host(b_d2)
+    assert (np.diff(ad, axis=1) >= 0).all()
+    common = 0
+    for u in range(len(X)):
+        m = dict(zip(bi[u].tolist(), bd[u].tolist()))
+        for v, dv in zip(ai[u].tolist(), ad[u].tolist()):
+            if v in m:
+                assert m[v] == dv
+                common += 1
+    assert common > 0.9 * ai.size
+
+
 def test_nndescent_float_statistical(pg, oracle, datagen):
     X, _ = datagen.unit_mixture(4000, 0, d=96, n_clusters=40, seed=4)
     ids, d2, st = pg.knn_build(dev(X), 16, S=8, max_iters=10, seed=2)
     assert st["join_path"] == "fp32-valu"  # norm expansion is not exact on this data
     with pytest.raises(pg.PgError) as e:
-        pg.knn_build(dev(X), 16, S=8, max_iters=2, seed=2, precision=pg.FP16)
-    assert e.value.status == -4
+        pg.knn_build(dev(X), 16, S=8, max_iters=2, seed=2, precision=pg.FP16, margin_rel=2.0)
+    assert e.value.status == -1
     rid, rd2, _, rst = oracle.nndescent(X, 16, 8, 10, 2, stop_updates=int(0.001 * 4000 * 16))
     gt, _ = oracle.exact_knn(X, X, 16, exclude=np.arange(4000))
     g = host(ids)
