@@ -64,6 +64,8 @@ def _load():
     lib.orc_search.restype = ctypes.c_int
     lib.orc_search.argtypes = [P, i64, i32, i64, P, i32, P, P, i64, i64, P, i32, i32, i32,
                                P, P, P]
+    lib.orc_search_self.restype = ctypes.c_int
+    lib.orc_search_self.argtypes = [P, i64, i32, i64, P, i32, P, i32, i32, P, P, P]
     _lib = lib
     return lib
 
@@ -200,6 +202,42 @@ def search(X, g_ids, g_deg, Q, entries, k, L):
                           _ptr(Q), nq, d, _ptr(entries), len(entries), k, L,
                           _ptr(ids), _ptr(d2), _ptr(stats)), "search")
     return ids, d2, stats
+
+
+def search_self(X, g_ids, g_deg, k, L):
+    """Alg. 5 Phase 3: KANNSearch(G, u, k, L, u) for every u, u itself left out."""
+    lib = _load()
+    X = _f32(X)
+    g_ids, g_deg = _i32(g_ids), _i32(g_deg)
+    n, d = X.shape
+    ids = np.empty((n, k), np.int32)
+    d2 = np.empty((n, k), np.float64)
+    stats = np.empty((n, 2), np.int64)
+    _check(lib.orc_search_self(_ptr(X), n, d, d, _ptr(g_ids), g_ids.shape[1], _ptr(g_deg), k, L,
+                               _ptr(ids), _ptr(d2), _ptr(stats)), "search_self")
+    return ids, d2, stats
+
+
+def opt_kcna(X, cand, k, L, M, alpha_deg):
+    """OptKCNA (Alg. 5): the alpha-PG of the candidate lists (prune with M and
+    alpha, reverse re-prune, connect), then a search from every point on it.
+    Returns the new candidate lists (n x k) and their d2."""
+    g = refine(X, cand, M, alpha_deg=alpha_deg)
+    ids, d2, _ = search_self(X, g["ids"], g["deg"], k, L)
+    return ids, d2
+
+
+def iter_nsg(X, K, S, max_iters, seed, stop_updates, k, L, M, alpha_deg, iterations):
+    """IterNSG (Alg. 6) with a fixed number of OptKCNA rounds: NN-Descent lists
+    (Phase 1), `iterations` rounds of OptKCNA, then the refinement of Alg. 2
+    (RNG pruning with M, reverse, entry point, connect).  Returns the graph dict
+    of refine() plus the final candidate lists under "cand"."""
+    cand, _, _, _ = nndescent(X, K, S, max_iters, seed, stop_updates=stop_updates)
+    for _ in range(iterations):
+        cand, _ = opt_kcna(X, cand, k, L, M, alpha_deg)
+    g = refine(X, cand, M)
+    g["cand"] = cand
+    return g
 
 
 def recall_at_k(found_ids, true_ids):

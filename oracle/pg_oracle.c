@@ -27,6 +27,7 @@
  *                  re-prune, DFS connectivity and extra edges; the entry point
  *                  of Alg. 2 Phase 2 (closest point to the centroid).
  *   orc_search     Alg. 1 (KANNSearch, beam search).
+ *   orc_search_self  the search phase of OptKCNA (Alg. 5, Phase 3).
  * Readings where the paper is silent are stated at each function.
  */
 #include <math.h>
@@ -968,6 +969,66 @@ int orc_refine(const float *X, int64_t n, int32_t d, int64_t ldx,
  * neighbours already in the pool; the seen-set removes those repeats.
  * stats (optional, 2 per query): expansions, distance evaluations.
  */
+/* One query of the beam search: pool (capacity L + n_entry + 1) holds the
+ * result, *size its length; seen/touched are per-thread scratch, cleared on
+ * return.  Returns expansions and distance evaluations through nexp, ndist. */
+static int32_t search_one(const float *X, int64_t n, int32_t d, int64_t ldx,
+                          const int32_t *g_ids, int32_t R, const int32_t *g_deg,
+                          const float *xq, const int32_t *entries, int32_t n_entry, int32_t L,
+                          orc_item *pool, uint8_t *seen, int32_t *touched,
+                          int64_t *nexp, int64_t *ndist)
+{
+    int64_t nt = 0;
+    int32_t size = 0;
+    *nexp = 0;
+    *ndist = 0;
+    for (int32_t e = 0; e < n_entry; ++e) {
+        int32_t v = entries[e];
+        if (v < 0 || v >= n || seen[v])
+            continue;
+        seen[v] = 1;
+        touched[nt++] = v;
+        pool[size].id = v;
+        pool[size].d2 = sqdist(xq, X + (int64_t)v * ldx, d);
+        pool[size].tag = 0;
+        ++size;
+        ++*ndist;
+    }
+    qsort(pool, (size_t)size, sizeof(orc_item), cmp_item);
+    if (size > L)
+        size = L;
+    for (;;) {
+        int32_t i = 0;
+        while (i < size && pool[i].tag)
+            ++i;
+        if (i >= size)
+            break;
+        pool[i].tag = 1;
+        ++*nexp;
+        int32_t x = pool[i].id;
+        for (int32_t j = 0; j < g_deg[x]; ++j) {
+            int32_t v = g_ids[(int64_t)x * R + j];
+            if (v < 0 || v >= n || seen[v])
+                continue;
+            seen[v] = 1;
+            touched[nt++] = v;
+            orc_item it = {sqdist(xq, X + (int64_t)v * ldx, d), v, 0};
+            ++*ndist;
+            if (size == L && !item_less(&it, &pool[L - 1]))
+                continue;
+            int32_t p = size < L ? size++ : L - 1;
+            while (p > 0 && item_less(&it, &pool[p - 1])) {
+                pool[p] = pool[p - 1];
+                --p;
+            }
+            pool[p] = it;
+        }
+    }
+    for (int64_t t = 0; t < nt; ++t)
+        seen[touched[t]] = 0;
+    return size;
+}
+
 int orc_search(const float *X, int64_t n, int32_t d, int64_t ldx,
                const int32_t *g_ids, int32_t R, const int32_t *g_deg,
                const float *Q, int64_t nq, int64_t ldq,
@@ -989,51 +1050,9 @@ int orc_search(const float *X, int64_t n, int32_t d, int64_t ldx,
         for (int64_t q = 0; q < nq; ++q) {
             if (!seen || !touched || !pool)
                 continue;
-            const float *xq = Q + q * ldq;
-            int64_t nt = 0, nexp = 0, ndist = 0;
-            int32_t size = 0;
-            for (int32_t e = 0; e < n_entry; ++e) {
-                int32_t v = entries[e];
-                if (v < 0 || v >= n || seen[v])
-                    continue;
-                seen[v] = 1;
-                touched[nt++] = v;
-                pool[size].id = v;
-                pool[size].d2 = sqdist(xq, X + (int64_t)v * ldx, d);
-                pool[size].tag = 0;
-                ++size;
-                ++ndist;
-            }
-            qsort(pool, (size_t)size, sizeof(orc_item), cmp_item);
-            if (size > L)
-                size = L;
-            for (;;) {
-                int32_t i = 0;
-                while (i < size && pool[i].tag)
-                    ++i;
-                if (i >= size)
-                    break;
-                pool[i].tag = 1;
-                ++nexp;
-                int32_t x = pool[i].id;
-                for (int32_t j = 0; j < g_deg[x]; ++j) {
-                    int32_t v = g_ids[(int64_t)x * R + j];
-                    if (v < 0 || v >= n || seen[v])
-                        continue;
-                    seen[v] = 1;
-                    touched[nt++] = v;
-                    orc_item it = {sqdist(xq, X + (int64_t)v * ldx, d), v, 0};
-                    ++ndist;
-                    if (size == L && !item_less(&it, &pool[L - 1]))
-                        continue;
-                    int32_t p = size < L ? size++ : L - 1;
-                    while (p > 0 && item_less(&it, &pool[p - 1])) {
-                        pool[p] = pool[p - 1];
-                        --p;
-                    }
-                    pool[p] = it;
-                }
-            }
+            int64_t nexp, ndist;
+            const int32_t size = search_one(X, n, d, ldx, g_ids, R, g_deg, Q + q * ldq, entries,
+                                            n_entry, L, pool, seen, touched, &nexp, &ndist);
             for (int32_t j = 0; j < k; ++j) {
                 out_ids[q * k + j] = j < size ? pool[j].id : -1;
                 out_d2[q * k + j] = j < size ? pool[j].d2 : INFINITY;
@@ -1042,8 +1061,60 @@ int orc_search(const float *X, int64_t n, int32_t d, int64_t ldx,
                 stats[2 * q] = nexp;
                 stats[2 * q + 1] = ndist;
             }
-            for (int64_t t = 0; t < nt; ++t)
-                seen[touched[t]] = 0;
+        }
+        free(seen);
+        free(touched);
+        free(pool);
+    }
+    return bad ? ORC_ENOMEM : ORC_OK;
+}
+
+/*
+ * The search phase of OptKCNA (Alg. 5, Phase 3): for every node u,
+ * KANNSearch(G, u, k, L, u), the beam search for the point x_u entering at u
+ * itself.  Reading: the paper is silent on whether u may be one of its own
+ * candidates; C(u) is the first k pool entries other than u (u sits in the
+ * pool at distance 0 unless at least L other points coincide with it).
+ * Needs k < L.
+ */
+int orc_search_self(const float *X, int64_t n, int32_t d, int64_t ldx,
+                    const int32_t *g_ids, int32_t R, const int32_t *g_deg,
+                    int32_t k, int32_t L, int32_t *out_ids, double *out_d2, int64_t *stats)
+{
+    if (!X || !g_ids || !g_deg || n <= 0 || d <= 0 || R <= 0 || k <= 0 || L <= k || ldx < d)
+        return ORC_EINVAL;
+    int bad = 0;
+#pragma omp parallel
+    {
+        uint8_t *seen = calloc((size_t)n, 1);
+        int32_t *touched = malloc(sizeof(int32_t) * (size_t)n);
+        orc_item *pool = malloc(sizeof(orc_item) * (size_t)(L + 2));
+        if (!seen || !touched || !pool)
+            bad = 1;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t u = 0; u < n; ++u) {
+            if (!seen || !touched || !pool)
+                continue;
+            int64_t nexp, ndist;
+            const int32_t entry = (int32_t)u;
+            const int32_t size = search_one(X, n, d, ldx, g_ids, R, g_deg, X + u * ldx, &entry, 1,
+                                            L, pool, seen, touched, &nexp, &ndist);
+            int32_t j = 0;
+            for (int32_t i = 0; i < size && j < k; ++i) {
+                if (pool[i].id == (int32_t)u)
+                    continue;
+                out_ids[u * k + j] = pool[i].id;
+                out_d2[u * k + j] = pool[i].d2;
+                ++j;
+            }
+            for (; j < k; ++j) {
+                out_ids[u * k + j] = -1;
+                out_d2[u * k + j] = INFINITY;
+            }
+            if (stats) {
+                stats[2 * u] = nexp;
+                stats[2 * u + 1] = ndist;
+            }
         }
         free(seen);
         free(touched);

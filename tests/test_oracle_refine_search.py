@@ -153,3 +153,53 @@ def test_connect_matches_restatement(oracle, datagen):
     assert list(full["roots"]) == roots
     assert np.array_equal(full["deg"], deg)
     assert np.array_equal(full["ids"], ids)
+
+
+# ------------------------------------------------ OptKCNA / IterNSG (Alg. 5, 6)
+
+def test_search_self_complete_graph_is_exact_without_self(oracle):
+    # complete graph: expanding the entry u evaluates every node, so the first
+    # k pool entries other than u are the exact k nearest other points
+    rng = np.random.default_rng(11)
+    n = 80
+    X = rng.standard_normal((n, 6)).astype(np.float32)
+    ids = np.array([[v for v in range(n) if v != u] for u in range(n)], np.int32)
+    deg = np.full(n, n - 1, np.int32)
+    got, d2, _ = oracle.search_self(X, ids, deg, 7, 8)
+    D = ((X[:, None, :].astype(np.float64) - X[None, :, :]) ** 2).sum(-1)
+    for u in range(n):
+        order = sorted((D[u, v], v) for v in range(n) if v != u)[:7]
+        assert list(got[u]) == [v for _, v in order]
+        assert np.allclose(d2[u], [dd for dd, _ in order], rtol=0, atol=1e-12)
+
+
+def test_search_self_large_pool_is_exact(oracle, datagen):
+    # L >= n on a connected graph: the search sees every node
+    X = datagen.uniform_int(300, 8, seed=12)
+    cand, _ = oracle.exact_knn(X, X, 10, exclude=np.arange(300))
+    g = oracle.refine(X, cand, 8)
+    got, d2, _ = oracle.search_self(X, g["ids"], g["deg"], 10, 300)
+    assert np.array_equal(got, cand)
+    assert (got != np.arange(300)[:, None]).all()
+
+
+def test_opt_kcna_round_keeps_list_invariants(oracle, datagen):
+    # one OptKCNA round on NN-Descent lists: lists stay sorted, self-free,
+    # and (on integer data, where d2 is exact) their distances are the true ones
+    X, _ = datagen.sift_like(1500, 0, d=16, n_clusters=10, sigma=6.0, seed=13)
+    cand, _, _, _ = oracle.nndescent(X, 12, 6, 3, 1)
+    ids, d2 = oracle.opt_kcna(X, cand, 12, 24, 8, 65.0)
+    n = len(X)
+    assert (ids != np.arange(n)[:, None]).all() and (ids >= 0).all()
+    assert (np.diff(d2, axis=1) >= 0).all()
+    true = ((X[np.arange(n)[:, None]].astype(np.float64) - X[ids]) ** 2).sum(-1)
+    assert np.array_equal(true, d2)
+    assert all(len(set(r)) == len(r) for r in ids.tolist())
+
+
+def test_iter_nsg_zero_rounds_is_refined_nndescent(oracle, datagen):
+    X, _ = datagen.sift_like(800, 0, d=16, n_clusters=8, sigma=6.0, seed=14)
+    g = oracle.iter_nsg(X, 12, 6, 4, 3, 0, 12, 24, 8, 65.0, 0)
+    cand, _, _, _ = oracle.nndescent(X, 12, 6, 4, 3, stop_updates=0)
+    r = oracle.refine(X, cand, 8)
+    assert np.array_equal(g["ids"], r["ids"]) and np.array_equal(g["cand"], cand)
