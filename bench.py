@@ -35,8 +35,46 @@ WORKLOADS = {
                  gen="uniform_int", desc="uniform-int 10kx128, K=32 R=32 FP32"),
 }
 L_LADDER = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
-PEAK_FP32_VALU_TFLOPS = 157.3
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector and FP32 MFMA (dense)
 PEAK_HBM_GBS = 8000.0
+# HBM traffic of the join measured with rocprofv3 counters; only valid while
+# the join source is the one the counters were taken on (sha256 recorded)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_join_sift1m.md")
+JOIN_SOURCE = os.path.join(ROOT, "paper_2410_01231_amd", "csrc", "knn.hip")
+
+
+def measured_traffic(path_name):
+    """HBM bytes per join launch for this path from the counter summary, or None."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+        sha = hashlib.sha256(open(JOIN_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"join source sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != sha:
+        return None
+    m = re.search(r"^traffic_bytes_per_launch\[" + re.escape(path_name) + r"\]: ([0-9.e+]+)$", text, re.M)
+    return float(m.group(1)) if m else None
+
+
+def roofline(join_path, work, launches, total_ms, name):
+    """Roofline entry of the join kernel: flops or bytes per launch over its mean duration."""
+    avg_ms = total_ms / max(launches, 1)
+    per_launch = work / max(launches, 1)
+    if join_path.endswith("mfma") and join_path.startswith("fp32"):
+        bound, unit, peak, scale = "mfma", "TFLOP/s", PEAK_FP32_TFLOPS, 1e12
+    elif join_path == "fp32-valu":
+        bound, unit, peak, scale = "alu", "TFLOP/s", PEAK_FP32_TFLOPS, 1e12
+    else:
+        bound, unit, peak, scale = "hbm", "GB/s", PEAK_HBM_GBS, 1e9
+    achieved = per_launch / (avg_ms / 1000.0) / scale if launches else 0.0
+    return {"kernel": "join", "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": measured_traffic(name),
+            "work_per_launch": per_launch,
+            "work_unit": "flops" if scale == 1e12 else "bytes",
+            "avg_launch_ms": avg_ms, "launches": launches}
 
 
 def gen_data(w):
@@ -156,10 +194,10 @@ def main():
 
 # join paths: precision code of pg_knn_build, dtype the join computes in
 PATHS = {
-    "fp32": {"precision": 0, "dtype": "f32"},
-    "fp16": {"precision": 1, "dtype": "f16-mfma/f32-acc"},
-    "bf16": {"precision": 2, "dtype": "bf16-mfma/f32-acc"},
-    "fp32-valu": {"precision": 3, "dtype": "f32"},
+    "fp32": {"name": "fp32", "precision": 0, "dtype": "f32"},
+    "fp16": {"name": "fp16", "precision": 1, "dtype": "f16-mfma/f32-acc"},
+    "bf16": {"name": "bf16", "precision": 2, "dtype": "bf16-mfma/f32-acc"},
+    "fp32-valu": {"name": "fp32-valu", "precision": 3, "dtype": "f32"},
 }
 
 
@@ -233,8 +271,6 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
     s1.synchronize()
     qps = Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)
 
-    avg_join_ms = join_ms / max(join_n, 1)
-    achieved = (join_work / max(join_n, 1)) / (avg_join_ms / 1000.0) / 1e12 if join_n else 0.0
     return {
         "points_per_s": n * args.steps / elapsed,
         "ms_per_step": 1000.0 * elapsed / args.steps,
@@ -245,11 +281,7 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         "query_latency_ms_batch1": {"p50": float(np.percentile(lat, 50)),
                                     "p99": float(np.percentile(lat, 99))},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_.items()},
-        "roofline": {"kernel": "join", "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
-                     "work_per_launch": join_work / max(join_n, 1),
-                     "avg_launch_ms": avg_join_ms, "launches": join_n},
+        "roofline": roofline(st["join_path"], join_work, join_n, join_ms, path["name"]),
     }
 
 

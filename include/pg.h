@@ -96,7 +96,9 @@ pg_status pg_ctx_destroy(pg_ctx *ctx);
  * bracketed by HIP events on the context stream.  pg_ctx_kernel_time (host
  * outputs) returns, for kernel `name`, the summed event time in ms, the number
  * of launches, and the summed algorithmic work of those launches (flops for
- * the distance kernels, bytes for the others, as documented per kernel).
+ * the distance kernels, bytes for the others, as documented per kernel;
+ * "join": 3 d flops per pair on the FP32 direct path, 2 d per pair on the
+ * FP32 MFMA path, 2 d16 bytes per join-set member row on the 16-bit paths).
  * Reading the times synchronises the stream.  Names: "join", "merge", "init",
  * "sample", "prune", "search", "exact_knn", and "connect" (the whole connect
  * step of pg_prune as one region: several launches and host synchronisations). */
@@ -152,6 +154,7 @@ typedef struct {
     int64_t retries;       /* extra join passes: a node's bucket and the spill list were full */
     int64_t spilled;       /* proposals that went past their node's bucket to the spill list */
     int64_t rechecked[64]; /* mixed precision: pairs recomputed in the direct form */
+    int64_t members[64];   /* join-set members of the joining sources (rows gathered) */
 } pg_knn_stats;
 
 /* Workspace bytes needed by pg_knn_build for these sizes (host output). */
@@ -231,16 +234,24 @@ pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ld
 /* Beam search (Alg. 1)                                                */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    int32_t k;                /* results per query, 1 <= k <= L */
-    int32_t L;                /* pool width, L <= 1024 */
-    int32_t n_entry;          /* number of entering points, >= 1 */
-    const int32_t *entry_ids; /* device, n_entry ids (repeats dropped) */
+    int32_t k;                  /* results per query, 1 <= k <= L (k < L with exclude) */
+    int32_t L;                  /* pool width, L <= 1024 */
+    int32_t n_entry;            /* number of shared entering points, >= 1 */
+    const int32_t *entry_ids;   /* device, n_entry ids (repeats dropped) */
+    const int32_t *query_entry; /* optional, device, nq ids: query q enters at
+                                   query_entry[q] alone (entry_ids unused) */
+    const int32_t *exclude;     /* optional, device, nq ids: query q returns the
+                                   first k pool entries other than exclude[q]
+                                   (the search itself still passes through it) */
 } pg_search_params;
 
 /* KANNSearch of Alg. 1 for every query row, starting from the entering
  * points: the pool keeps the L closest by (d2, id); the closest unexpanded
  * entry is expanded until the first min(L, |pool|) are expanded.
- * g_ids is n x R with degrees g_deg.  out_ids / out_d2 are nq x k. */
+ * g_ids is n x R with degrees g_deg.  out_ids / out_d2 are nq x k, padded
+ * with -1 / +inf.  With Q = X, query_entry[u] = u and exclude[u] = u this is
+ * the search phase of OptKCNA (Alg. 5, Phase 3): KANNSearch(G, u, k, L, u),
+ * u not being its own candidate. */
 pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
                     const int32_t *g_ids, int32_t R, const int32_t *g_deg,
                     const float *Q, int64_t nq, int64_t ldq,

@@ -37,7 +37,56 @@
 
 namespace pgi {
 
-enum { C_UPDATES = 0, C_PROPOSALS = 1, C_OVF = 2, C_PAIRS = 3, C_SPILL = 4, C_RECHECK = 5, C_NCOUNTERS = 8 };
+enum {
+    C_UPDATES = 0,
+    C_PROPOSALS = 1,
+    C_OVF = 2,
+    C_PAIRS = 3,
+    C_SPILL = 4,
+    C_RECHECK = 5,
+    C_MEMBERS = 6,  // join-set members of the sources that join (rows each join gathers)
+    C_NCOUNTERS = 8
+};
+
+// Counters are striped: NSTRIPE slots of CSTRIDE words (one 128-byte line
+// each), and a workgroup adds to slot blockIdx.x % NSTRIPE.  Device-scope
+// atomics on one address from every XCD serialize; spread over lines they do
+// not.  The spill list is cut into NSTRIPE segments of `seg` entries the same
+// way, each filled through the C_SPILL word of its slot.
+constexpr int NSTRIPE = 256;
+constexpr int CSTRIDE = 16;
+enum { C_SPILLMAX = 7 };  // reduced view only: largest (clipped) segment fill
+
+__device__ __forceinline__ unsigned long long *stripe_of(unsigned long long *c) {
+    return c + (blockIdx.x % NSTRIPE) * CSTRIDE;
+}
+
+// out[f] = sum over slots of field f; C_SPILL counts stored entries (each
+// segment clipped at seg) and C_SPILLMAX the largest clipped fill.  One block
+// of NSTRIPE threads.
+__global__ __launch_bounds__(NSTRIPE) void k_counters_reduce(const unsigned long long *__restrict__ c, int64_t seg,
+                                                             unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long sh[C_NCOUNTERS][NSTRIPE];
+    const int t = threadIdx.x;
+    for (int f = 0; f < C_NCOUNTERS; ++f) {
+        unsigned long long v = c[t * CSTRIDE + f];
+        if (f == C_SPILL) v = min(v, (unsigned long long)seg);
+        if (f == C_SPILLMAX) v = min(c[t * CSTRIDE + C_SPILL], (unsigned long long)seg);
+        sh[f][t] = v;
+    }
+    __syncthreads();
+    for (int o = NSTRIPE / 2; o > 0; o >>= 1) {
+        if (t < o)
+            for (int f = 0; f < C_NCOUNTERS; ++f)
+                sh[f][t] = f == C_SPILLMAX ? max(sh[f][t], sh[f][t + o]) : sh[f][t] + sh[f][t + o];
+        __syncthreads();
+    }
+    if (t < C_NCOUNTERS) out[t] = sh[t][0];
+}
+
+__global__ __launch_bounds__(NSTRIPE) void k_counters_clear(unsigned long long *__restrict__ c, int field) {
+    c[threadIdx.x * CSTRIDE + field] = 0ull;
+}
 
 // ---------------------------------------------------------------------------
 // init: K distinct random neighbours, hash4(seed, 0, u, attempt) mod (n-1)
@@ -193,12 +242,12 @@ __global__ __launch_bounds__(256) void k_build_join(
     const int64_t *__restrict__ ro_off, const int32_t *__restrict__ ro_list,
     int32_t *__restrict__ jn, int32_t *__restrict__ jn_c, int JN, int32_t *__restrict__ jo,
     int32_t *__restrict__ jo_c, int JO, unsigned long long *__restrict__ counters) {
-    __shared__ unsigned long long pairs_s[4];
+    __shared__ unsigned long long pairs_s[4], memb_s[4];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
-    const int64_t v = (int64_t)blockIdx.x * 4 + w;
-    unsigned long long pairs = 0;
-    if (v < n) {
+    unsigned long long pairs = 0, memb = 0;
+    // grid-stride over nodes, one wave each; one counter atomic per block
+    for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4) {
         const uint64_t rsel = select_reverse(v, rn_off, rn_list, seed, stream_rn);
         const uint64_t osel = select_reverse(v, ro_off, ro_list, seed, stream_ro);
         // new set (|new_f| <= S and |Rnew| <= S, S <= 32: one id per lane)
@@ -236,14 +285,21 @@ __global__ __launch_bounds__(256) void k_build_join(
         if (lane == 0) {
             jn_c[v] = nn;
             jo_c[v] = ca + cb;
-            pairs = (unsigned long long)nn * (nn - 1) / 2 + (unsigned long long)nn * (ca + cb);
+            pairs += (unsigned long long)nn * (nn - 1) / 2 + (unsigned long long)nn * (ca + cb);
+            memb += (nn > 0 && nn + ca + cb >= 2) ? (unsigned long long)(nn + ca + cb) : 0ull;
         }
     }
-    if (lane == 0) pairs_s[w] = pairs;
+    if (lane == 0) {
+        pairs_s[w] = pairs;
+        memb_s[w] = memb;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long t = pairs_s[0] + pairs_s[1] + pairs_s[2] + pairs_s[3];
-        if (t) atomicAdd(&counters[C_PAIRS], t);
+        const unsigned long long mm = memb_s[0] + memb_s[1] + memb_s[2] + memb_s[3];
+        unsigned long long *cs = stripe_of(counters);
+        if (t) atomicAdd(&cs[C_PAIRS], t);
+        if (mm) atomicAdd(&cs[C_MEMBERS], mm);
     }
 }
 
@@ -263,9 +319,10 @@ __device__ __forceinline__ bool list_has(const uint64_t *__restrict__ row, int K
     return lo < K && row[lo] == key;
 }
 
-// Proposals beyond their node's bucket go to the shared spill list (a
-// range reserved per member of the join set); when that is full too, the
-// node is marked for a repeat pass.
+// Proposals beyond their node's bucket go to the workgroup's spill segment
+// (a range reserved per member of the join set; cap = the segment end); when
+// that is full too, the node is marked for a repeat pass.  `counters` is the
+// workgroup's counter slot.
 __device__ __forceinline__ void spill_put(int32_t t, uint64_t key, int64_t pos,
                                           int32_t *__restrict__ spill_t,
                                           uint64_t *__restrict__ spill_k, int64_t cap,
@@ -282,11 +339,12 @@ __device__ __forceinline__ void spill_put(int32_t t, uint64_t key, int64_t pos,
 
 // Reserve this wave's bucket ranges for members i = lane + 64 j: one global
 // atomic per member on its proposal counter, and one per wave and j on the
-// spill counter for the parts that do not fit in the buckets.
+// fill counter of the workgroup's spill segment for the parts that do not fit
+// in the buckets.
 __device__ __forceinline__ unsigned long long reserve_ranges(
     int m, const int32_t *__restrict__ ids, int32_t *__restrict__ cnt, int32_t *__restrict__ base,
     int64_t *__restrict__ sbase, int32_t *__restrict__ pcnt, int B,
-    unsigned long long *__restrict__ counters) {
+    unsigned long long *__restrict__ cslot, int64_t seg_begin) {
     const int lane = lane_id();
     unsigned long long props = 0;
     for (int j0 = 0; j0 < m; j0 += PG_WAVE) {
@@ -312,26 +370,38 @@ __device__ __forceinline__ unsigned long long reserve_ranges(
         const int total = __shfl(incl, PG_WAVE - 1, PG_WAVE);
         unsigned long long sb = 0;
         if (total > 0) {
-            if (lane == PG_WAVE - 1) sb = atomicAdd(&counters[C_SPILL], (unsigned long long)total);
+            if (lane == PG_WAVE - 1) sb = atomicAdd(&cslot[C_SPILL], (unsigned long long)total);
             sb = (unsigned long long)__shfl((long long)sb, PG_WAVE - 1, PG_WAVE);
         }
-        if (over > 0) sbase[i] = (int64_t)(sb + (unsigned long long)(incl - over));
+        if (over > 0) sbase[i] = seg_begin + (int64_t)(sb + (unsigned long long)(incl - over));
     }
     return props;
 }
 
-__global__ void k_spill_count(const int32_t *__restrict__ spill_t, int64_t cnt,
-                              int32_t *__restrict__ scnt) {
+// ids per value (counting sort of small integer keys)
+__global__ void k_count_ids(const int32_t *__restrict__ key, int64_t cnt, int32_t *__restrict__ kcnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) atomicAdd(&scnt[spill_t[i]], 1);
+    if (i < cnt) atomicAdd(&kcnt[key[i]], 1);
 }
 
-__global__ void k_spill_scatter(const int32_t *__restrict__ spill_t,
-                                const uint64_t *__restrict__ spill_k, int64_t cnt,
+// spilled entries per target node, over every segment (grid.y = segment)
+__global__ void k_spill_count(const int32_t *__restrict__ spill_t, const unsigned long long *__restrict__ c,
+                              int64_t seg, int32_t *__restrict__ scnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = blockIdx.y;
+    const int64_t fill = min((int64_t)c[s * CSTRIDE + C_SPILL], seg);
+    if (j < fill) atomicAdd(&scnt[spill_t[s * seg + j]], 1);
+}
+
+__global__ void k_spill_scatter(const int32_t *__restrict__ spill_t, const uint64_t *__restrict__ spill_k,
+                                const unsigned long long *__restrict__ c, int64_t seg,
                                 const int64_t *__restrict__ soff, int32_t *__restrict__ scur,
                                 uint64_t *__restrict__ sorted) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = blockIdx.y;
+    const int64_t fill = min((int64_t)c[s * CSTRIDE + C_SPILL], seg);
+    if (j < fill) {
+        const int64_t i = s * seg + j;
         const int32_t t = spill_t[i];
         sorted[soff[t] + atomicAdd(&scur[t], 1)] = spill_k[i];
     }
@@ -371,7 +441,7 @@ __global__ __launch_bounds__(JT) void k_join(
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
     const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
     int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
-    int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t spill_cap,
+    int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t seg,
     uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, const int32_t *__restrict__ order,
     int64_t n, PassRange pr, int maxm, unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -382,6 +452,8 @@ __global__ __launch_bounds__(JT) void k_join(
     const int64_t lb = xcd_logical_block(blockIdx.x, nlog);
     const int64_t u = lb < nlog ? pass_source(order, n, pr, lb * JW + wv) : -1;
     if (u < 0) return;
+    unsigned long long *cslot = stripe_of(counters);
+    const int64_t seg_begin = (int64_t)(blockIdx.x % NSTRIPE) * seg, seg_end = seg_begin + seg;
     unsigned char *region = smem + (size_t)wv * join_wave_lds(maxm);
     float *tile = reinterpret_cast<float *>(region);
     uint64_t *kth = reinterpret_cast<uint64_t *>(tile + (size_t)JDC * MPS);
@@ -500,7 +572,7 @@ __global__ __launch_bounds__(JT) void k_join(
             }
         }
         __builtin_amdgcn_wave_barrier();
-        local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, counters);
+        local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
         __builtin_amdgcn_wave_barrier();
         if (brb >= 0) {
 #pragma unroll
@@ -520,7 +592,7 @@ __global__ __launch_bounds__(JT) void k_join(
                             bucket[(int64_t)v * B + slot] = kw;
                         else
                             spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k,
-                                      spill_cap, ovf_next, counters);
+                                      seg_end, ovf_next, cslot);
                     }
                     if (to_col & bit) {
                         const int32_t w = ids[col];
@@ -530,7 +602,7 @@ __global__ __launch_bounds__(JT) void k_join(
                             bucket[(int64_t)w * B + slot] = kv;
                         else
                             spill_put(w, kv, sbase[col] + (slot - max(base[col], B)), spill_t, spill_k,
-                                      spill_cap, ovf_next, counters);
+                                      seg_end, ovf_next, cslot);
                     }
                 }
             }
@@ -543,7 +615,7 @@ __global__ __launch_bounds__(JT) void k_join(
         const unsigned long long t = __shfl_xor((long long)local_props, o, PG_WAVE);
         local_props += t;
     }
-    if (lane == 0 && local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
+    if (lane == 0 && local_props) atomicAdd(&cslot[C_PROPOSALS], local_props);
 }
 
 // ---------------------------------------------------------------------------
@@ -774,7 +846,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
     const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
     int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
-    int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t spill_cap,
+    int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t seg,
     uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, const int32_t *__restrict__ order,
     int64_t n, PassRange pr, int maxm, MixedParams mx, unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -785,6 +857,8 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
     const int64_t lb = xcd_logical_block(blockIdx.x, nlog);
     const int64_t u = lb < nlog ? pass_source(order, n, pr, lb * MW + wv) : -1;
     if (u < 0) return;
+    unsigned long long *cslot = stripe_of(counters);
+    const int64_t seg_begin = (int64_t)(blockIdx.x % NSTRIPE) * seg, seg_end = seg_begin + seg;
     unsigned char *region = smem + (size_t)wv * MPS * (8 + 8 + 4 + 4 + 4 + 4 + 4);
     uint64_t *kth = reinterpret_cast<uint64_t *>(region);
     int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
@@ -864,7 +938,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
                 if (c_c) off_col = atomicAdd(&cnt[cm], c_c);
             }
             __builtin_amdgcn_wave_barrier();
-            local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, counters);
+            local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -879,8 +953,8 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
                     if (slot < B)
                         bucket[(int64_t)v * B + slot] = kw;
                     else
-                        spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k, spill_cap,
-                                  ovf_next, counters);
+                        spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k, seg_end,
+                                  ovf_next, cslot);
                 }
                 if (to_col & bit) {
                     const int32_t w = ids[cm];
@@ -889,8 +963,8 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
                     if (slot < B)
                         bucket[(int64_t)w * B + slot] = kv;
                     else
-                        spill_put(w, kv, sbase[cm] + (slot - max(base[cm], B)), spill_t, spill_k, spill_cap,
-                                  ovf_next, counters);
+                        spill_put(w, kv, sbase[cm] + (slot - max(base[cm], B)), spill_t, spill_k, seg_end,
+                                  ovf_next, cslot);
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -901,8 +975,8 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
         local_props += (unsigned long long)__shfl_xor((long long)local_props, o, PG_WAVE);
         local_rechk += (unsigned long long)__shfl_xor((long long)local_rechk, o, PG_WAVE);
     }
-    if (lane == 0 && local_props) atomicAdd(&counters[C_PROPOSALS], local_props);
-    if (lane == 0 && local_rechk) atomicAdd(&counters[C_RECHECK], local_rechk);
+    if (lane == 0 && local_props) atomicAdd(&cslot[C_PROPOSALS], local_props);
+    if (lane == 0 && local_rechk) atomicAdd(&cslot[C_RECHECK], local_rechk);
 }
 
 static size_t join_mfma_lds_bytes(int maxm) {
@@ -980,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_count_updates(uint64_t *__restrict__ in
         if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && s[0]) atomicAdd(&counters[C_UPDATES], s[0]);
+    if (threadIdx.x == 0 && s[0]) atomicAdd(&stripe_of(counters)[C_UPDATES], s[0]);
 }
 
 __global__ void k_unpack(const uint64_t *__restrict__ keys, int64_t total,
@@ -1172,9 +1246,9 @@ static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d) {
     L.bucket = take(sizeof(uint64_t) * n * (size_t)L.B);
     L.mark = take(n);
     L.mark_next = take(n);
-    L.counters = take(sizeof(unsigned long long) * C_NCOUNTERS);
+    L.counters = take(sizeof(unsigned long long) * (NSTRIPE * CSTRIDE + C_NCOUNTERS));
     L.scan_tmp = take(scan_tmp_bytes(n + 1));
-    L.spill_cap = std::max<int64_t>(1 << 16, n * K / 2);
+    L.spill_cap = (std::max<int64_t>(1 << 16, n * K / 2) + NSTRIPE - 1) / NSTRIPE * NSTRIPE;
     L.spill_t = take(sizeof(int32_t) * L.spill_cap);
     L.spill_k = take(sizeof(uint64_t) * L.spill_cap);
     L.spill_s = take(sizeof(uint64_t) * L.spill_cap);
@@ -1325,6 +1399,8 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
     int32_t *spill_t = (int32_t *)(w + L.spill_t);
     uint64_t *spill_k = (uint64_t *)(w + L.spill_k), *spill_s = (uint64_t *)(w + L.spill_s);
     unsigned long long *counters = (unsigned long long *)(w + L.counters);
+    unsigned long long *csum = counters + NSTRIPE * CSTRIDE;  // reduced view
+    const int64_t seg = L.spill_cap / NSTRIPE;                // spill entries per segment
     void *scan_tmp = w + L.scan_tmp;
     hipStream_t st = ctx->stream;
     const int K = p->K, S = p->S;
@@ -1411,7 +1487,7 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
             float *pd2 = (float *)jo;
             PG_TRY(launch_exact(ctx, X, P, d, step * ldx, X, n, ldx, nullptr, 0, 1, piv, pd2));
             PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * P, st));
-            hipLaunchKernelGGL(k_spill_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, piv, n,
+            hipLaunchKernelGGL(k_count_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, piv, n,
                                rn_cnt);
             PG_TRY(scan_exclusive(ctx, rn_cnt, rn_off, P, scan_tmp));
             PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * P, st));
@@ -1425,7 +1501,7 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
     int iters = 0;
     int64_t prev_props = -1;
     for (int t = 1; t <= p->max_iters; ++t) {
-        PG_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * C_NCOUNTERS, st));
+        PG_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * (NSTRIPE * CSTRIDE + C_NCOUNTERS), st));
         PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
         PG_HIP(hipMemsetAsync(ro_cnt, 0, sizeof(int32_t) * n, st));
         {
@@ -1441,7 +1517,8 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         hipLaunchKernelGGL(k_rev_scatter, dim3(wave_blocks), dim3(256), 0, st, n, nf, nf_c, S, of,
                            of_c, K, rn_off, rn_cnt, rn_list, ro_off, ro_cnt, ro_list);
         PG_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_build_join, dim3(wave_blocks), dim3(256), 0, st, n, K, S, p->seed,
+        hipLaunchKernelGGL(k_build_join, dim3(std::min<unsigned>(wave_blocks, 8192)), dim3(256), 0, st, n, K, S,
+                           p->seed,
                            (uint64_t)(3 * t + 1), (uint64_t)(3 * t + 2), nf, nf_c, of, of_c, rn_off,
                            rn_list, ro_off, ro_list, jn, jn_c, L.JN, jo, jo_c, L.JO, counters);
         PG_HIP(hipGetLastError());
@@ -1482,51 +1559,52 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                     if (path == PG_JOIN_VALU)
                         hipLaunchKernelGGL(k_join, dim3(xcd_grid((pr.items + JW - 1) / JW)), dim3(JT), lds, st,
                                            X, ldx, d, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt, bucket,
-                                           L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, counters);
                     else if (path == PG_JOIN_MFMA_FP32)
                         hipLaunchKernelGGL((k_join_mfma<PG_FP32, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
                                            x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
-                                           pcnt, bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk,
+                                           pcnt, bucket, L.B, spill_t, spill_k, seg, mark_next, mk,
                                            order, n, pr, maxm, mx, counters);
                     else if (path == PG_JOIN_MFMA_FP16)
                         hipLaunchKernelGGL((k_join_mfma<PG_FP16, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
-                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, mx, counters);
                     else if (path == PG_JOIN_MFMA_BF16)
                         hipLaunchKernelGGL((k_join_mfma<PG_BF16, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
-                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, mx, counters);
                     else if (path == PG_JOIN_MIXED_FP16)
                         hipLaunchKernelGGL((k_join_mfma<PG_FP16, true>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
-                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, mx, counters);
                     else
                         hipLaunchKernelGGL((k_join_mfma<PG_BF16, true>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
-                                           bucket, L.B, spill_t, spill_k, L.spill_cap, mark_next, mk, order, n, pr,
+                                           bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, mx, counters);
                     PG_HIP(hipGetLastError());
                 }
                 unsigned long long hc2[C_NCOUNTERS];
-                PG_HIP(hipMemcpyAsync(hc2, counters, sizeof(hc2), hipMemcpyDeviceToHost, st));
+                hipLaunchKernelGGL(k_counters_reduce, dim3(1), dim3(NSTRIPE), 0, st, counters, seg, csum);
+                PG_HIP(hipMemcpyAsync(hc2, csum, sizeof(hc2), hipMemcpyDeviceToHost, st));
                 PG_HIP(hipStreamSynchronize(st));
-                const int64_t nsp = std::min<int64_t>((int64_t)hc2[C_SPILL], L.spill_cap);
+                const int64_t nsp = (int64_t)hc2[C_SPILL];
                 const int64_t *soff = nullptr;
                 if (nsp > 0) {
-                    // group the spilled proposals by node (counting sort)
-                    const unsigned sb = (unsigned)((nsp + 255) / 256);
+                    // group the spilled proposals by node (counting sort over every segment)
+                    const dim3 sg((unsigned)((hc2[C_SPILLMAX] + 255) / 256), NSTRIPE);
                     PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
-                    hipLaunchKernelGGL(k_spill_count, dim3(sb), dim3(256), 0, st, spill_t, nsp, rn_cnt);
+                    hipLaunchKernelGGL(k_spill_count, sg, dim3(256), 0, st, spill_t, counters, seg, rn_cnt);
                     PG_TRY(scan_exclusive(ctx, rn_cnt, rn_off, n, scan_tmp));
                     PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
-                    hipLaunchKernelGGL(k_spill_scatter, dim3(sb), dim3(256), 0, st, spill_t, spill_k, nsp,
-                                       rn_off, rn_cnt, spill_s);
+                    hipLaunchKernelGGL(k_spill_scatter, sg, dim3(256), 0, st, spill_t, spill_k, counters, seg, rn_off,
+                                       rn_cnt, spill_s);
+                    hipLaunchKernelGGL(k_counters_clear, dim3(1), dim3(NSTRIPE), 0, st, counters, (int)C_SPILL);
                     PG_HIP(hipGetLastError());
-                    PG_HIP(hipMemsetAsync(counters + C_SPILL, 0, sizeof(unsigned long long), st));
                     soff = rn_off;
                     if (stats) stats->spilled += nsp;
                 }
@@ -1542,7 +1620,7 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                     return PG_EOVERFLOW;
                 }
                 if (stats) stats->retries++;
-                PG_HIP(hipMemsetAsync(counters + C_OVF, 0, sizeof(unsigned long long), st));
+                hipLaunchKernelGGL(k_counters_clear, dim3(1), dim3(NSTRIPE), 0, st, counters, (int)C_OVF);
                 hipLaunchKernelGGL(k_mark_swap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                                    mark, mark_next, n);
                 PG_HIP(hipGetLastError());
@@ -1553,7 +1631,8 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                            n, counters);
         PG_HIP(hipGetLastError());
         unsigned long long hc[C_NCOUNTERS];
-        PG_HIP(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_counters_reduce, dim3(1), dim3(NSTRIPE), 0, st, counters, seg, csum);
+        PG_HIP(hipMemcpyAsync(hc, csum, sizeof(hc), hipMemcpyDeviceToHost, st));
         PG_HIP(hipStreamSynchronize(st));
         iters = t;
         prev_props = (int64_t)hc[C_PROPOSALS];
@@ -1562,8 +1641,16 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
             stats->pairs[t - 1] = (int64_t)hc[C_PAIRS];
             stats->proposals[t - 1] = (int64_t)hc[C_PROPOSALS];
             stats->rechecked[t - 1] = (int64_t)hc[C_RECHECK];
+            stats->members[t - 1] = (int64_t)hc[C_MEMBERS];
         }
-        ctx_add_work(ctx, K_JOIN, 3.0 * (double)hc[C_PAIRS] * d);
+        // algorithmic work of the joins: flops of the distance form for the
+        // FP32 paths, bytes of 16-bit row gathers for the 16-bit ones
+        if (path == PG_JOIN_VALU)
+            ctx_add_work(ctx, K_JOIN, 3.0 * (double)hc[C_PAIRS] * d);
+        else if (path == PG_JOIN_MFMA_FP32)
+            ctx_add_work(ctx, K_JOIN, 2.0 * (double)hc[C_PAIRS] * d);
+        else
+            ctx_add_work(ctx, K_JOIN, 2.0 * (double)hc[C_MEMBERS] * L.d16);
         if ((int64_t)hc[C_UPDATES] <= p->stop_updates) break;
     }
     if (stats) stats->iters_run = iters;

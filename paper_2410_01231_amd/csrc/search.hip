@@ -35,8 +35,10 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
                                                int64_t n, const int32_t *__restrict__ g, int R,
                                                const int32_t *__restrict__ deg,
                                                const float *__restrict__ Q, int64_t ldq, int64_t nq,
-                                               const int32_t *__restrict__ entries, int n_entry, int k,
-                                               int L, int32_t *__restrict__ out_ids,
+                                               const int32_t *__restrict__ entries, int n_entry,
+                                               const int32_t *__restrict__ query_entry,
+                                               const int32_t *__restrict__ exclude, int k, int L,
+                                               int32_t *__restrict__ out_ids,
                                                float *__restrict__ out_d2) {
     extern __shared__ __align__(16) unsigned char smem[];
     float *qv = reinterpret_cast<float *>(smem);
@@ -99,7 +101,10 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
         return cm;
     };
 
-    for (int b = 0; b < n_entry; b += PG_WAVE) prepare(b + lane < n_entry ? entries[b + lane] : -1);
+    if (query_entry)
+        prepare(lane == 0 ? query_entry[qi] : -1);
+    else
+        for (int b = 0; b < n_entry; b += PG_WAVE) prepare(b + lane < n_entry ? entries[b + lane] : -1);
 
     while (true) {
         int first = 0x7fffffff;
@@ -119,10 +124,20 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
         const int dx = min(deg[x], R);
         for (int b = 0; b < dx; b += PG_WAVE) prepare(b + lane < dx ? g[(int64_t)x * R + b + lane] : -1);
     }
+    // position of the excluded node in the pool (it appears at most once)
+    int skip = 0x7fffffff;
+    if (exclude) {
+        const int32_t ex = exclude[qi];
+        for (int p = lane; p < size; p += PG_WAVE)
+            if (key_id(pa[p]) == ex) skip = p;
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) skip = min(skip, __shfl_xor(skip, o, PG_WAVE));
+    }
     for (int j = lane; j < k; j += PG_WAVE) {
-        const bool have = j < size;
-        out_ids[qi * k + j] = have ? key_id(pa[j]) : -1;
-        out_d2[qi * k + j] = have ? key_d2(pa[j]) : __int_as_float(0x7f800000);
+        const int p = j + (j >= skip ? 1 : 0);
+        const bool have = p < size;
+        out_ids[qi * k + j] = have ? key_id(pa[p]) : -1;
+        out_d2[qi * k + j] = have ? key_d2(pa[p]) : __int_as_float(0x7f800000);
     }
 }
 
@@ -134,7 +149,8 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
                                const int32_t *g_ids, int32_t R, const int32_t *g_deg, const float *Q,
                                int64_t nq, int64_t ldq, const pg_search_params *p, int32_t *out_ids,
                                float *out_d2) {
-    if (!ctx || !X || !g_ids || !g_deg || !Q || !p || !out_ids || !out_d2 || !p->entry_ids) {
+    if (!ctx || !X || !g_ids || !g_deg || !Q || !p || !out_ids || !out_d2 ||
+        (!p->entry_ids && !p->query_entry)) {
         set_error("pg_search: NULL argument");
         return PG_EINVAL;
     }
@@ -142,9 +158,13 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         set_error("pg_search: bad sizes n=%lld nq=%lld d=%d R=%d", (long long)n, (long long)nq, d, R);
         return PG_EINVAL;
     }
-    if (p->L < 1 || p->L > 1024 || p->k < 1 || p->k > p->L || p->n_entry < 1) {
+    if (p->L < 1 || p->L > 1024 || p->k < 1 || p->k > p->L || (!p->query_entry && p->n_entry < 1)) {
         set_error("pg_search: need 1 <= k <= L <= 1024 and n_entry >= 1 (k=%d L=%d n_entry=%d)", p->k,
                   p->L, p->n_entry);
+        return PG_EINVAL;
+    }
+    if (p->exclude && p->k >= p->L) {
+        set_error("pg_search: with exclude, k=%d must be below L=%d", p->k, p->L);
         return PG_EINVAL;
     }
     if (d % 4 || ldx % 4 || ((uintptr_t)X & 15) || d > 8192) {
@@ -156,7 +176,8 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
                        2 * (size_t)p->L;
     TimedLaunch tl(ctx, K_SEARCH, -1.0);
     hipLaunchKernelGGL(k_search, dim3((unsigned)nq), dim3(64), lds, ctx->stream, X, ldx, d, n, g_ids, R,
-                       g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->k, p->L, out_ids, out_d2);
+                       g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry, p->exclude, p->k, p->L,
+                       out_ids, out_d2);
     PG_HIP(hipGetLastError());
     return PG_OK;
 }

@@ -39,7 +39,7 @@ class KnnParams(ctypes.Structure):
 class KnnStats(ctypes.Structure):
     _fields_ = [("iters_run", c_int32), ("join_path", c_int32), ("updates", c_int64 * 64),
                 ("pairs", c_int64 * 64), ("proposals", c_int64 * 64), ("retries", c_int64),
-                ("spilled", c_int64), ("rechecked", c_int64 * 64)]
+                ("spilled", c_int64), ("rechecked", c_int64 * 64), ("members", c_int64 * 64)]
 
 
 class PruneParams(ctypes.Structure):
@@ -48,7 +48,8 @@ class PruneParams(ctypes.Structure):
 
 
 class SearchParams(ctypes.Structure):
-    _fields_ = [("k", c_int32), ("L", c_int32), ("n_entry", c_int32), ("entry_ids", c_void_p)]
+    _fields_ = [("k", c_int32), ("L", c_int32), ("n_entry", c_int32), ("entry_ids", c_void_p),
+                ("query_entry", c_void_p), ("exclude", c_void_p)]
 
 
 EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
@@ -191,6 +192,7 @@ def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001
     it = st.iters_run
     stats = {"iters": it, "updates": list(st.updates[:it]), "pairs": list(st.pairs[:it]),
              "proposals": list(st.proposals[:it]), "rechecked": list(st.rechecked[:it]),
+             "members": list(st.members[:it]),
              "retries": st.retries,
              "spilled": st.spilled, "join_path": JOIN_PATHS.get(st.join_path, st.join_path)}
     return ids, d2, stats
@@ -250,22 +252,68 @@ def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair
     return {"ids": g_ids, "d2": g_d2, "deg": g_deg, "ep": ep, "roots": roots[:nroots.value]}
 
 
-def search(X, g_ids, g_deg, Q, entries, k, L, ctx=None):
-    """Alg. 1 beam search for every row of Q: returns (ids, d2)."""
+def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, ctx=None):
+    """Alg. 1 beam search for every row of Q: returns (ids, d2).
+
+    entries: shared entering points; query_entry (nq ids, optional) gives each
+    query its own single entering point instead; exclude (nq ids, optional)
+    leaves one node out of each query's results."""
     lib = load_library()
     X, Q = _dev_f32(X, "X"), _dev_f32(Q, "Q")
     g_ids, g_deg = _dev_i32(g_ids, "g_ids"), _dev_i32(g_deg, "g_deg")
-    entries = _dev_i32(entries.reshape(-1), "entries")
     n, d = X.shape
     nq = Q.shape[0]
+    if entries is not None:
+        entries = _dev_i32(entries.reshape(-1), "entries")
+    if query_entry is not None:
+        query_entry = _dev_i32(query_entry.reshape(-1), "query_entry")
+        if query_entry.numel() != nq:
+            raise ValueError("query_entry needs one id per query")
+    if exclude is not None:
+        exclude = _dev_i32(exclude.reshape(-1), "exclude")
+        if exclude.numel() != nq:
+            raise ValueError("exclude needs one id per query")
     ids = torch.empty((nq, k), dtype=torch.int32, device=X.device)
     d2 = torch.empty((nq, k), dtype=torch.float32, device=X.device)
-    p = SearchParams(k=k, L=L, n_entry=entries.numel(), entry_ids=entries.data_ptr())
+    p = SearchParams(k=k, L=L, n_entry=entries.numel() if entries is not None else 0,
+                     entry_ids=entries.data_ptr() if entries is not None else None,
+                     query_entry=query_entry.data_ptr() if query_entry is not None else None,
+                     exclude=exclude.data_ptr() if exclude is not None else None)
     ctx = ctx or context(X.device.index)
     _check(lib.pg_search(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(g_ids), g_ids.shape[1],
                          _ptr(g_deg), _ptr(Q), nq, Q.stride(0), ctypes.byref(p), _ptr(ids), _ptr(d2)),
            "pg_search")
     return ids, d2
+
+
+def search_self(X, g_ids, g_deg, k, L, ctx=None):
+    """Search phase of OptKCNA (Alg. 5): KANNSearch(G, u, k, L, u) for every
+    point u, u not being its own candidate.  Returns (ids, d2), n x k."""
+    n = X.shape[0]
+    selfid = torch.arange(n, dtype=torch.int32, device=X.device)
+    return search(X, g_ids, g_deg, X, None, k, L, query_entry=selfid, exclude=selfid, ctx=ctx)
+
+
+def opt_kcna(X, cand, k, L, M, alpha_deg, cand_d2=None, ctx=None):
+    """OptKCNA (Alg. 5): the alpha-PG of the candidate lists (prune with M and
+    alpha, reverse re-prune, connect), then a search from every point on it.
+    Returns the new candidate lists (ids, d2), n x k."""
+    g = prune(X, cand, M, alpha_deg=alpha_deg, cand_d2=cand_d2, ctx=ctx)
+    return search_self(X, g["ids"], g["deg"], k, L, ctx=ctx)
+
+
+def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0, delta=0.001,
+             ctx=None, **knn_kw):
+    """IterNSG (Alg. 6) with a fixed number of OptKCNA rounds: NN-Descent lists,
+    `iterations` rounds of OptKCNA with angle alpha_deg, then the refinement of
+    Alg. 2 with RNG pruning.  Returns the graph dict of prune() plus the final
+    candidate lists ("cand", "cand_d2") and the kNN statistics."""
+    cand, cd2, st = knn_build(X, K, S=S, max_iters=max_iters, seed=seed, delta=delta, ctx=ctx, **knn_kw)
+    for _ in range(iterations):
+        cand, cd2 = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, ctx=ctx)
+    g = prune(X, cand, R, cand_d2=cd2, ctx=ctx)
+    g["cand"], g["cand_d2"], g["knn_stats"] = cand, cd2, st
+    return g
 
 
 def build_graph(X, K, R, S=None, max_iters=12, seed=0, delta=0.001, alpha_deg=60.0, ctx=None,

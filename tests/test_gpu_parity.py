@@ -372,3 +372,34 @@ def test_end_to_end_recall_matches_oracle(pg, oracle, datagen):
     rg, ro = oracle.recall_at_k(host(ids), gt), oracle.recall_at_k(rid, gt)
     log("search recall gpu", rg, "oracle", ro)
     assert abs(rg - ro) <= 0.005
+
+
+# ------------------------------------------------- OptKCNA / IterNSG (Alg. 5, 6)
+
+def test_search_self_bit_exact(pg, oracle, datagen):
+    # the search phase of OptKCNA: every point searched for, entering at itself,
+    # itself left out of its own results
+    X, _ = datagen.sift_like(2500, 0, d=32, n_clusters=15, sigma=10.0, seed=42)
+    cand, _ = oracle.exact_knn(X, X, 20, exclude=np.arange(2500))
+    g = oracle.refine(X, cand, 12, alpha_deg=65.0)
+    ids, d2 = pg.search_self(dev(X), dev(g["ids"]), dev(g["deg"]), 16, 40)
+    rid, rd2, _ = oracle.search_self(X, g["ids"], g["deg"], 16, 40)
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d2), rd2.astype(np.float32))
+
+
+@pytest.mark.parametrize("nn,d,nc,sig,K,S,k,L,R,alpha", [
+    (3000, 32, 20, 12.0, 16, 8, 16, 32, 16, 65.0),
+    (2000, 64, 10, 20.0, 24, 12, 24, 40, 20, 62.0),
+])
+def test_iter_nsg_bit_exact(pg, oracle, datagen, nn, d, nc, sig, K, S, k, L, R, alpha):
+    # IterNSG with two OptKCNA rounds, the whole pipeline on integer data
+    X, _ = datagen.sift_like(nn, 0, d=d, n_clusters=nc, sigma=sig, seed=41)
+    stop = int(0.001 * nn * K)
+    g = pg.iter_nsg(dev(X), K, R, k, L, alpha, 2, S=S, max_iters=8, seed=3, stop_updates=stop)
+    r = oracle.iter_nsg(X, K, S, 8, 3, stop, k, L, R, alpha, 2)
+    assert np.array_equal(host(g["cand"]), r["cand"])
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert np.array_equal(host(g["deg"]), r["deg"])
+    assert np.array_equal(host(g["roots"]), r["roots"])
+    assert int(host(g["ep"])[0]) == r["ep"]
