@@ -96,7 +96,9 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
                                               uint64_t *__restrict__ keys,
                                               uint64_t *__restrict__ newm,
                                               uint64_t *__restrict__ insm) {
+    constexpr int IDC = 32, IST = IDC + 4;  // dims per LDS chunk, row stride (floats)
     __shared__ int32_t acc_s[4][PG_WAVE];
+    __shared__ __align__(16) float rows_s[4][(PG_WAVE + 1) * IST];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const int64_t u = (int64_t)blockIdx.x * 4 + w;
@@ -122,8 +124,39 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
         j0 += PG_WAVE;
     }
     const int32_t id = lane < K ? acc[lane] : -1;
+    // canonical chains of u against its K draws: the 64 rows and u's row pass
+    // through LDS in chunks of IDC dimensions (coalesced loads, one read each)
+    float *rs = rows_s[w];
+    float s = 0.0f;
+    for (int c0 = 0; c0 < d; c0 += IDC) {
+        const int vpr = min(IDC, d - c0) / 4;  // float4 per row in this chunk
+        __builtin_amdgcn_wave_barrier();
+        for (int v = lane; v < (PG_WAVE + 1) * vpr; v += PG_WAVE) {
+            const int r = v / vpr, c = (v - r * vpr) * 4;
+            const int64_t rid = r < PG_WAVE ? (r < K ? (int64_t)acc[r] : -1) : u;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (rid >= 0) x = *reinterpret_cast<const float4 *>(X + rid * ldx + c0 + c);
+            *reinterpret_cast<float4 *>(rs + r * IST + c) = x;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (id >= 0) {
+            for (int q = 0; q < 4 * vpr; q += 4) {
+                const float4 x = *reinterpret_cast<const float4 *>(rs + PG_WAVE * IST + q);
+                const float4 y = *reinterpret_cast<const float4 *>(rs + lane * IST + q);
+                float t;
+                t = x.x - y.x;
+                s = fmaf(t, t, s);
+                t = x.y - y.y;
+                s = fmaf(t, t, s);
+                t = x.z - y.z;
+                s = fmaf(t, t, s);
+                t = x.w - y.w;
+                s = fmaf(t, t, s);
+            }
+        }
+    }
     uint64_t key = KEY_INF;
-    if (id >= 0) key = pack_key(dist_chain(X + u * ldx, X + (int64_t)id * ldx, d), id);
+    if (id >= 0) key = pack_key(s, id);
     wave_sort(key);
     if (lane < K) keys[u * K + lane] = key;
     if (lane == 0) {
