@@ -412,6 +412,41 @@ __device__ __forceinline__ unsigned long long reserve_ranges(
 }
 
 // ids per value (counting sort of small integer keys)
+// The same for one member per lane (mi < 0: none), in a single pass.
+__device__ __forceinline__ unsigned long long reserve_lanes(int mi, const int32_t *__restrict__ ids,
+                                                           int32_t *__restrict__ cnt, int32_t *__restrict__ base,
+                                                           int64_t *__restrict__ sbase, int32_t *__restrict__ pcnt,
+                                                           int B, unsigned long long *__restrict__ cslot,
+                                                           int64_t seg_begin) {
+    const int lane = lane_id();
+    unsigned long long props = 0;
+    int over = 0;
+    if (mi >= 0) {
+        const int c = cnt[mi];
+        if (c > 0) {
+            const int b0 = atomicAdd(&pcnt[ids[mi]], c);
+            base[mi] = b0;
+            over = max(0, b0 + c - max(b0, B));
+            props = (unsigned long long)c;
+        }
+        cnt[mi] = 0;
+    }
+    int incl = over;
+#pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1) {
+        const int t = __shfl_up(incl, o, PG_WAVE);
+        if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, PG_WAVE - 1, PG_WAVE);
+    unsigned long long sb = 0;
+    if (total > 0) {
+        if (lane == PG_WAVE - 1) sb = atomicAdd(&cslot[C_SPILL], (unsigned long long)total);
+        sb = (unsigned long long)__shfl((long long)sb, PG_WAVE - 1, PG_WAVE);
+    }
+    if (over > 0) sbase[mi] = seg_begin + (int64_t)(sb + (unsigned long long)(incl - over));
+    return props;
+}
+
 __global__ void k_count_ids(const int32_t *__restrict__ key, int64_t cnt, int32_t *__restrict__ kcnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) atomicAdd(&kcnt[key[i]], 1);
@@ -839,7 +874,7 @@ __device__ __forceinline__ mf_f32x16 gram_tile(const float *__restrict__ X, int6
             }
         }
     } else {
-        constexpr int GK = 8;
+        constexpr int GK = 4;
         typedef typename std::conditional<P == PG_FP16, mf_f16x8, mf_bf16x8>::type vec8;
         typedef typename std::conditional<P == PG_FP16, _Float16, __bf16>::type elem;
         const elem *ra = reinterpret_cast<const elem *>(X16) + (int64_t)rid * d16 + 8 * h;
@@ -873,7 +908,7 @@ constexpr int MW = 4;  // sources (waves) per workgroup in the MFMA join
 // ballots (the 32 lanes of a half share the row), so only one LDS atomic per
 // (row, tile half) and one per (lane, column) are needed.
 template <int P, bool MIX>
-__global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
+__global__ __launch_bounds__(MW * PG_WAVE, (P == PG_FP32 || MIX) ? 3 : 4) void k_join_mfma(
     const float *__restrict__ X, int64_t ldx, const void *__restrict__ X16, int d, int d16,
     const float *__restrict__ norms, int K, const int32_t *__restrict__ jn,
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
@@ -892,7 +927,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
     if (u < 0) return;
     unsigned long long *cslot = stripe_of(counters);
     const int64_t seg_begin = (int64_t)(blockIdx.x % NSTRIPE) * seg, seg_end = seg_begin + seg;
-    unsigned char *region = smem + (size_t)wv * MPS * (8 + 8 + 4 + 4 + 4 + 4 + 4);
+    unsigned char *region = smem + (size_t)wv * MPS * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4);
     uint64_t *kth = reinterpret_cast<uint64_t *>(region);
     int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
     int32_t *ids = reinterpret_cast<int32_t *>(sbase + MPS);
@@ -900,6 +935,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
     int32_t *base = cnt + MPS;
     int32_t *mk = base + MPS;
     float *nrm = reinterpret_cast<float *>(mk + MPS);
+    float *thr = nrm + MPS;  // d2 of the member's cut when it takes proposals, else -1
 
     const int nn = jn_c[u], no = jo_c[u];
     const int m = nn + no;
@@ -909,11 +945,13 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
     for (int i = lane; i < mp; i += PG_WAVE) {
         const int32_t id = i < nn ? jn[u * JN + i] : (i < m ? jo[u * JO + (i - nn)] : -1);
         ids[i] = id;
-        kth[i] = id >= 0 ? keys[(int64_t)id * K + (K - 1)] : 0ull;
+        const uint64_t kk = id >= 0 ? keys[(int64_t)id * K + (K - 1)] : 0ull;
+        kth[i] = kk;
         nrm[i] = id >= 0 ? norms[id] : 0.f;
         cnt[i] = 0;
         const int mkv = (mark && id >= 0) ? (int)mark[id] : (mark ? 0 : 1);
         mk[i] = mkv;
+        thr[i] = (id >= 0 && mkv) ? key_d2(kk) : -1.0f;
         anymark |= (id >= 0 && mkv != 0);
     }
     if (__ballot(anymark) == 0) return;
@@ -932,13 +970,16 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
             // decisions (bit g of each mask = accumulator register g)
             uint32_t to_row = 0, to_col = 0;
             const float nc = nrm[cm < mp ? cm : 0];
+            const float thc = thr[cm < mp ? cm : 0];
             float dx[MIX ? 16 : 1];  // mixed: direct-form distances of the rechecked pairs
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
                 if (MIX) dx[MIX ? q : 0] = __int_as_float(0x7f800000);
-                if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
                 float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                // a key below an end's cut has d2 <= the cut's d2: most pairs stop here
+                if (!MIX && !(d2 <= thr[r]) && !(d2 <= thc)) continue;
+                if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
                 if (MIX) {
                     const float cut = fmaxf(mk[r] ? key_d2(kth[r]) : -1.0f, mk[cm] ? key_d2(kth[cm]) : -1.0f);
                     if (cut < 0.0f || !(d2 <= mixed_bound(mx, cut, nrm[r], nc, g[q]))) continue;
@@ -952,26 +993,36 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
                 if (mk[cm] && kv < kth[cm] && !(mark && list_has(keys + (int64_t)ids[cm] * K, K, kv)))
                     to_col |= 1u << q;
             }
-            // offsets: rows by ballot (one LDS atomic per row and half), columns per lane
+            // Offsets within this tile's contribution to each target.  Each
+            // (register, half) is a distinct row, so a row's count is one
+            // popcount of its ballot; the two halves of a column combine by a
+            // shuffle.  In a diagonal tile a member is both a row and a
+            // column: its column proposals go after its row proposals.
             int off_row[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const uint64_t bm = __ballot((to_row >> q) & 1u);
                 const uint64_t mine = h ? (bm >> 32) : (bm & 0xFFFFFFFFull);
                 const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
-                int b0 = 0;
-                if (l32 == 0 && mine) b0 = atomicAdd(&cnt[r], __popcll(mine));
-                b0 = __shfl(b0, lane & 32, PG_WAVE);
+                if (l32 == 0) cnt[r] = __popcll(mine);
                 const uint64_t below = (lanemask_lt() >> (32 * h)) & 0xFFFFFFFFull;
-                off_row[q] = b0 + __popcll(mine & below);
-            }
-            int off_col = 0;
-            {
-                const int c_c = __popc(to_col);
-                if (c_c) off_col = atomicAdd(&cnt[cm], c_c);
+                off_row[q] = __popcll(mine & below);
             }
             __builtin_amdgcn_wave_barrier();
-            local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
+            int off_col;
+            {
+                const int cc = __popc(to_col), cc_other = __shfl_xor(cc, 32, PG_WAVE);
+                const int rows_before = (rb == cb) ? cnt[cm] : 0;
+                off_col = rows_before + (h ? cc_other : 0);
+                __builtin_amdgcn_wave_barrier();
+                if (h == 0 && (rb == cb || cc + cc_other > 0)) cnt[cm] = rows_before + cc + cc_other;
+            }
+            __builtin_amdgcn_wave_barrier();
+            {
+                // only the tile's rows and columns can hold proposals
+                const int mi = h == 0 ? 32 * rb + l32 : (cb != rb ? 32 * cb + l32 : -1);
+                local_props += reserve_lanes(mi < m ? mi : -1, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
+            }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -1014,7 +1065,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, 3) void k_join_mfma(
 
 static size_t join_mfma_lds_bytes(int maxm) {
     const int mps = (maxm + 31) / 32 * 32;
-    return (size_t)MW * mps * (8 + 8 + 4 + 4 + 4 + 4 + 4);
+    return (size_t)MW * mps * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4);
 }
 
 // ---------------------------------------------------------------------------
