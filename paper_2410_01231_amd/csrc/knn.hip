@@ -856,7 +856,7 @@ __device__ __forceinline__ mf_f32x16 gram_tile(const float *__restrict__ X, int6
     // tile waits for memory once per batch instead of once per step.
     if (P == PG_FP32) {
         // float4 chunk t: lane half h takes dims 4t+2h and 4t+2h+1 in two steps
-        constexpr int GK = 16;
+        constexpr int GK = 8;
         const float *ra = X + (int64_t)rid * ldx + 2 * h;
         const float *ca = X + (int64_t)cid * ldx + 2 * h;
         for (int t0 = 0; t0 < d; t0 += 4 * GK) {
@@ -908,7 +908,7 @@ constexpr int MW = 4;  // sources (waves) per workgroup in the MFMA join
 // ballots (the 32 lanes of a half share the row), so only one LDS atomic per
 // (row, tile half) and one per (lane, column) are needed.
 template <int P, bool MIX>
-__global__ __launch_bounds__(MW * PG_WAVE, (P == PG_FP32 || MIX) ? 3 : 4) void k_join_mfma(
+__global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     const float *__restrict__ X, int64_t ldx, const void *__restrict__ X16, int d, int d16,
     const float *__restrict__ norms, int K, const int32_t *__restrict__ jn,
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
