@@ -271,6 +271,24 @@ def test_prune_mfma_exact_path_bit_exact(pg, oracle, datagen, nn, d, C, R, alpha
     assert int(host(g["ep"])[0]) == r["ep"]
 
 
+def test_prune_mfma_unsorted_candidates_with_repeats(pg, oracle, datagen):
+    # the exact MFMA path on candidate lists that are not kNN lists: random
+    # order, repeats, u itself and -1 padding, with their exact distances given
+    X, _ = datagen.sift_like(1500, 0, d=40, n_clusters=10, sigma=8.0, seed=33)
+    n = len(X)
+    cand = datagen.random_candidates(n, 48, seed=34)
+    cand[:, 5] = cand[:, 2]              # repeats
+    cand[::7, 9] = np.arange(n)[::7]     # self
+    cand[::3, 47] = -1                   # padding
+    Xd64 = X.astype(np.float64)
+    safe = np.where(cand >= 0, cand, 0)
+    cd2 = ((Xd64[:, None, :] - Xd64[safe]) ** 2).sum(-1).astype(np.float32)
+    g = pg.prune(dev(X), dev(cand), 16, cand_d2=dev(cd2), stages=pg.STAGE_PRUNE | pg.STAGE_REVERSE)
+    r = oracle.refine(X, cand, 16, stages=oracle.STAGE_PRUNE | oracle.STAGE_REVERSE)
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert np.array_equal(host(g["deg"]), r["deg"])
+
+
 def test_prune_given_distances_match_computed_on_float_data(pg, datagen):
     # non-integer data keep the canonical FP32 path; given distances from the
     # kNN build are the same chain values, so the graphs are identical
