@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_prune_prep(const float *__restrict__ X,
     }
 }
 
-constexpr int PM_DC = 64;            // dimensions per staged chunk
+constexpr int PM_DC = 32;            // dimensions per staged chunk
 constexpr int PM_RS = PM_DC + 8;     // LDS row stride in halves (16-byte pad)
 constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept nodes
 
@@ -266,7 +266,7 @@ constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept 
 // Occlusion among this round's candidates is kept per occluding row (lane i
 // holds the set of later candidates that i occludes); the greedy scan of
 // Alg. 3 ORs in the set of every candidate it keeps.
-__global__ __launch_bounds__(64) void k_prune_mfma(
+__global__ __launch_bounds__(64, 4) void k_prune_mfma(
     const _Float16 *__restrict__ X16, int d16, const float *__restrict__ norms, int64_t n,
     const int32_t *__restrict__ src1, const float *__restrict__ src1_d2, int C1,
     const int32_t *__restrict__ src1_deg, const int64_t *__restrict__ src2_off,
@@ -306,6 +306,17 @@ __global__ __launch_bounds__(64) void k_prune_mfma(
                 key = pack_key(dd, id);
                 if (!first && key <= last) key = KEY_INF;
             }
+            if (first && m <= PG_WAVE) {
+                // a list that is already sorted, distinct and valid (a kNN
+                // list, a PRUNE result) is the round as it stands
+                const uint64_t prv = shfl64(key, max(lane - 1, 0));
+                const bool bad = idx < m && (key == KEY_INF || (lane > 0 && !(prv < key)));
+                if (__ballot(bad) == 0) {
+                    top = key;
+                    tpos = idx;
+                    continue;
+                }
+            }
             int pos = idx;
             wave_sort(key, pos);
             const uint64_t prev = shfl64(key, max(lane - 1, 0));
@@ -325,15 +336,13 @@ __global__ __launch_bounds__(64) void k_prune_mfma(
             const int32_t kid = lane < nk ? key_id(kept_key[lane]) : -1;
             kn[lane] = kid >= 0 ? norms[kid] : 0.f;
         }
-        const bool two = cm > 32, withk = nk > 0;
-        pm_f32x16 t00, t01, t11, k0, k1;
-#pragma unroll
-        for (int g = 0; g < 16; ++g) t00[g] = t01[g] = t11[g] = k0[g] = k1[g] = 0.f;
-        for (int c0 = 0; c0 < d16; c0 += PM_DC) {
-            const int dc = min(PM_DC, d16 - c0);
+        const bool two = cm > 32;
+        // stage rows [0, nrows) of this round (candidates, then kept nodes at
+        // 64..) for dimensions [c0, c0 + dc)
+        auto stage = [&](int c0, int dc, int nrows) {
             const int vpr = dc / 8;
             __syncthreads();
-            for (int v = lane; v < PM_ROWS * vpr; v += PG_WAVE) {
+            for (int v = lane; v < nrows * vpr; v += PG_WAVE) {
                 const int r = v / vpr, c = (v - r * vpr) * 8;
                 int32_t id = -1;
                 if (r < 64)
@@ -345,67 +354,85 @@ __global__ __launch_bounds__(64) void k_prune_mfma(
                 *reinterpret_cast<pm_f16x8 *>(rows + r * PM_RS + c) = x;
             }
             __syncthreads();
-            const _Float16 *r0 = rows + l32 * PM_RS + 8 * h;
-            const _Float16 *r1 = rows + (32 + l32) * PM_RS + 8 * h;
-            const _Float16 *rk = rows + (64 + l32) * PM_RS + 8 * h;
-            for (int k = 0; k < dc; k += 16) {
-                const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
-                t00 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a0, t00, 0, 0, 0);
-                if (two) {
-                    const pm_f16x8 a1 = *reinterpret_cast<const pm_f16x8 *>(r1 + k);
-                    t01 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a1, t01, 0, 0, 0);
-                    t11 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, a1, t11, 0, 0, 0);
-                    if (withk) {
-                        const pm_f16x8 ak = *reinterpret_cast<const pm_f16x8 *>(rk + k);
-                        k0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ak, a0, k0, 0, 0, 0);
+        };
+        const _Float16 *r0 = rows + l32 * PM_RS + 8 * h;
+        const _Float16 *r1 = rows + (32 + l32) * PM_RS + 8 * h;
+        const _Float16 *rk = rows + (64 + l32) * PM_RS + 8 * h;
+        // ---- occlusion among this round's candidates: kill sets per row
+        uint64_t killv = 0, occk = 0;
+        {
+            pm_f32x16 t00, t01, t11;
+#pragma unroll
+            for (int g = 0; g < 16; ++g) t00[g] = t01[g] = t11[g] = 0.f;
+            for (int c0 = 0; c0 < d16; c0 += PM_DC) {
+                const int dc = min(PM_DC, d16 - c0);
+                stage(c0, dc, two ? 64 : 32);
+                for (int k = 0; k < dc; k += 16) {
+                    const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
+                    t00 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a0, t00, 0, 0, 0);
+                    if (two) {
+                        const pm_f16x8 a1 = *reinterpret_cast<const pm_f16x8 *>(r1 + k);
+                        t01 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a1, t01, 0, 0, 0);
+                        t11 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, a1, t11, 0, 0, 0);
+                    }
+                }
+            }
+            auto cand_tile = [&](const pm_f32x16 &t, int rb, int cb) {
+                const int j = 32 * cb + l32;
+                const float cj = key_d2(chunk_key[j]), nj = cn[j];
+#pragma unroll
+                for (int g = 0; g < 16; ++g) {
+                    const int i = 32 * rb + 8 * (g / 4) + 4 * h + (g % 4);
+                    bool cnd = false;
+                    if (i < cm && j < cm && i < j) {
+                        const float b = fmaxf(fmaf(-2.0f, t[g], cn[i] + nj), 0.0f);
+                        cnd = occludes(key_d2(chunk_key[i]), b, cj, strict, use_angle, kappa);
+                    }
+                    const uint64_t bm = __ballot(cnd);
+                    const int i0 = 32 * rb + 8 * (g / 4) + (g % 4);
+                    if (lane == i0) killv |= (bm & 0xFFFFFFFFull) << (32 * cb);
+                    if (lane == i0 + 4) killv |= (bm >> 32) << (32 * cb);
+                }
+            };
+            cand_tile(t00, 0, 0);
+            if (two) {
+                cand_tile(t01, 0, 1);
+                cand_tile(t11, 1, 1);
+            }
+        }
+        // ---- occlusion by the nodes kept in earlier rounds (second pass)
+        if (nk > 0) {
+            pm_f32x16 k0, k1;
+#pragma unroll
+            for (int g = 0; g < 16; ++g) k0[g] = k1[g] = 0.f;
+            for (int c0 = 0; c0 < d16; c0 += PM_DC) {
+                const int dc = min(PM_DC, d16 - c0);
+                stage(c0, dc, PM_ROWS);
+                for (int k = 0; k < dc; k += 16) {
+                    const pm_f16x8 ak = *reinterpret_cast<const pm_f16x8 *>(rk + k);
+                    const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
+                    k0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ak, a0, k0, 0, 0, 0);
+                    if (two) {
+                        const pm_f16x8 a1 = *reinterpret_cast<const pm_f16x8 *>(r1 + k);
                         k1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ak, a1, k1, 0, 0, 0);
                     }
-                } else if (withk) {
-                    const pm_f16x8 ak = *reinterpret_cast<const pm_f16x8 *>(rk + k);
-                    k0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ak, a0, k0, 0, 0, 0);
                 }
             }
-        }
-        // ---- occlusion: kill sets per candidate row, kept-node occlusion per column
-        uint64_t killv = 0, occk = 0;
-        auto cand_tile = [&](const pm_f32x16 &t, int rb, int cb) {
-            const int j = 32 * cb + l32;
-            const float cj = key_d2(chunk_key[j]), nj = cn[j];
+            auto kept_tile = [&](const pm_f32x16 &t, int cb) {
+                const int j = 32 * cb + l32;
+                const float cj = key_d2(chunk_key[j]), nj = cn[j];
 #pragma unroll
-            for (int g = 0; g < 16; ++g) {
-                const int i = 32 * rb + 8 * (g / 4) + 4 * h + (g % 4);
-                bool cnd = false;
-                if (i < cm && j < cm && i < j) {
-                    const float b = fmaxf(fmaf(-2.0f, t[g], cn[i] + nj), 0.0f);
-                    cnd = occludes(key_d2(chunk_key[i]), b, cj, strict, use_angle, kappa);
+                for (int g = 0; g < 16; ++g) {
+                    const int k = 8 * (g / 4) + 4 * h + (g % 4);
+                    bool cnd = false;
+                    if (k < nk && j < cm) {
+                        const float b = fmaxf(fmaf(-2.0f, t[g], kn[k] + nj), 0.0f);
+                        cnd = occludes(key_d2(kept_key[k]), b, cj, strict, use_angle, kappa);
+                    }
+                    const uint64_t bm = __ballot(cnd);
+                    occk |= ((bm & 0xFFFFFFFFull) | (bm >> 32)) << (32 * cb);
                 }
-                const uint64_t bm = __ballot(cnd);
-                const int i0 = 32 * rb + 8 * (g / 4) + (g % 4);
-                if (lane == i0) killv |= (bm & 0xFFFFFFFFull) << (32 * cb);
-                if (lane == i0 + 4) killv |= (bm >> 32) << (32 * cb);
-            }
-        };
-        auto kept_tile = [&](const pm_f32x16 &t, int cb) {
-            const int j = 32 * cb + l32;
-            const float cj = key_d2(chunk_key[j]), nj = cn[j];
-#pragma unroll
-            for (int g = 0; g < 16; ++g) {
-                const int k = 8 * (g / 4) + 4 * h + (g % 4);
-                bool cnd = false;
-                if (k < nk && j < cm) {
-                    const float b = fmaxf(fmaf(-2.0f, t[g], kn[k] + nj), 0.0f);
-                    cnd = occludes(key_d2(kept_key[k]), b, cj, strict, use_angle, kappa);
-                }
-                const uint64_t bm = __ballot(cnd);
-                occk |= ((bm & 0xFFFFFFFFull) | (bm >> 32)) << (32 * cb);
-            }
-        };
-        cand_tile(t00, 0, 0);
-        if (two) {
-            cand_tile(t01, 0, 1);
-            cand_tile(t11, 1, 1);
-        }
-        if (withk) {
+            };
             kept_tile(k0, 0);
             if (two) kept_tile(k1, 1);
         }
