@@ -10,6 +10,7 @@ readings taken where the paper is silent.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -227,16 +228,47 @@ def opt_kcna(X, cand, k, L, M, alpha_deg):
     return ids, d2
 
 
-def iter_nsg(X, K, S, max_iters, seed, stop_updates, k, L, M, alpha_deg, iterations):
-    """IterNSG (Alg. 6) with a fixed number of OptKCNA rounds: NN-Descent lists
-    (Phase 1), `iterations` rounds of OptKCNA, then the refinement of Alg. 2
-    (RNG pruning with M, reverse, entry point, connect).  Returns the graph dict
-    of refine() plus the final candidate lists under "cand"."""
+def quality_sample_size(n, eps, l=1):
+    """Sample size of the quality examination (Section 5.2, the theorem on
+    n_s): n_s >= (8 + 2 eps) l log n / eps^2 (natural log) samples estimate the
+    mean k-CNA recall within eps/2 with probability at least 1 - n^-l."""
+    return int(math.ceil((8.0 + 2.0 * eps) * l * math.log(n) / (eps * eps)))
+
+
+def quality_examination(X, cand, k, sample):
+    """Estimated k-CNA quality of the candidate lists: the mean over the sampled
+    nodes u of |C(u)[:k] & N*_k(u)| / k, with N*_k(u) the exact k nearest other
+    points (brute force)."""
+    X = _f32(X)
+    sample = _i32(sample)
+    gt, _ = exact_knn(X, X[sample], k, exclude=sample)
+    cand = np.asarray(cand)
+    hits = 0
+    for u, t in zip(sample.tolist(), gt.tolist()):
+        hits += len(set(int(v) for v in cand[u, :k] if v >= 0) & set(t))
+    return hits / (k * len(sample))
+
+
+def iter_nsg(X, K, S, max_iters, seed, stop_updates, k, L, M, alpha_deg, iterations,
+             target=None, sample=None):
+    """IterNSG (Alg. 6): NN-Descent lists (Phase 1), rounds of OptKCNA, then the
+    refinement of Alg. 2 (RNG pruning with M, reverse, entry point, connect).
+    Without `target` it runs `iterations` rounds.  With `target`, the quality
+    examination (Phase 4) on the sampled nodes runs before each round and the
+    rounds stop once the estimate reaches `target` (or after `iterations`).
+    Returns the graph dict of refine() plus the final candidate lists ("cand"),
+    the rounds run ("rounds") and the estimates ("quality")."""
     cand, _, _, _ = nndescent(X, K, S, max_iters, seed, stop_updates=stop_updates)
-    for _ in range(iterations):
+    rounds, quality = 0, []
+    while rounds < iterations:
+        if target is not None:
+            quality.append(quality_examination(X, cand, k, sample))
+            if quality[-1] >= target:
+                break
         cand, _ = opt_kcna(X, cand, k, L, M, alpha_deg)
+        rounds += 1
     g = refine(X, cand, M)
-    g["cand"] = cand
+    g["cand"], g["rounds"], g["quality"] = cand, rounds, quality
     return g
 
 

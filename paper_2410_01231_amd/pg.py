@@ -302,17 +302,49 @@ def opt_kcna(X, cand, k, L, M, alpha_deg, cand_d2=None, ctx=None):
     return search_self(X, g["ids"], g["deg"], k, L, ctx=ctx)
 
 
+def quality_sample_size(n, eps, l=1):
+    """Sample size of the quality examination (Section 5.2): the theorem's
+    n_s >= (8 + 2 eps) l log n / eps^2 estimates the mean k-CNA recall within
+    eps/2 with probability at least 1 - n^-l."""
+    import math
+    return int(math.ceil((8.0 + 2.0 * eps) * l * math.log(n) / (eps * eps)))
+
+
+def quality_examination(X, cand, k, sample, ctx=None):
+    """Estimated k-CNA quality of the candidate lists (Section 5.2): the mean
+    over the sampled nodes u of |C(u)[:k] & N*_k(u)| / k, the exact k nearest
+    other points N*_k coming from the brute-force kernel."""
+    X = _dev_f32(X, "X")
+    cand = _dev_i32(cand, "cand")
+    sample = _dev_i32(torch.as_tensor(sample).reshape(1, -1).to(X.device), "sample").reshape(-1)
+    rows = sample.long()
+    gt, _ = exact_knn(X, X[rows].contiguous(), k, exclude=sample, ctx=ctx)
+    c = cand[rows, :k]
+    hit = ((c.unsqueeze(2) == gt.unsqueeze(1)).any(2) & (c >= 0)).sum()
+    return float(hit.item()) / (k * sample.numel())
+
+
 def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0, delta=0.001,
-             ctx=None, **knn_kw):
-    """IterNSG (Alg. 6) with a fixed number of OptKCNA rounds: NN-Descent lists,
-    `iterations` rounds of OptKCNA with angle alpha_deg, then the refinement of
-    Alg. 2 with RNG pruning.  Returns the graph dict of prune() plus the final
-    candidate lists ("cand", "cand_d2") and the kNN statistics."""
+             target=None, sample=None, ctx=None, **knn_kw):
+    """IterNSG (Alg. 6): NN-Descent lists, rounds of OptKCNA with angle
+    alpha_deg, then the refinement of Alg. 2 with RNG pruning.  Without
+    `target` it runs `iterations` rounds; with `target` the quality
+    examination on the nodes `sample` runs before each round and the rounds
+    stop once the estimate reaches it (or after `iterations`).  Returns the
+    graph dict of prune() plus the final candidate lists ("cand", "cand_d2"),
+    the rounds run, the estimates and the kNN statistics."""
     cand, cd2, st = knn_build(X, K, S=S, max_iters=max_iters, seed=seed, delta=delta, ctx=ctx, **knn_kw)
-    for _ in range(iterations):
+    rounds, quality = 0, []
+    while rounds < iterations:
+        if target is not None:
+            quality.append(quality_examination(X, cand, k, sample, ctx=ctx))
+            if quality[-1] >= target:
+                break
         cand, cd2 = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, ctx=ctx)
+        rounds += 1
     g = prune(X, cand, R, cand_d2=cd2, ctx=ctx)
     g["cand"], g["cand_d2"], g["knn_stats"] = cand, cd2, st
+    g["rounds"], g["quality"] = rounds, quality
     return g
 
 

@@ -421,3 +421,21 @@ def test_iter_nsg_bit_exact(pg, oracle, datagen, nn, d, nc, sig, K, S, k, L, R, 
     assert np.array_equal(host(g["deg"]), r["deg"])
     assert np.array_equal(host(g["roots"]), r["roots"])
     assert int(host(g["ep"])[0]) == r["ep"]
+
+
+def test_quality_examination_and_stopping_rule(pg, oracle, datagen):
+    # Section 5.2: the sampled k-CNA quality estimate, and IterNSG stopping
+    # once it reaches the target, both as in the oracle
+    X, _ = datagen.sift_like(3000, 0, d=32, n_clusters=20, sigma=12.0, seed=41)
+    n, K, S, k, L, R = len(X), 16, 8, 16, 32, 16
+    sample = datagen.sample_ids(n, 300, seed=6)
+    cand, _, _, _ = oracle.nndescent(X, K, S, 2, 3)
+    assert pg.quality_examination(dev(X), dev(cand), k, sample) == \
+        oracle.quality_examination(X, cand, k, sample)
+    stop = int(0.001 * n * K)
+    r = oracle.iter_nsg(X, K, S, 3, 3, stop, k, L, R, 65.0, 3, target=0.995, sample=sample)
+    g = pg.iter_nsg(dev(X), K, R, k, L, 65.0, 3, S=S, max_iters=3, seed=3, stop_updates=stop,
+                    target=0.995, sample=sample)
+    log("rounds", g["rounds"], r["rounds"], "quality", g["quality"], r["quality"])
+    assert g["rounds"] == r["rounds"] == 1 and g["quality"] == r["quality"]
+    assert np.array_equal(host(g["ids"]), r["ids"])

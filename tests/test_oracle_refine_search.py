@@ -203,3 +203,47 @@ def test_iter_nsg_zero_rounds_is_refined_nndescent(oracle, datagen):
     cand, _, _, _ = oracle.nndescent(X, 12, 6, 4, 3, stop_updates=0)
     r = oracle.refine(X, cand, 8)
     assert np.array_equal(g["ids"], r["ids"]) and np.array_equal(g["cand"], cand)
+
+
+# ------------------------------------------- quality examination (Section 5.2)
+
+def test_quality_sample_size(oracle):
+    # the theorem's bound, natural log: 1M points, eps = 0.6, l = 1 -> 354
+    assert oracle.quality_sample_size(10**6, 0.6) == 354
+    assert oracle.quality_sample_size(10**6, 0.6, l=2) == 707
+    assert oracle.quality_sample_size(10**4, 0.3) > oracle.quality_sample_size(10**4, 0.6)
+
+
+def test_quality_examination_known_lists(oracle, datagen):
+    # exact lists score 1, lists of far points score 0, and lists whose first
+    # half is exact score 1/2 exactly
+    X = datagen.uniform_int(1500, 8, seed=21)
+    n, k = len(X), 10
+    exact, _ = oracle.exact_knn(X, X, 2 * k, exclude=np.arange(n))
+    sample = datagen.sample_ids(n, 200, seed=3)
+    assert oracle.quality_examination(X, exact, k, sample) == 1.0
+    far = exact[:, k:2 * k]                 # ranks k..2k-1: none among the k nearest
+    assert oracle.quality_examination(X, far, k, sample) == 0.0
+    half = np.concatenate([exact[:, :k // 2], far[:, :k - k // 2]], axis=1)
+    assert oracle.quality_examination(X, half, k, sample) == 0.5
+
+
+def test_quality_estimate_concentrates(datagen):
+    # the estimator on a sample of the theorem's size stays within eps/2 of
+    # the true mean recall (per-node recalls drawn at random, many samples)
+    import math
+    rng = np.random.default_rng(4)
+    n, eps = 5000, 0.2
+    ns = int(math.ceil((8 + 2 * eps) * math.log(n) / eps ** 2))
+    r = rng.integers(0, 11, size=n) / 10.0
+    worst = max(abs(r[rng.choice(n, ns, replace=False)].mean() - r.mean()) for _ in range(300))
+    assert worst < eps / 2
+
+
+def test_iter_nsg_stops_on_quality(oracle, datagen):
+    X, _ = datagen.sift_like(800, 0, d=16, n_clusters=8, sigma=6.0, seed=14)
+    sample = datagen.sample_ids(len(X), 100, seed=5)
+    g = oracle.iter_nsg(X, 12, 6, 4, 3, 0, 12, 24, 8, 65.0, 3, target=0.0, sample=sample)
+    assert g["rounds"] == 0 and len(g["quality"]) == 1
+    g = oracle.iter_nsg(X, 12, 6, 4, 3, 0, 12, 24, 8, 65.0, 2, target=1.01, sample=sample)
+    assert g["rounds"] == 2 and len(g["quality"]) == 2
