@@ -176,7 +176,9 @@ __global__ __launch_bounds__(256) void k_sample(const uint64_t *__restrict__ key
                                                 int32_t *__restrict__ of,
                                                 int32_t *__restrict__ of_c,
                                                 int32_t *__restrict__ rn_cnt,
-                                                int32_t *__restrict__ ro_cnt) {
+                                                int32_t *__restrict__ ro_cnt,
+                                                int32_t *__restrict__ nf_slot,
+                                                int32_t *__restrict__ of_slot) {
     const int lane = lane_id();
     const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (u >= n) return;
@@ -195,12 +197,13 @@ __global__ __launch_bounds__(256) void k_sample(const uint64_t *__restrict__ key
     if (sel) {
         const int32_t v = key_id(sk);
         nf[u * S + lane] = v;
-        atomicAdd(&rn_cnt[v], 1);
+        nf_slot[u * S + lane] = atomicAdd(&rn_cnt[v], 1);  // u's place in v's reverse list
     }
     const uint64_t om = __ballot(isold);
     if (isold) {
-        of[u * K + __popcll(om & lanemask_lt())] = id;
-        atomicAdd(&ro_cnt[id], 1);
+        const int at = __popcll(om & lanemask_lt());
+        of[u * K + at] = id;
+        of_slot[u * K + at] = atomicAdd(&ro_cnt[id], 1);
     }
     if (lane == 0) {
         nf_c[u] = min(S, __popcll(nm & ((K == 64) ? ~0ull : ((1ull << K) - 1ull))));
@@ -212,37 +215,40 @@ __global__ __launch_bounds__(256) void k_sample(const uint64_t *__restrict__ key
 // ---------------------------------------------------------------------------
 // reverse lists (CSR)
 // ---------------------------------------------------------------------------
+// u goes to its place (taken by the counting atomics of k_sample) in the
+// reverse list of every v it sampled
 __global__ __launch_bounds__(256) void k_rev_scatter(int64_t n, const int32_t *__restrict__ nf,
                                                      const int32_t *__restrict__ nf_c, int S,
                                                      const int32_t *__restrict__ of,
                                                      const int32_t *__restrict__ of_c, int K,
                                                      const int64_t *__restrict__ rn_off,
-                                                     int32_t *__restrict__ rn_cur,
+                                                     const int32_t *__restrict__ nf_slot,
                                                      int32_t *__restrict__ rn_list,
                                                      const int64_t *__restrict__ ro_off,
-                                                     int32_t *__restrict__ ro_cur,
+                                                     const int32_t *__restrict__ of_slot,
                                                      int32_t *__restrict__ ro_list) {
     const int lane = lane_id();
     const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (u >= n) return;
     if (lane < nf_c[u]) {
         const int32_t v = nf[u * S + lane];
-        const int p = atomicAdd(&rn_cur[v], 1);
-        rn_list[rn_off[v] + p] = (int32_t)u;
+        rn_list[rn_off[v] + nf_slot[u * S + lane]] = (int32_t)u;
     }
     if (lane < of_c[u]) {
         const int32_t v = of[u * K + lane];
-        const int p = atomicAdd(&ro_cur[v], 1);
-        ro_list[ro_off[v] + p] = (int32_t)u;
+        ro_list[ro_off[v] + of_slot[u * K + lane]] = (int32_t)u;
     }
 }
 
-// S smallest sample keys among the CSR list of v (stream `stream`), ascending.
+// S smallest sample keys among the CSR list of v (stream `stream`), ascending;
+// a list of at most S entries is selected whole (ids only, in list order).
 __device__ __forceinline__ uint64_t select_reverse(int64_t v, const int64_t *__restrict__ off,
                                                    const int32_t *__restrict__ list,
-                                                   uint64_t seed, uint64_t stream) {
+                                                   uint64_t seed, uint64_t stream, int S) {
     const int lane = lane_id();
     const int64_t beg = off[v], cnt = off[v + 1] - beg;
+    if (cnt <= S)  // every entry is selected; callers use the ids only
+        return lane < cnt ? (uint64_t)(uint32_t)list[beg + lane] : KEY_INF;
     uint64_t top = KEY_INF;
     int dummy = 0;
     for (int64_t b = 0; b < cnt; b += PG_WAVE) {
@@ -281,8 +287,8 @@ __global__ __launch_bounds__(256) void k_build_join(
     unsigned long long pairs = 0, memb = 0;
     // grid-stride over nodes, one wave each; one counter atomic per block
     for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4) {
-        const uint64_t rsel = select_reverse(v, rn_off, rn_list, seed, stream_rn);
-        const uint64_t osel = select_reverse(v, ro_off, ro_list, seed, stream_ro);
+        const uint64_t rsel = select_reverse(v, rn_off, rn_list, seed, stream_rn, S);
+        const uint64_t osel = select_reverse(v, ro_off, ro_list, seed, stream_ro, S);
         // new set (|new_f| <= S and |Rnew| <= S, S <= 32: one id per lane)
         const int nfc = nf_c[v];
         const uint64_t rsel_id = (lane < S && rsel != KEY_INF) ? (uint64_t)(uint32_t)key_id(rsel) : KEY_INF;
@@ -1590,16 +1596,15 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         PG_HIP(hipMemsetAsync(ro_cnt, 0, sizeof(int32_t) * n, st));
         {
             TimedLaunch tl(ctx, K_SAMPLE, (double)n * K * 8.0);
+            // slots of the reverse entries live in jn / jo until the join sets are built
             hipLaunchKernelGGL(k_sample, dim3(wave_blocks), dim3(256), 0, st, keys, newm, n, K, S,
-                               p->seed, (uint64_t)(3 * t), nf, nf_c, of, of_c, rn_cnt, ro_cnt);
+                               p->seed, (uint64_t)(3 * t), nf, nf_c, of, of_c, rn_cnt, ro_cnt, jn, jo);
             PG_HIP(hipGetLastError());
         }
         PG_TRY(scan_exclusive(ctx, rn_cnt, rn_off, n, scan_tmp));
         PG_TRY(scan_exclusive(ctx, ro_cnt, ro_off, n, scan_tmp));
-        PG_HIP(hipMemsetAsync(rn_cnt, 0, sizeof(int32_t) * n, st));
-        PG_HIP(hipMemsetAsync(ro_cnt, 0, sizeof(int32_t) * n, st));
         hipLaunchKernelGGL(k_rev_scatter, dim3(wave_blocks), dim3(256), 0, st, n, nf, nf_c, S, of,
-                           of_c, K, rn_off, rn_cnt, rn_list, ro_off, ro_cnt, ro_list);
+                           of_c, K, rn_off, jn, rn_list, ro_off, jo, ro_list);
         PG_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_build_join, dim3(std::min<unsigned>(wave_blocks, 8192)), dim3(256), 0, st, n, K, S,
                            p->seed,
