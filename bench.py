@@ -122,6 +122,9 @@ def main():
     ap.add_argument("--workload", default="sift1m", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iternsg", type=int, default=0, metavar="I",
+                    help="also build the IterNSG graph (Alg. 6) with I OptKCNA rounds on the "
+                         "fastest path and report its build time and search recall")
     ap.add_argument("--paths", default="fp32,fp16",
                     help="comma-separated join paths to measure: fp32, fp16, bf16, fp32-valu")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -186,10 +189,48 @@ def main():
         "paths": {p: {k: v for k, v in results[p].items() if k != "roofline"} | {"roofline": results[p]["roofline"]}
                   for p in results},
     }
+    if args.iternsg:
+        out["iter_nsg"] = run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[best])
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_sample} points")
         out["cpu_baseline"] = cpu_baseline(w, X, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, path):
+    """IterNSG (Alg. 6) with args.iternsg OptKCNA rounds (alpha 65 degrees, k = K,
+    L = 2K): build time (untimed warm-up first), then the search ladder."""
+    K, R, S = w["K"], w["R"], w["S"]
+
+    def build():
+        return pg.iter_nsg(Xd, K, R, K, 2 * K, 65.0, args.iternsg, S=S, max_iters=w["iters"], seed=1,
+                           delta=0.001, precision=path["precision"], ctx=ctx)
+    build()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = build()
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    entries = torch.cat([g["ep"], g["roots"]]).contiguous()
+    ladder, chosen = [], None
+    for L in L_LADDER:
+        f, _ = pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, L, ctx=ctx)
+        r = recall(f.cpu().numpy(), gt)
+        ladder.append((L, r))
+        log(f"[bench] iternsg L={L} recall@10={r:.4f}")
+        if r >= 0.95:
+            chosen = L
+            break
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record()
+    pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, chosen or L_LADDER[-1], ctx=ctx)
+    s1.record()
+    s1.synchronize()
+    return {"rounds": args.iternsg, "alpha_deg": 65.0, "k": K, "L_search": 2 * K,
+            "build_ms": 1000.0 * build_s, "points_per_s": w["n"] / build_s, "L": chosen,
+            "search_ladder": ladder,
+            "qps_batch": Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)}
 
 
 # join paths: precision code of pg_knn_build, dtype the join computes in

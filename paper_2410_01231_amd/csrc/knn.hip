@@ -1078,6 +1078,8 @@ static size_t join_mfma_lds_bytes(int maxm) {
 // merge: list <- K smallest distinct keys of (list U bucket)
 // flags per entry: bit 0 = new, bit 1 = inserted during this iteration
 // ---------------------------------------------------------------------------
+constexpr int MERGE_INSERT_MAX = 16;  // survivors of a batch inserted one by one
+
 __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
                                                uint64_t *__restrict__ newm,
                                                uint64_t *__restrict__ insm, int64_t n, int K,
@@ -1105,7 +1107,31 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
         else if (e < cc + sc)
             bk = spilled[s0 + (e - cc)];
         if (bk >= kth) bk = KEY_INF;
-        if (__ballot(bk != KEY_INF) == 0) continue;
+        const uint64_t vm = __ballot(bk != KEY_INF);
+        if (vm == 0) continue;
+        if (__popcll(vm) <= MERGE_INSERT_MAX) {
+            // few survivors: insert them one by one (rank by ballot, shift up)
+            for (uint64_t rem = vm; rem; rem &= rem - 1) {
+                const uint64_t x = readlane64(bk, __ffsll((long long)rem) - 1);
+                if (x >= shfl64(a, K - 1)) continue;  // not among the K smallest
+                if (__ballot(a == x)) continue;       // already in the list
+                const int at = __popcll(__ballot(a < x));
+                const uint64_t up = shfl64(a, max(lane - 1, 0));
+                const int fup = __shfl(fl, max(lane - 1, 0), PG_WAVE);
+                if (lane > at) {
+                    a = up;
+                    fl = fup;
+                } else if (lane == at) {
+                    a = x;
+                    fl = 3;
+                }
+                if (lane >= K) {
+                    a = KEY_INF;
+                    fl = 0;
+                }
+            }
+            continue;
+        }
         int pb = 3;
         wave_sort(bk, pb);
         const uint64_t prev = shfl64(bk, max(lane - 1, 0));
