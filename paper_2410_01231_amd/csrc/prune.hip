@@ -597,27 +597,46 @@ __global__ __launch_bounds__(256) void k_argmin_final(const double *__restrict__
 //   * a node p counts as reached from the turn of the smallest root reaching
 //     it, and that root is the smallest unreached node reaching p.
 // The roots and every node's turn ("reach time") therefore come from a
-// parallel min-ancestor label propagation, every root's sorted candidate list
-// from one parallel pass, and only the degree bookkeeping (a node at degree R
+// parallel min-ancestor label propagation, every root's sorted key list from
+// parallel passes, and only the degree bookkeeping (a node at degree R
 // accepts no edge) runs in root order, in one wave.
+//
+// Degrees only grow, so every node the step can still choose lies in the
+// free set F of nodes below degree R when the step starts.  A root's key list
+// holds its usable candidates (reached at its turn, below degree R at list
+// time), sorted; a root with fewer than GLOBAL_TAIL_BELOW of them gets the
+// nearest nodes of F reached at its turn appended, sorted.  The first entry
+// still below degree R at the root's turn is then exactly the rule's choice:
+// the nearest usable candidate if one is left, else the nearest usable node
+// of the whole graph, unless every listed node has filled up, in which case
+// an exact scan over F decides.
 // ---------------------------------------------------------------------------
 struct ConnState {
     int32_t fcount[2];
     int32_t changed;    // label propagation: some label dropped in this round
     int32_t idx;        // next root (global index) for the matching wave
-    int32_t stop_root;  // >= 0: root waiting for the exact scan of all nodes
+    int32_t stop_root;  // >= 0: root waiting for the exact scan over F; -1: batch done; -2: overflow
     int32_t stop_turn;  //       and its 1-based turn
-    int32_t n_empty;    // roots of the current batch with no usable candidate
+    int32_t n_empty;    // roots of the current batch queued for the scan over F
     int32_t overflow;
     unsigned long long nearest;
 };
 
-// roots handled per batch of candidate lists
+// roots handled per batch of key lists
 constexpr int32_t CONNECT_BATCH = 16384;
 // roots per step of the matching wave
 constexpr int MATCH_STEP = 16;
-// roots per block of the all-nodes scan
+// roots with fewer usable candidates than this get the nearest free nodes
+// appended to their key lists
+constexpr int GLOBAL_TAIL_BELOW = 1;
+// roots per block of the scan over F (four per wave)
 constexpr int GQ = 16;
+// free nodes per tile of that scan (one per thread)
+constexpr int TG_TILE = 256;
+// the scan over F aims at this many workgroups, splitting F into chunks of
+// at least TG_MIN_CHUNK nodes when few roots are queued
+constexpr int TG_BLOCKS = 2048;
+constexpr int TG_MIN_CHUNK = 2048;
 
 // loads that must see stores and atomics made earlier in the same kernel
 __device__ __forceinline__ int32_t ld_fresh(const int32_t *p) {
@@ -634,6 +653,17 @@ __global__ void k_scatter_unreached(const int32_t *__restrict__ visited, int64_t
                                     const int64_t *__restrict__ off, int32_t *__restrict__ U) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && visited[i] == 0) U[off[i]] = (int32_t)i;
+}
+
+__global__ void k_flag_free(const int32_t *__restrict__ deg, int64_t n, int R, int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = deg[i] < R;
+}
+
+__global__ void k_scatter_free(const int32_t *__restrict__ deg, int64_t n, int R,
+                               const int64_t *__restrict__ off, int32_t *__restrict__ F) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && deg[i] < R) F[off[i]] = (int32_t)i;
 }
 
 __global__ void k_label_init(const int32_t *__restrict__ U, int32_t nu, int32_t *__restrict__ lab) {
@@ -701,15 +731,16 @@ __global__ void k_reach_time(const int32_t *__restrict__ U, int32_t nu, const in
 
 // Sorted keys (d2, p) of the candidates of roots [b0, b1) that count as
 // reached at the root's turn and are below degree R now (degrees only grow,
-// so a node dropped here could not be chosen later).  Roots left with no key
-// are queued for the scan over all nodes.
+// so a node dropped here could not be chosen later).  Roots with fewer than
+// GLOBAL_TAIL_BELOW such keys are queued, with their key count, for the scan
+// over F.
 __global__ __launch_bounds__(256) void k_root_lists(const float *__restrict__ X, int64_t ldx, int d,
                                                     int64_t n, int R, const int32_t *__restrict__ cand,
                                                     int C, const int32_t *__restrict__ roots, int32_t b0,
                                                     int32_t b1, const int32_t *__restrict__ tt,
                                                     const int32_t *__restrict__ deg,
-                                                    uint64_t *__restrict__ keys,
-                                                    int32_t *__restrict__ empty, ConnState *cs) {
+                                                    uint64_t *__restrict__ keys, int32_t *__restrict__ queue,
+                                                    int32_t *__restrict__ qvalid, ConnState *cs) {
     const int lane = lane_id();
     const int32_t b = b0 + (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
     if (b >= b1) return;
@@ -723,83 +754,136 @@ __global__ __launch_bounds__(256) void k_root_lists(const float *__restrict__ X,
     int pay = 0;
     wave_sort(key, pay);
     if (lane < C) keys[(int64_t)(b - b0) * C + lane] = key;
-    const uint64_t first = shfl64(key, 0);
-    if (lane == 0 && first == KEY_INF) empty[atomicAdd(&cs->n_empty, 1)] = b;
+    const int nv = __popcll(__ballot(key != KEY_INF));
+    if (lane == 0 && nv < GLOBAL_TAIL_BELOW && nv < C) {
+        const int32_t q = atomicAdd(&cs->n_empty, 1);
+        queue[q] = b;
+        qvalid[q] = nv;
+    }
 }
 
-// For each queued root b = empty[q]: the smallest (d2, p) over all nodes p
-// that count as reached at its turn and are below degree R now, into slot 0 of
-// its key list.  A block covers 256 nodes and GQ queued roots; each thread
-// keeps the canonical distance chains of its node to those roots.
-__global__ __launch_bounds__(256) void k_global_nearest(const float *__restrict__ X, int64_t ldx, int d,
-                                                        int64_t n, int R, const int32_t *__restrict__ roots,
-                                                        const int32_t *__restrict__ tt,
-                                                        const int32_t *__restrict__ deg,
-                                                        const int32_t *__restrict__ empty, int32_t n_empty,
-                                                        int32_t b0, uint64_t *keys, int C) {
-    __shared__ unsigned long long red[4][GQ];
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// Nearest nodes of F for the queued roots.  Block (x, y) scans chunk x of F
+// for queued roots [GQ y, GQ y + GQ): every thread takes one free node per
+// tile and computes the canonical distance chains to those roots; a node
+// counts if it is reached at the root's turn and below degree R now.  Each
+// wave keeps, for four of the roots, the C smallest keys seen so far as one
+// ascending key per lane and merges a 64-key slice of the tile into it only
+// when some key of the slice beats the current C-th.  With one chunk the
+// result goes straight behind the root's candidate keys; otherwise into the
+// per-chunk lists `part`, which k_topg_merge combines.
+__global__ __launch_bounds__(256) void k_global_topg(const float *__restrict__ X, int64_t ldx, int d, int R,
+                                                     const int32_t *__restrict__ roots,
+                                                     const int32_t *__restrict__ tt,
+                                                     const int32_t *__restrict__ deg,
+                                                     const int32_t *__restrict__ F, int32_t nf, int32_t chunk,
+                                                     int32_t nchunk, const int32_t *__restrict__ queue,
+                                                     const int32_t *__restrict__ qvalid, int32_t nqueued,
+                                                     int32_t b0, int C, uint64_t *__restrict__ keys,
+                                                     uint64_t *__restrict__ part) {
+    __shared__ uint64_t kb[GQ][TG_TILE];
+    constexpr int PER_WAVE = GQ / 4;
+    const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
     const int q0 = (int)blockIdx.y * GQ;
-    const int nq = min(GQ, n_empty - q0);
-    int32_t rq[GQ];
-    float acc[GQ];
+    const int nq = min(GQ, nqueued - q0);
+    int32_t rq[GQ], bq[GQ];
 #pragma unroll
     for (int q = 0; q < GQ; ++q) {
-        rq[q] = q < nq ? roots[empty[q0 + q]] : 0;
-        acc[q] = 0.f;
+        bq[q] = q < nq ? queue[q0 + q] : -1;
+        rq[q] = roots[q < nq ? bq[q] : queue[q0]];
     }
-    const int64_t pc = p < n ? p : n - 1;
-    const float *xp = X + pc * ldx;
-    for (int k = 0; k < d; k += 4) {
-        const float4 x = *reinterpret_cast<const float4 *>(xp + k);
+    uint64_t top[PER_WAVE];
 #pragma unroll
-        for (int q = 0; q < GQ; ++q) {
-            if (q < nq) {
+    for (int s = 0; s < PER_WAVE; ++s) top[s] = KEY_INF;
+    const int32_t f0 = (int32_t)blockIdx.x * chunk, f1 = min(nf, f0 + chunk);
+    for (int32_t t = f0; t < f1; t += TG_TILE) {
+        const int32_t i = t + (int32_t)threadIdx.x;
+        const int32_t p = i < f1 ? F[i] : F[f0];
+        float acc[GQ];
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) acc[q] = 0.f;
+        const float *xp = X + (int64_t)p * ldx;
+        for (int k = 0; k < d; k += 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(xp + k);
+#pragma unroll
+            for (int q = 0; q < GQ; ++q) {
                 const float4 y = *reinterpret_cast<const float4 *>(X + (int64_t)rq[q] * ldx + k);
-                float t;
-                t = x.x - y.x;
-                acc[q] = fmaf(t, t, acc[q]);
-                t = x.y - y.y;
-                acc[q] = fmaf(t, t, acc[q]);
-                t = x.z - y.z;
-                acc[q] = fmaf(t, t, acc[q]);
-                t = x.w - y.w;
-                acc[q] = fmaf(t, t, acc[q]);
+                float e;
+                e = x.x - y.x;
+                acc[q] = fmaf(e, e, acc[q]);
+                e = x.y - y.y;
+                acc[q] = fmaf(e, e, acc[q]);
+                e = x.z - y.z;
+                acc[q] = fmaf(e, e, acc[q]);
+                e = x.w - y.w;
+                acc[q] = fmaf(e, e, acc[q]);
             }
         }
-    }
-    const int32_t tp = p < n ? tt[p] : INT32_MAX;
-    const bool free_p = p < n && deg[p] < R;
-    const int wv = threadIdx.x >> 6;
+        const int32_t tp = (i < f1 && deg[p] < R) ? tt[p] : INT32_MAX;
 #pragma unroll
-    for (int q = 0; q < GQ; ++q) {
-        uint64_t key = KEY_INF;
-        if (q < nq && free_p && tp <= empty[q0 + q]) key = pack_key(acc[q], (int32_t)p);
+        for (int q = 0; q < GQ; ++q) kb[q][threadIdx.x] = tp <= bq[q] ? pack_key(acc[q], p) : KEY_INF;
+        __syncthreads();
 #pragma unroll
-        for (int o = 1; o < PG_WAVE; o <<= 1) {
-            const uint64_t t = shfl_xor64(key, o);
-            key = t < key ? t : key;
+        for (int s = 0; s < PER_WAVE; ++s) {
+            const int q = wv * PER_WAVE + s;
+#pragma unroll
+            for (int c = 0; c < TG_TILE; c += PG_WAVE) {
+                uint64_t k = kb[q][c + lane];
+                if (__ballot(k < readlane64(top[s], C - 1)) == 0) continue;
+                int pk = 0, pt = 0;
+                wave_sort(k, pk);
+                wave_merge_lowest(top[s], pt, k, pk);
+            }
         }
-        if (lane_id() == 0) red[wv][q] = key;
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < nq) {
-        unsigned long long m = red[0][threadIdx.x];
-        for (int w = 1; w < 4; ++w) m = red[w][threadIdx.x] < m ? red[w][threadIdx.x] : m;
-        if (m != KEY_INF) atomicMin((unsigned long long *)&keys[(int64_t)(empty[q0 + threadIdx.x] - b0) * C], m);
+#pragma unroll
+    for (int s = 0; s < PER_WAVE; ++s) {
+        const int q = wv * PER_WAVE + s;
+        if (q >= nq) continue;
+        if (nchunk == 1) {
+            const int nv = qvalid[q0 + q];
+            if (lane < C - nv) keys[(int64_t)(bq[q] - b0) * C + nv + lane] = top[s];
+        } else if (lane < C) {
+            part[((int64_t)(q0 + q) * nchunk + blockIdx.x) * C + lane] = top[s];
+        }
     }
+}
+
+// One wave per queued root: the C smallest keys over its per-chunk lists
+// (each ascending), written behind the root's candidate keys.
+__global__ __launch_bounds__(256) void k_topg_merge(const uint64_t *__restrict__ part, int32_t nchunk,
+                                                    const int32_t *__restrict__ queue,
+                                                    const int32_t *__restrict__ qvalid, int32_t nqueued,
+                                                    int32_t b0, int C, uint64_t *__restrict__ keys) {
+    const int lane = lane_id();
+    const int32_t qi = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+    if (qi >= nqueued) return;
+    uint64_t top = KEY_INF;
+    for (int32_t c = 0; c < nchunk; ++c) {
+        const uint64_t k = lane < C ? part[((int64_t)qi * nchunk + c) * C + lane] : KEY_INF;
+        if (__ballot(k < readlane64(top, C - 1)) == 0) continue;
+        int pt = 0;
+        wave_merge_lowest(top, pt, k, 0);
+    }
+    const int nv = qvalid[qi];
+    if (lane < C - nv) keys[(int64_t)(queue[qi] - b0) * C + nv + lane] = top;
 }
 
 // Roots in turn order, MATCH_STEP at a time: each takes the first key of its
 // list whose node is still below degree R and appends the edge p -> r there.
 // Degrees are read once per step (after the previous step's atomics have
 // landed) and corrected by the picks made earlier in the same step.  A root
-// whose list has no such node stops the wave; the host then runs the exact
-// scan over all nodes for it and restarts the wave after it.
+// whose list has no such node stops the wave (stop_root >= 0, nearest reset);
+// the host then runs the exact scan over F for it and restarts the wave.  A
+// wave started after a failed scan reports the overflow (stop_root = -2).
 __global__ __launch_bounds__(64) void k_match(const int32_t *__restrict__ roots, int32_t b0, int32_t b1,
                                               const uint64_t *__restrict__ keys, int C, int R, int32_t *g,
                                               float *gd, int32_t *deg, ConnState *cs) {
     const int lane = lane_id();
+    if (cs->overflow) {
+        if (lane == 0) cs->stop_root = -2;
+        return;
+    }
     for (int32_t b = cs->idx; b < b1; b += MATCH_STEP) {
         uint64_t kk[MATCH_STEP];
         int32_t dv[MATCH_STEP], pick[MATCH_STEP];
@@ -823,6 +907,7 @@ __global__ __launch_bounds__(64) void k_match(const int32_t *__restrict__ roots,
                         cs->idx = b + k;
                         cs->stop_root = roots[b + k];
                         cs->stop_turn = b + k + 1;
+                        cs->nearest = KEY_INF;
                     }
                     return;
                 }
@@ -880,17 +965,21 @@ __global__ __launch_bounds__(256) void k_bfs_step(const int32_t *__restrict__ g,
     if (push) fout[base + __popcll(m & lanemask_lt())] = y;
 }
 
-// exact scan for the stopped root: nearest node reached at its turn and below
-// degree R now
-__global__ __launch_bounds__(256) void k_nearest_at(const float *__restrict__ X, int64_t ldx, int d,
-                                                    int64_t n, int R, const int32_t *__restrict__ tt,
+// exact scan for the stopped root: nearest node of F reached at its turn and
+// below degree R now
+__global__ __launch_bounds__(256) void k_nearest_at(const float *__restrict__ X, int64_t ldx, int d, int R,
+                                                    const int32_t *__restrict__ F, int32_t nf,
+                                                    const int32_t *__restrict__ tt,
                                                     const int32_t *__restrict__ deg,
                                                     ConnState *__restrict__ cs) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t r = cs->stop_root, turn = cs->stop_turn;
     uint64_t key = KEY_INF;
-    if (p < n && tt[p] < turn && deg[p] < R)
-        key = pack_key(dist_chain(X + (int64_t)r * ldx, X + p * ldx, d), (int32_t)p);
+    if (i < nf) {
+        const int32_t p = F[i];
+        if (tt[p] < turn && deg[p] < R)
+            key = pack_key(dist_chain(X + (int64_t)r * ldx, X + (int64_t)p * ldx, d), p);
+    }
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) {
         const uint64_t t = shfl_xor64(key, o);
@@ -919,8 +1008,8 @@ __global__ void k_attach(int32_t *__restrict__ g, float *__restrict__ gd, int32_
 // host side
 // ---------------------------------------------------------------------------
 struct PruneLayout {
-    size_t p_ids, p_d2, p_deg, cnt, off, rev, rev_d2, visited, fa, fb, cs, keys, empty, cpart, cen, apd,
-        api, scan_tmp, x16, norms, exflags, total;
+    size_t p_ids, p_d2, p_deg, cnt, off, rev, rev_d2, visited, fa, fb, cs, keys, empty, qvalid, free_ids,
+        part, cpart, cen, apd, api, scan_tmp, x16, norms, exflags, total;
     int d16;
     int64_t ncb, nab;
 };
@@ -950,6 +1039,13 @@ static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d) {
     const int64_t nb = std::min<int64_t>(n, CONNECT_BATCH);
     L.keys = take(sizeof(uint64_t) * 64 * nb);
     L.empty = take(sizeof(int32_t) * nb);
+    L.qvalid = take(sizeof(int32_t) * nb);
+    L.free_ids = take(sizeof(int32_t) * n);
+    // per-chunk lists of the scan over F: only written when F is split, which
+    // keeps chunks x root groups below 2 TG_BLOCKS
+    const int64_t groups = (nb + GQ - 1) / GQ;
+    const int64_t part_blocks = std::min<int64_t>(2 * TG_BLOCKS, groups * ((n + TG_MIN_CHUNK - 1) / TG_MIN_CHUNK));
+    L.part = take(sizeof(uint64_t) * 64 * GQ * part_blocks);
     L.cpart = take(sizeof(double) * L.ncb * d);
     L.cen = take(sizeof(double) * d);
     L.apd = take(sizeof(double) * L.nab);
@@ -1042,9 +1138,10 @@ static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float
                          int32_t *g_deg, const int32_t *ep, int32_t *roots, int32_t *n_roots) {
     hipStream_t st = ctx->stream;
     int32_t *cnt = (int32_t *)(w + L.cnt), *U = (int32_t *)(w + L.rev), *visited = (int32_t *)(w + L.visited),
-            *fa = (int32_t *)(w + L.fa), *fb = (int32_t *)(w + L.fb), *empty = (int32_t *)(w + L.empty);
+            *fa = (int32_t *)(w + L.fa), *fb = (int32_t *)(w + L.fb), *queue = (int32_t *)(w + L.empty),
+            *qvalid = (int32_t *)(w + L.qvalid), *F = (int32_t *)(w + L.free_ids);
     int64_t *off = (int64_t *)(w + L.off);
-    uint64_t *keys = (uint64_t *)(w + L.keys);
+    uint64_t *keys = (uint64_t *)(w + L.keys), *part = (uint64_t *)(w + L.part);
     ConnState *cs = (ConnState *)(w + L.cs);
     int32_t *rts = roots ? roots : (int32_t *)(w + L.p_ids);
     const unsigned nbn = (unsigned)((n + 255) / 256);
@@ -1087,18 +1184,39 @@ static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float
     PG_TRY(read_back(ctx, &m64, off + nu));
     const int32_t m = (int32_t)m64;
 
+    // the free set F: nodes below degree R now
+    hipLaunchKernelGGL(k_flag_free, dim3(nbn), dim3(256), 0, st, g_deg, n, R, cnt);
+    PG_TRY(scan_exclusive(ctx, cnt, off, n, w + L.scan_tmp));
+    hipLaunchKernelGGL(k_scatter_free, dim3(nbn), dim3(256), 0, st, g_deg, n, R, off, F);
+    PG_HIP(hipGetLastError());
+    int64_t nf64 = 0;
+    PG_TRY(read_back(ctx, &nf64, off + n));
+    const int32_t nf = (int32_t)nf64;
+    const unsigned nbf = (unsigned)std::max<int64_t>(1, (nf + 255) / 256);
+
     for (int32_t b0 = 0; b0 < m; b0 += CONNECT_BATCH) {
         const int32_t b1 = std::min<int32_t>(m, b0 + CONNECT_BATCH);
         PG_HIP(hipMemsetAsync(&cs->n_empty, 0, sizeof(int32_t), st));
         hipLaunchKernelGGL(k_root_lists, dim3((unsigned)((b1 - b0 + 3) / 4)), dim3(256), 0, st, X, ldx, d, n, R,
-                           cand, C, rts, b0, b1, tt, g_deg, keys, empty, cs);
+                           cand, C, rts, b0, b1, tt, g_deg, keys, queue, qvalid, cs);
         PG_HIP(hipGetLastError());
         int32_t ne = 0;
         PG_TRY(read_back(ctx, &ne, &cs->n_empty));
-        if (ne > 0) {
-            hipLaunchKernelGGL(k_global_nearest, dim3(nbn, (unsigned)((ne + GQ - 1) / GQ)), dim3(256), 0, st, X,
-                               ldx, d, n, R, rts, tt, g_deg, empty, ne, b0, keys, C);
+        if (ne > 0 && nf > 0) {
+            const int64_t groups = (ne + GQ - 1) / GQ;
+            int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((TG_BLOCKS + groups - 1) / groups,
+                                                                    (nf + TG_MIN_CHUNK - 1) / TG_MIN_CHUNK));
+            const int64_t chunk = ((nf + nchunk - 1) / nchunk + TG_TILE - 1) / TG_TILE * TG_TILE;
+            nchunk = (nf + chunk - 1) / chunk;
+            hipLaunchKernelGGL(k_global_topg, dim3((unsigned)nchunk, (unsigned)groups), dim3(256), 0, st, X, ldx, d,
+                               R, rts, tt, g_deg, F, nf, (int32_t)chunk, (int32_t)nchunk, queue, qvalid, ne, b0, C,
+                               keys, part);
             PG_HIP(hipGetLastError());
+            if (nchunk > 1) {
+                hipLaunchKernelGGL(k_topg_merge, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, st, part,
+                                   (int32_t)nchunk, queue, qvalid, ne, b0, C, keys);
+                PG_HIP(hipGetLastError());
+            }
         }
         PG_TRY(write_to(ctx, &cs->idx, b0));
         for (;;) {
@@ -1106,17 +1224,14 @@ static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float
             PG_HIP(hipGetLastError());
             int32_t stop = -1;
             PG_TRY(read_back(ctx, &stop, &cs->stop_root));
-            if (stop < 0) break;
-            PG_TRY(write_to(ctx, &cs->nearest, (unsigned long long)KEY_INF));
-            hipLaunchKernelGGL(k_nearest_at, dim3(nbn), dim3(256), 0, st, X, ldx, d, n, R, tt, g_deg, cs);
-            hipLaunchKernelGGL(k_attach, dim3(1), dim3(1), 0, st, g_ids, g_d2, g_deg, R, cs);
-            PG_HIP(hipGetLastError());
-            int32_t ovf = 0;
-            PG_TRY(read_back(ctx, &ovf, &cs->overflow));
-            if (ovf) {
+            if (stop == -1) break;
+            if (stop == -2) {
                 set_error("pg_prune: connect found every reachable node at degree R=%d", R);
                 return PG_EOVERFLOW;
             }
+            hipLaunchKernelGGL(k_nearest_at, dim3(nbf), dim3(256), 0, st, X, ldx, d, R, F, nf, tt, g_deg, cs);
+            hipLaunchKernelGGL(k_attach, dim3(1), dim3(1), 0, st, g_ids, g_d2, g_deg, R, cs);
+            PG_HIP(hipGetLastError());
         }
     }
     if (n_roots) *n_roots = m;

@@ -236,6 +236,24 @@ def test_connect_saturation_bit_exact(pg, oracle, datagen, nn, d, nc, sigma, C, 
     assert np.array_equal(host(g["d2"]), r["d2"].astype(np.float32))
 
 
+@pytest.mark.parametrize("R", [8, 12])
+def test_connect_alpha_graph_bit_exact(pg, oracle, datagen, R):
+    # alpha = 65 on exact lists in 128 dimensions: after the reverse re-prune
+    # almost every node sits at degree R, so most roots have no usable
+    # candidate and take the nearest free node of the whole graph (at R = 8
+    # there are more roots than free nodes)
+    X, _ = datagen.sift_like(8000, 0, d=128, n_clusters=80, sigma=20.0, seed=31)
+    cand = _exact_lists(oracle, X, 32)
+    g = pg.prune(dev(X), dev(cand), R, alpha_deg=65.0)
+    r = oracle.refine(X, cand, R, alpha_deg=65.0)
+    log("roots gpu", len(g["roots"]), "oracle", len(r["roots"]))
+    assert len(r["roots"]) > 200
+    assert np.array_equal(host(g["roots"]), r["roots"])
+    assert np.array_equal(host(g["deg"]), r["deg"])
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert np.array_equal(host(g["d2"]), r["d2"].astype(np.float32))
+
+
 def test_connect_overflow_is_reported(pg, oracle, datagen):
     # R = 2 on tight clusters: at some turn every reached node has degree R
     X, _ = datagen.sift_like(1500, 0, d=8, n_clusters=30, sigma=2.0, seed=15)
