@@ -1,11 +1,22 @@
 // search.hip -- beam search (the paper's Alg. 1, KANNSearch) for gfx950.
 //
-// One wave per query.  The pool (<= L keys, ascending by (d2, id), plus an
-// expanded flag) lives in LDS.  Each step expands the first unexpanded pool
-// entry: its <= R out-neighbours get their squared distance to the query
-// (one lane each), candidates already in the pool or not better than the
-// L-th pool key are dropped, the rest are sorted with a wave64 bitonic sort
-// and merged into the pool by merge-path ranks (binary searches in LDS).
+// A wave serves 64 / HW queries, one per segment of HW lanes, with HW the
+// smallest of 32 and 64 that holds a node's R out-neighbours: at R <= 32 two
+// queries share a wave and every lane computes a distance.  Each query keeps
+// its pool (<= L keys, ascending by (d2, id), plus an expanded flag) in its
+// own LDS slice and expands one node per step, as Alg. 1 does; the segments
+// of a wave step together.
+//
+// A step expands the first unexpanded pool entry: the node's adjacency row
+// and degree load together, its out-neighbours get their squared distance to
+// the query (one lane each), candidates already in the pool or not better
+// than the L-th pool key are dropped, and the rest are sorted with a bitonic
+// sort over the segment.  Each candidate carries its insertion point in the
+// pool (the binary search that found it absent), so the merge moves pool
+// entries in place, top chunk first, by the number of candidates inserted
+// below them, and drops the candidates into the gaps.  The first unexpanded
+// entry is tracked from a cursor: entries below both the expanded position
+// and the lowest insertion point stay expanded.
 //
 // Alg. 1 keeps a pool only; the oracle also remembers every node it has
 // evaluated.  Checking the pool alone gives the same search: a node that
@@ -31,6 +42,50 @@ __device__ __forceinline__ int lds_lower_bound(const uint64_t *a, int len, uint6
     return lo;
 }
 
+// bits of a wave ballot that belong to segment s of HW lanes
+template <int HW>
+__device__ __forceinline__ uint64_t seg_bits(uint64_t ballot, int s) {
+    if constexpr (HW == PG_WAVE)
+        return ballot;
+    else
+        return (ballot >> (s * HW)) & ((1ull << HW) - 1);
+}
+
+// ascending bitonic sort inside each segment of HW lanes; payload p travels
+// with its key
+template <int HW>
+__device__ __forceinline__ void seg_sort(uint64_t &k, int &p) {
+    const int sl = lane_id() % HW;
+#pragma unroll
+    for (int size = 2; size <= HW; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint64_t ok = shfl_xor64(k, j);
+            const int op = __shfl_xor(p, j, PG_WAVE);
+            const bool asc = (sl & size) == 0;
+            const bool lower = (sl & j) == 0;
+            const bool take = (lower == asc) ? (ok < k) : (ok > k);
+            if (take) {
+                k = ok;
+                p = op;
+            }
+        }
+    }
+}
+
+// row staging: dimensions per slice, LDS floats per staged row (padded
+// against bank conflicts of the per-lane row reads)
+constexpr int ST_DIMS = 32;
+constexpr int ST_STRIDE = 36;
+constexpr size_t ST_BYTES = sizeof(float) * PG_WAVE * ST_STRIDE;
+
+// LDS bytes of one query's slice: query vector, pool keys, pool flags
+__host__ __device__ inline size_t search_slice_bytes(int d, int L) {
+    return ((sizeof(float) * (size_t)((d + 3) & ~3) + sizeof(uint64_t) * (size_t)L + (size_t)L) + 15) &
+           ~(size_t)15;
+}
+
+template <int HW>
 __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int64_t ldx, int d,
                                                int64_t n, const int32_t *__restrict__ g, int R,
                                                const int32_t *__restrict__ deg,
@@ -40,100 +95,195 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
                                                const int32_t *__restrict__ exclude, int k, int L,
                                                int32_t *__restrict__ out_ids,
                                                float *__restrict__ out_d2) {
+    constexpr int QPW = PG_WAVE / HW;
     extern __shared__ __align__(16) unsigned char smem[];
-    float *qv = reinterpret_cast<float *>(smem);
-    uint64_t *pa = reinterpret_cast<uint64_t *>(qv + ((d + 3) & ~3));
-    uint64_t *pb = pa + L;
-    uint64_t *cand = pb + L;
-    uint8_t *fa = reinterpret_cast<uint8_t *>(cand + PG_WAVE);
-    uint8_t *fb = fa + L;
     const int lane = lane_id();
-    const int64_t qi = blockIdx.x;
-    if (qi >= nq) return;
-    for (int j = lane; j < d; j += PG_WAVE) qv[j] = Q[qi * ldq + j];
+    const int s = lane / HW, sl = lane % HW, base = s * HW;
+    unsigned char *slice = smem + (size_t)s * search_slice_bytes(d, L);
+    float *qv = reinterpret_cast<float *>(slice);
+    uint64_t *pa = reinterpret_cast<uint64_t *>(qv + ((d + 3) & ~3));
+    uint8_t *fa = reinterpret_cast<uint8_t *>(pa + L);
+    float *tile = reinterpret_cast<float *>(smem + QPW * search_slice_bytes(d, L));
+    const int64_t qi = (int64_t)blockIdx.x * QPW + s;
+    const bool live = qi < nq;
+    if (live)
+        for (int j = sl; j < d; j += HW) qv[j] = Q[qi * ldq + j];
     __builtin_amdgcn_wave_barrier();
-    int size = 0;
+    int size = 0;   // pool size of this lane's query (uniform over its segment)
+    int lowest;     // lowest insertion point of the current step
 
-    // merge the sorted, de-duplicated keys ck (one per lane, KEY_INF padded,
-    // none already in the pool) into the pool; new entries are unexpanded
-    auto merge_in = [&](uint64_t ck, int cm) {
-        cand[lane] = ck;
-        __builtin_amdgcn_wave_barrier();
-        for (int p = lane; p < size; p += PG_WAVE) {
-            const uint64_t x = pa[p];
-            const int np = p + lds_lower_bound(cand, cm, x);
-            if (np < L) {
-                pb[np] = x;
-                fb[np] = fa[p];
+    // keys of the candidate ids (one per lane) that enter the pool: distance,
+    // filter, sort, compact, then the in-place merge
+    auto prepare = [&](int32_t id) {
+        if (id >= n) id = -1;
+        // canonical distance chain of each lane's row to its query; the rows
+        // of the wave arrive one 32-dimension slice at a time, eight lanes per
+        // row reading whole 128-byte lines, through the LDS tile, the next
+        // slice loading while the current one is summed
+        int32_t rid[PG_WAVE / 8];
+#pragma unroll
+        for (int i = 0; i < PG_WAVE / 8; ++i) rid[i] = __shfl(id, i * 8 + (lane >> 3), PG_WAVE);
+        const int part = (lane & 7) * 4;
+        float4 v[PG_WAVE / 8];
+        auto fetch = [&](int c) {
+            const int w = min(ST_DIMS, d - c);
+#pragma unroll
+            for (int i = 0; i < PG_WAVE / 8; ++i) {
+                v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (rid[i] >= 0 && part < w)
+                    v[i] = *reinterpret_cast<const float4 *>(X + (int64_t)rid[i] * ldx + c + part);
             }
+        };
+        float acc = 0.f;
+        fetch(0);
+        for (int c = 0; c < d; c += ST_DIMS) {
+            const int w = min(ST_DIMS, d - c);
+#pragma unroll
+            for (int i = 0; i < PG_WAVE / 8; ++i)
+                *reinterpret_cast<float4 *>(tile + (i * 8 + (lane >> 3)) * ST_STRIDE + part) = v[i];
+            // the next slice is in flight while this one is summed
+            if (c + ST_DIMS < d) fetch(c + ST_DIMS);
+            __builtin_amdgcn_wave_barrier();
+            for (int j = 0; j < w; j += 4) {
+                const float4 x = *reinterpret_cast<const float4 *>(tile + lane * ST_STRIDE + j);
+                const float4 y = *reinterpret_cast<const float4 *>(qv + c + j);
+                float t;
+                t = y.x - x.x;
+                acc = fmaf(t, t, acc);
+                t = y.y - x.y;
+                acc = fmaf(t, t, acc);
+                t = y.z - x.z;
+                acc = fmaf(t, t, acc);
+                t = y.w - x.w;
+                acc = fmaf(t, t, acc);
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        if (lane < cm) {
-            const int np = lane + lds_lower_bound(pa, size, ck);
-            if (np < L) {
-                pb[np] = ck;
-                fb[np] = 0;
+        uint64_t key = id >= 0 ? pack_key(acc, id) : KEY_INF;
+        int at = 0;
+        if (key != KEY_INF && size == L && key >= pa[L - 1]) key = KEY_INF;
+        if (key != KEY_INF && size > 0) {
+            at = lds_lower_bound(pa, size, key);
+            if (at < size && pa[at] == key) key = KEY_INF;
+        }
+        // nothing left in any query of the wave: no sort, no merge
+        if (__ballot(key != KEY_INF) == 0) return;
+        seg_sort<HW>(key, at);
+        const uint64_t prev = shfl64(key, base + max(sl - 1, 0));
+        const bool valid = key != KEY_INF && !(sl > 0 && prev == key);
+        // compact the valid keys to the front of the segment
+        const uint64_t m = seg_bits<HW>(__ballot(valid), s);
+        const int cm = __popcll(m);
+        const uint64_t below = sl ? (m & ((1ull << sl) - 1)) : 0ull;
+        const uint64_t below_inv = sl ? (~m & ((1ull << sl) - 1)) : 0ull;
+        const int dst = base + (valid ? __popcll(below) : cm + __popcll(below_inv));
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst * 4, (int)(uint32_t)key);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst * 4, (int)(uint32_t)(key >> 32));
+        at = __builtin_amdgcn_ds_permute(dst * 4, at);
+        key = (((uint64_t)hi << 32) | lo);
+        // candidates j < cm, ascending, with insertion points at_j (non-
+        // decreasing): candidate j goes to at_j + j, pool entry p to p plus
+        // the number of j with at_j <= p
+        int cmax = cm;
+#pragma unroll
+        for (int q = 0; q < QPW; ++q) cmax = max(cmax, __builtin_amdgcn_readlane(cm, q * HW));
+        if (cmax == 0) return;
+        const int at0 = __shfl(at, base, PG_WAVE);
+        if (cm > 0) lowest = min(lowest, at0);
+        // chunks [c_lo, c_hi) of the pool hold the entries that move
+        const int c_hi = cm > 0 ? (size + HW - 1) / HW : 0;
+        const int c_lo = cm > 0 ? at0 / HW : 0x7fffffff;
+        int chi = c_hi, clo = c_lo;
+#pragma unroll
+        for (int q = 0; q < QPW; ++q) {
+            chi = max(chi, __builtin_amdgcn_readlane(c_hi, q * HW));
+            clo = min(clo, __builtin_amdgcn_readlane(c_lo, q * HW));
+        }
+        for (int c = chi - 1; c >= clo; --c) {
+            const int p = c * HW + sl;
+            const bool mv = cm > 0 && p < size && p >= at0;
+            uint64_t v = 0;
+            uint8_t f = 0;
+            if (mv) {
+                v = pa[p];
+                f = fa[p];
             }
+            // number of candidates with at_j <= p (binary lifting over the
+            // ascending at_j of the segment)
+            int sh = 0;
+#pragma unroll
+            for (int step = HW / 2; step > 0; step >>= 1) {
+                const int probe = sh + step - 1;
+                const int a = __shfl(at, base + probe, PG_WAVE);
+                if (probe < cm && a <= p) sh += step;
+            }
+            {
+                const int a = __shfl(at, base + min(sh, HW - 1), PG_WAVE);
+                if (sh < cm && a <= p) sh += 1;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (mv && p + sh < L) {
+                pa[p + sh] = v;
+                fa[p + sh] = f;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (sl < cm && at + sl < L) {
+            pa[at + sl] = key;
+            fa[at + sl] = 0;
         }
         __builtin_amdgcn_wave_barrier();
         size = min(L, size + cm);
-        for (int p = lane; p < size; p += PG_WAVE) {
-            pa[p] = pb[p];
-            fa[p] = fb[p];
-        }
-        __builtin_amdgcn_wave_barrier();
     };
 
-    // keys of the candidate ids (one per lane) that may enter the pool
-    auto prepare = [&](int32_t id) -> int {
-        uint64_t key = KEY_INF;
-        if (id >= 0 && id < n) key = pack_key(dist_chain(qv, X + (int64_t)id * ldx, d), id);
-        if (key != KEY_INF && size == L && key >= pa[L - 1]) key = KEY_INF;
-        if (key != KEY_INF && size > 0) {
-            const int at = lds_lower_bound(pa, size, key);
-            if (at < size && pa[at] == key) key = KEY_INF;
-        }
-        int dummy = 0;
-        wave_sort(key, dummy);
-        const uint64_t prev = shfl64(key, max(lane - 1, 0));
-        const bool valid = key != KEY_INF && !(lane > 0 && prev == key);
-        const int cm = wave_compact(key, dummy, valid);
-        if (cm) merge_in(key, cm);
-        return cm;
-    };
-
+    lowest = 0x7fffffff;
     if (query_entry)
-        prepare(lane == 0 ? query_entry[qi] : -1);
+        prepare((live && sl == 0) ? query_entry[qi] : -1);
     else
-        for (int b = 0; b < n_entry; b += PG_WAVE) prepare(b + lane < n_entry ? entries[b + lane] : -1);
+        for (int b = 0; b < n_entry; b += HW) prepare((live && b + sl < n_entry) ? entries[b + sl] : -1);
 
+    int start = 0;  // every pool entry below it is expanded
     while (true) {
+        // first unexpanded entry at or after start among the first min(L, size)
         int first = 0x7fffffff;
         const int lim = min(L, size);
-        for (int p = lane; p < lim; p += PG_WAVE)
-            if (!fa[p]) {
-                first = p;
+        for (int c0 = start; c0 < lim; c0 += HW) {
+            const int p = c0 + sl;
+            const uint64_t m = seg_bits<HW>(__ballot(p < lim && !fa[p]), s);
+            if (m) {
+                first = c0 + __builtin_ctzll(m);
                 break;
             }
-#pragma unroll
-        for (int o = 1; o < PG_WAVE; o <<= 1) first = min(first, __shfl_xor(first, o, PG_WAVE));
-        if (first == 0x7fffffff) break;
-        const int32_t x = key_id(pa[first]);
+        }
+        const bool active = first != 0x7fffffff;
+        if (__ballot(active) == 0) break;
+        int32_t x = 0, dx = 0;
+        if (active) {
+            x = key_id(pa[first]);
+            __builtin_amdgcn_wave_barrier();
+            if (sl == 0) fa[first] = 1;
+            dx = min(deg[x], R);
+        }
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) fa[first] = 1;
-        __builtin_amdgcn_wave_barrier();
-        const int dx = min(deg[x], R);
-        for (int b = 0; b < dx; b += PG_WAVE) prepare(b + lane < dx ? g[(int64_t)x * R + b + lane] : -1);
+        lowest = 0x7fffffff;
+        for (int b = 0; b < R; b += HW) {
+            const int j = b + sl;
+            const int32_t nb = (active && j < R) ? g[(int64_t)x * R + j] : -1;
+            prepare(j < dx ? nb : -1);
+        }
+        if (active) start = min(first + 1, lowest);
     }
+    if (!live) return;
     // position of the excluded node in the pool (it appears at most once)
     int skip = 0x7fffffff;
     if (exclude) {
         const int32_t ex = exclude[qi];
-        for (int p = lane; p < size; p += PG_WAVE)
+        for (int p = sl; p < size; p += HW)
             if (key_id(pa[p]) == ex) skip = p;
 #pragma unroll
-        for (int o = 1; o < PG_WAVE; o <<= 1) skip = min(skip, __shfl_xor(skip, o, PG_WAVE));
+        for (int o = 1; o < HW; o <<= 1) skip = min(skip, __shfl_xor(skip, o, PG_WAVE));
     }
-    for (int j = lane; j < k; j += PG_WAVE) {
+    for (int j = sl; j < k; j += HW) {
         const int p = j + (j >= skip ? 1 : 0);
         const bool have = p < size;
         out_ids[qi * k + j] = have ? key_id(pa[p]) : -1;
@@ -172,12 +322,19 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         return PG_EUNSUPPORTED;
     }
     if (nq == 0) return PG_OK;
-    const size_t lds = sizeof(float) * ((d + 3) & ~3) + sizeof(uint64_t) * (2 * (size_t)p->L + PG_WAVE) +
-                       2 * (size_t)p->L;
+    // two queries per wave when a node's out-neighbours fit 32 lanes and two
+    // LDS slices stay within 64 KB
+    const size_t slice = search_slice_bytes(d, p->L);
+    const bool pair = R <= 32 && 2 * slice + ST_BYTES <= 65536;
     TimedLaunch tl(ctx, K_SEARCH, -1.0);
-    hipLaunchKernelGGL(k_search, dim3((unsigned)nq), dim3(64), lds, ctx->stream, X, ldx, d, n, g_ids, R,
-                       g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry, p->exclude, p->k, p->L,
-                       out_ids, out_d2);
+    if (pair)
+        hipLaunchKernelGGL(k_search<32>, dim3((unsigned)((nq + 1) / 2)), dim3(64), 2 * slice + ST_BYTES, ctx->stream, X,
+                           ldx, d, n, g_ids, R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry,
+                           p->exclude, p->k, p->L, out_ids, out_d2);
+    else
+        hipLaunchKernelGGL(k_search<64>, dim3((unsigned)nq), dim3(64), slice + ST_BYTES, ctx->stream, X, ldx, d, n, g_ids,
+                           R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry, p->exclude, p->k,
+                           p->L, out_ids, out_d2);
     PG_HIP(hipGetLastError());
     return PG_OK;
 }

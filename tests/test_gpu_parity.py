@@ -351,13 +351,30 @@ def test_prune_alpha_float_decisions(pg, oracle, datagen):
 
 # ---------------------------------------------------------------- search
 def test_search_bit_exact(pg, oracle, datagen):
-    X, Q = datagen.sift_like(4000, 300, d=32, n_clusters=10, sigma=10.0, seed=9)
+    X, Q = datagen.sift_like(4000, 299, d=32, n_clusters=10, sigma=10.0, seed=9)
     cand = _exact_lists(oracle, X, 24)
     r = oracle.refine(X, cand, 12)
     entries = np.concatenate([[r["ep"]], r["roots"]]).astype(np.int32)
     for L in (10, 37, 128):
         ids, d2 = pg.search(dev(X), dev(r["ids"]), dev(r["deg"]), dev(Q), dev(entries), 10, L)
         rid, rd2, _ = oracle.search(X, r["ids"], r["deg"], Q, entries, 10, L)
+        assert np.array_equal(host(ids), rid), L
+        assert np.array_equal(host(d2), rd2.astype(np.float32)), L
+
+
+@pytest.mark.parametrize("R,nq", [(48, 301), (80, 129), (1, 7)])
+def test_search_wide_rows_bit_exact(pg, oracle, datagen, R, nq):
+    # rows wider than 32 (one query per wave) and wider than 64 (neighbours in
+    # chunks); odd query counts leave half a wave without a query
+    X, Q = datagen.sift_like(3000, nq, d=32, n_clusters=8, sigma=12.0, seed=17)
+    rng = np.random.default_rng(R)
+    g = rng.integers(0, 3000, size=(3000, R), dtype=np.int64).astype(np.int32)
+    deg = rng.integers(0, R + 1, size=3000).astype(np.int32)
+    g[np.arange(R)[None, :] >= deg[:, None]] = -1
+    entries = rng.choice(3000, size=70, replace=False).astype(np.int32)
+    for L in (16, 100):
+        ids, d2 = pg.search(dev(X), dev(g), dev(deg), dev(Q), dev(entries), 10, L)
+        rid, rd2, _ = oracle.search(X, g, deg, Q, entries, 10, L)
         assert np.array_equal(host(ids), rid), L
         assert np.array_equal(host(d2), rd2.astype(np.float32)), L
 
