@@ -125,6 +125,10 @@ def main():
     ap.add_argument("--iternsg", type=int, default=0, metavar="I",
                     help="also build the IterNSG graph (Alg. 6) with I OptKCNA rounds on the "
                          "fastest path and report its build time and search recall")
+    ap.add_argument("--hnsw", type=int, default=0, metavar="EF",
+                    help="also build the global HNSW (Alg. 7, FastHNSW) with ef=EF, M=R, k0=K, "
+                         "alpha 65 degrees and 2 OptKCNA rounds per layer on the fastest path, "
+                         "and report its build time and layered-search recall")
     ap.add_argument("--paths", default="fp32,fp16",
                     help="comma-separated join paths to measure: fp32, fp16, bf16, fp32-valu")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -191,6 +195,8 @@ def main():
     }
     if args.iternsg:
         out["iter_nsg"] = run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[best])
+    if args.hnsw:
+        out["fast_hnsw"] = run_hnsw(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[best])
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_sample} points")
         out["cpu_baseline"] = cpu_baseline(w, X, args.cpu_sample)
@@ -231,6 +237,45 @@ def run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, path):
             "build_ms": 1000.0 * build_s, "points_per_s": w["n"] / build_s, "L": chosen,
             "search_ladder": ladder,
             "qps_batch": Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)}
+
+
+def run_hnsw(args, w, pg, torch, ctx, Xd, Qd, gt, path):
+    """FastHNSW (Alg. 7): layers drawn from seeded uniforms, each layer built by
+    IterNSG with ef = args.hnsw, M = R, k0 = K, alpha 65 degrees, 2 rounds;
+    build time (untimed warm-up first), then the layered-search ladder."""
+    from paper_2410_01231_amd import datagen
+    K, R, S, ef = w["K"], w["R"], w["S"], args.hnsw
+    U = torch.from_numpy(datagen.uniform_open01(w["n"], seed=7)).cuda()
+
+    def build():
+        return pg.opt_hnsw(Xd, U, K, ef, R, 65.0, iterations=2, S=S, max_iters=w["iters"], seed=1,
+                           delta=0.001, precision=path["precision"], ctx=ctx)
+    build()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = build()
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    ladder, chosen = [], None
+    for L in L_LADDER:
+        f, _ = pg.hnsw_search(H, Qd, 10, L, ctx=ctx)
+        r = recall(f.cpu().numpy(), gt)
+        ladder.append((L, r))
+        log(f"[bench] hnsw ef_search={L} recall@10={r:.4f}")
+        if r >= 0.95:
+            chosen = L
+            break
+    Ls = chosen or L_LADDER[-1]
+    pg.hnsw_search(H, Qd, 10, Ls, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pg.hnsw_search(H, Qd, 10, Ls, ctx=ctx)
+    torch.cuda.synchronize()
+    qs = time.perf_counter() - t0
+    sizes = [int(l["nodes"].numel()) for l in H["layers"]]
+    return {"ef": ef, "M": R, "k0": K, "alpha_deg": 65.0, "rounds": 2, "layer_sizes": sizes,
+            "build_ms": 1000.0 * build_s, "points_per_s": w["n"] / build_s, "ef_search": chosen,
+            "search_ladder": ladder, "qps_batch": Qd.shape[0] / qs}
 
 
 # join paths: precision code of pg_knn_build, dtype the join computes in

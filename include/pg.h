@@ -257,6 +257,20 @@ pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t l
                     const float *Q, int64_t nq, int64_t ldq,
                     const pg_search_params *p, int32_t *out_ids, float *out_d2);
 
+/* ------------------------------------------------------------------ */
+/* Global HNSW construction (Alg. 7): layer assignment                 */
+/* ------------------------------------------------------------------ */
+/* The highest layer of every node, as HNSW draws it (Alg. 7, first loop;
+ * Section 5.3): levels[u] = floor(-ln U[u] / ln M), evaluated exactly as the
+ * number of i >= 1 with U[u] * M^i <= 1 (M^i exact in double precision:
+ * levels stop at 31 and at the last i with M^i below 2^53).  U (device, n doubles in (0, 1]) holds the uniform
+ * draws; levels (device, n int32) receives the layers and max_level
+ * (device, one int32) their maximum m_L.  The layers themselves are built
+ * with pg_knn_build, pg_prune and pg_search on each layer's rows (IterNSG),
+ * or as complete graphs when a layer has at most M nodes. */
+pg_status pg_hnsw_levels(pg_ctx *ctx, const double *U, int64_t n, int32_t M, int32_t *levels,
+                         int32_t *max_level);
+
 #ifdef __cplusplus
 }
 #endif

@@ -281,3 +281,77 @@ def recall_at_k(found_ids, true_ids):
     for f, t in zip(found_ids, true_ids):
         hits += len(set(int(x) for x in f[:k] if x >= 0) & set(int(x) for x in t))
     return hits / (k * len(true_ids))
+
+
+# ------------------------------------------------------------------ OptHNSW (Alg. 7)
+
+def hnsw_levels(U, M):
+    """Highest layer of each node, as HNSW draws it (Alg. 7, first loop):
+    floor(-ln U / ln M) for U in (0, 1].  Evaluated as the number of i >= 1
+    with U * M^i <= 1, M^i being an exact integer in double precision, so no
+    logarithm enters.  Levels stop at 31 and at the last i with M^i below
+    2^53 (U would have to be below 2^-53 to reach it)."""
+    U = np.asarray(U, dtype=np.float64)
+    out = np.zeros(len(U), np.int32)
+    for j, u in enumerate(U.tolist()):
+        lev, p = 0, float(M)
+        while lev < 31 and u * p <= 1.0 and p < 2.0 ** 53:
+            lev += 1
+            p *= M
+        out[j] = lev
+    return out
+
+
+def opt_hnsw(X, U, k0, ef, M, alpha_deg, iterations, S, max_iters, seed, delta):
+    """OptHNSW (Alg. 7).  D_i = nodes whose highest layer is at least i.  A
+    layer with at most M nodes links every node to all the others ((d2, id)
+    order); a larger one is IterNSG(D_i, k0, ef, ef, M, alpha) on its rows,
+    with NN-Descent K = min(k0, |D_i| - 1), S capped at K, the stop rule
+    delta |D_i| K, and C(u) the ef - 1 entries other than u of a pool of
+    width ef.  The entry point is the smallest id of the top layer.  Returns
+    levels, max_level, ep and per layer: nodes (global ids, ascending), ids
+    and deg (local ids)."""
+    X = _f32(X)
+    levels = hnsw_levels(U, M)
+    top = int(levels.max())
+    layers = []
+    for i in range(top + 1):
+        nodes = np.nonzero(levels >= i)[0].astype(np.int32)
+        m = len(nodes)
+        Xi = X[nodes]
+        if m <= M:
+            ids = np.full((m, M), -1, np.int32)
+            if m >= 2:
+                nb, _ = exact_knn(Xi, Xi, m - 1, exclude=np.arange(m, dtype=np.int32))
+                ids[:, :m - 1] = nb
+            deg = np.full(m, m - 1, np.int32)
+        else:
+            K = min(k0, m - 1)
+            Si = min(S, K)
+            g = iter_nsg(Xi, K, Si, max_iters, seed, int(delta * m * K), ef - 1, ef, M, alpha_deg,
+                         iterations)
+            ids, deg = g["ids"], g["deg"]
+        layers.append({"nodes": nodes, "ids": ids, "deg": deg})
+    return {"levels": levels, "max_level": top, "ep": int(layers[top]["nodes"][0]), "layers": layers}
+
+
+def hnsw_search(X, H, Q, k, ef):
+    """Greedy routing (KANNSearch with k = L = 1) from the entry point down to
+    layer 1, each layer entered at the node found above it, then KANNSearch
+    with L = ef on layer 0; one query at a time."""
+    X, Q = _f32(X), _f32(Q)
+    nq = len(Q)
+    ids = np.empty((nq, k), np.int32)
+    d2 = np.empty((nq, k), np.float64)
+    for q in range(nq):
+        w = H["ep"]
+        for i in range(H["max_level"], 0, -1):
+            lay = H["layers"][i]
+            local = int(np.searchsorted(lay["nodes"], w))
+            r, _, _ = search(X[lay["nodes"]], lay["ids"], lay["deg"], Q[q:q + 1],
+                             np.array([local], np.int32), 1, 1)
+            w = int(lay["nodes"][r[0, 0]])
+        lay = H["layers"][0]
+        r, rd, _ = search(X, lay["ids"], lay["deg"], Q[q:q + 1], np.array([w], np.int32), k, ef)
+        ids[q], d2[q] = r[0], rd[0]
+    return ids, d2

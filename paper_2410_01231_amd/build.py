@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpg.so")
-SOURCES = ["api.hip", "knn.hip", "prune.hip", "search.hip"]
+SOURCES = ["api.hip", "knn.hip", "prune.hip", "search.hip", "hnsw.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=off: every fused multiply-add in the kernels is written out
 # explicitly, so distances have one bit pattern wherever they are computed.

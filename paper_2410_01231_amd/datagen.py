@@ -99,3 +99,8 @@ def sample_ids(n: int, count: int, seed: int, sub: int = 9) -> np.ndarray:
 def random_candidates(n: int, C: int, seed: int, sub: int = 11) -> np.ndarray:
     """n x C candidate ids drawn uniformly from [0, n) (repeats and self allowed)."""
     return _rng(seed, sub).integers(0, n, size=(n, C)).astype(np.int32)
+
+
+def uniform_open01(n: int, seed: int, sub: int = 13) -> np.ndarray:
+    """n uniform draws in (0, 1] as float64 (the layer draws of an HNSW build)."""
+    return 1.0 - _rng(seed, sub).random(n)

@@ -54,7 +54,7 @@ class SearchParams(ctypes.Structure):
 
 EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
            "pg_ctx_kernel_time", "pg_ctx_reset_timing", "pg_knn_build_workspace", "pg_knn_build",
-           "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search"]
+           "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search", "pg_hnsw_levels"]
 
 _lib = None
 
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
                              c_size_t, P, P, P, P, P, POINTER(c_int32)]
     lib.pg_search.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, P, P, c_int64, c_int64,
                               POINTER(SearchParams), P, P]
+    lib.pg_hnsw_levels.argtypes = [P, P, c_int64, c_int32, P, P]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("pg_version", "pg_last_error"):
@@ -355,3 +356,88 @@ def build_graph(X, K, R, S=None, max_iters=12, seed=0, delta=0.001, alpha_deg=60
     g = prune(X, ids, R, alpha_deg=alpha_deg, cand_d2=d2, ctx=ctx)
     g["knn_ids"], g["knn_d2"], g["knn_stats"] = ids, d2, st
     return g
+
+
+# ------------------------------------------------------------------ FastHNSW (Alg. 7)
+
+def hnsw_levels(U, M, ctx=None):
+    """Highest layer of every node from its uniform draw U in (0, 1]:
+    floor(-ln U / ln M) (Alg. 7, first loop).  Returns (levels int32, m_L)."""
+    lib = load_library()
+    U = torch.as_tensor(U)
+    if U.dtype != torch.float64 or U.dim() != 1 or not U.is_cuda:
+        raise ValueError("U must be a 1-D float64 CUDA tensor")
+    U = U.contiguous()
+    n = U.numel()
+    levels = torch.empty(n, dtype=torch.int32, device=U.device)
+    top = torch.empty(1, dtype=torch.int32, device=U.device)
+    ctx = ctx or context(U.device.index)
+    _check(lib.pg_hnsw_levels(ctx.handle, _ptr(U), n, M, _ptr(levels), _ptr(top)), "pg_hnsw_levels")
+    return levels, int(top.item())
+
+
+def _complete_layer(Xi, M, ctx):
+    """Every node of a layer with at most M nodes linked to all the others, in
+    (d2, id) order (Alg. 7: N(u) = D_i without u)."""
+    m = Xi.shape[0]
+    ids = torch.full((m, M), -1, dtype=torch.int32, device=Xi.device)
+    deg = torch.full((m,), m - 1, dtype=torch.int32, device=Xi.device)
+    if m >= 2:
+        self_ids = torch.arange(m, dtype=torch.int32, device=Xi.device)
+        nb, _ = exact_knn(Xi, Xi, m - 1, exclude=self_ids, ctx=ctx)
+        ids[:, :m - 1] = nb
+    return ids, deg
+
+
+def opt_hnsw(X, U, k0, ef, M, alpha_deg, iterations=2, S=None, max_iters=12, seed=0, delta=0.001,
+             ctx=None, **knn_kw):
+    """OptHNSW (Alg. 7): layers from the draws U, then every layer D_i with
+    more than M nodes built by IterNSG(D_i, k0, ef, ef, M, alpha) on its own
+    rows, smaller layers as complete graphs; the entry point is the smallest
+    id of the top layer.  In each layer's OptKCNA search the pool holds
+    L = ef entries and C(u) takes the ef - 1 of them other than u; NN-Descent
+    uses K = min(k0, |D_i| - 1) and stops after delta |D_i| K updates.
+    Returns dict(levels, max_level, ep, layers); layer i holds its nodes
+    (global ids, ascending), pos (global -> local id, -1 outside), X (its
+    rows), ids / deg (the graph in local ids)."""
+    X = _dev_f32(X, "X")
+    n = X.shape[0]
+    ctx = ctx or context(X.device.index)
+    levels, top = hnsw_levels(U, M, ctx=ctx)
+    layers = []
+    for i in range(top + 1):
+        nodes = torch.nonzero(levels >= i).flatten().to(torch.int32) if i else \
+            torch.arange(n, dtype=torch.int32, device=X.device)
+        m = nodes.numel()
+        Xi = X if i == 0 else X[nodes.long()].contiguous()
+        if m <= M:
+            ids, deg = _complete_layer(Xi, M, ctx)
+        else:
+            K = min(k0, m - 1)
+            Si = min((K + 1) // 2 if S is None else S, K)
+            g = iter_nsg(Xi, K, M, ef - 1, ef, alpha_deg, iterations, S=Si, max_iters=max_iters,
+                         seed=seed, stop_updates=int(delta * m * K), ctx=ctx, **knn_kw)
+            ids, deg = g["ids"], g["deg"]
+        pos = torch.full((n,), -1, dtype=torch.int32, device=X.device)
+        pos[nodes.long()] = torch.arange(m, dtype=torch.int32, device=X.device)
+        layers.append({"nodes": nodes, "pos": pos, "X": Xi, "ids": ids, "deg": deg})
+    ep = int(layers[top]["nodes"][0].item())
+    return {"levels": levels, "max_level": top, "ep": ep, "layers": layers}
+
+
+def hnsw_search(H, Q, k, ef, ctx=None):
+    """k-ANN search on a layered graph: greedy routing (KANNSearch with
+    k = L = 1) from the entry point down to layer 1, each layer entered at
+    the node found above it, then KANNSearch with L = ef on layer 0.
+    Returns (ids, d2), nq x k, ids global."""
+    layers = H["layers"]
+    Q = _dev_f32(Q, "Q")
+    nq = Q.shape[0]
+    w = torch.full((nq,), H["ep"], dtype=torch.int32, device=Q.device)
+    for i in range(H["max_level"], 0, -1):
+        L_ = layers[i]
+        e = L_["pos"][w.long()].contiguous()
+        f, _ = search(L_["X"], L_["ids"], L_["deg"], Q, None, 1, 1, query_entry=e, ctx=ctx)
+        w = L_["nodes"][f[:, 0].long()].contiguous()
+    L0 = layers[0]
+    return search(L0["X"], L0["ids"], L0["deg"], Q, None, k, ef, query_entry=w, ctx=ctx)
