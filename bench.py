@@ -205,18 +205,27 @@ def main():
 
 def run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, path):
     """IterNSG (Alg. 6) with args.iternsg OptKCNA rounds (alpha 65 degrees, k = K,
-    L = 2K): build time (untimed warm-up first), then the search ladder."""
+    L = 2K): build time without and with P2K (Section 5.4; the graphs must be
+    identical), each after an untimed warm-up, then the search ladder."""
     K, R, S = w["K"], w["R"], w["S"]
 
-    def build():
+    def build(p2k, counts=None):
         return pg.iter_nsg(Xd, K, R, K, 2 * K, 65.0, args.iternsg, S=S, max_iters=w["iters"], seed=1,
-                           delta=0.001, precision=path["precision"], ctx=ctx)
-    build()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g = build()
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
+                           delta=0.001, precision=path["precision"], p2k=p2k, counts=counts, ctx=ctx)
+    times, graphs, counts = {}, {}, {}
+    for p2k in (False, True):
+        build(p2k)
+        torch.cuda.synchronize()
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        t0 = time.perf_counter()
+        graphs[p2k] = build(p2k, cnt)
+        torch.cuda.synchronize()
+        times[p2k] = time.perf_counter() - t0
+        counts[p2k] = [int(x) for x in cnt.cpu().tolist()]
+        log(f"[bench] iternsg p2k={p2k} build {times[p2k]:.3f} s, distances computed/reused {counts[p2k]}")
+    same = all(torch.equal(graphs[False][k], graphs[True][k]) for k in ("ids", "deg", "cand"))
+    g = graphs[True]
+    build_s = times[True]
     entries = torch.cat([g["ep"], g["roots"]]).contiguous()
     ladder, chosen = [], None
     for L in L_LADDER:
@@ -234,8 +243,12 @@ def run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, path):
     s1.record()
     s1.synchronize()
     return {"rounds": args.iternsg, "alpha_deg": 65.0, "k": K, "L_search": 2 * K,
-            "build_ms": 1000.0 * build_s, "points_per_s": w["n"] / build_s, "L": chosen,
-            "search_ladder": ladder,
+            "build_ms": 1000.0 * build_s, "points_per_s": w["n"] / build_s,
+            "build_ms_without_p2k": 1000.0 * times[False],
+            "self_search_distances": {"without_p2k": counts[False][0],
+                                      "with_p2k_computed": counts[True][0],
+                                      "with_p2k_reused": counts[True][1]},
+            "p2k_graph_identical": bool(same), "L": chosen, "search_ladder": ladder,
             "qps_batch": Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)}
 
 

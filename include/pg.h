@@ -243,6 +243,20 @@ typedef struct {
     const int32_t *exclude;     /* optional, device, nq ids: query q returns the
                                    first k pool entries other than exclude[q]
                                    (the search itself still passes through it) */
+    /* P2K (Section 5.4): distances of the same query recorded by an earlier
+       search, used instead of gathering the rows again. */
+    const int32_t *record_ids;  /* optional, device, nq x record_L ids (-1 pads);
+                                   record_d2 holds their canonical squared
+                                   distances to the same query row */
+    const float *record_d2;
+    int32_t record_L;           /* 0 .. 1024 */
+    int32_t *pool_ids;          /* optional, device, nq x L: the final pool of
+                                   each query, (d2, id) order, -1 / +inf pads;
+                                   the record of a later search */
+    float *pool_d2;
+    unsigned long long *counts; /* optional, device, 2 values added to:
+                                   distances computed, distances taken from
+                                   the record */
 } pg_search_params;
 
 /* KANNSearch of Alg. 1 for every query row, starting from the entering
@@ -251,7 +265,11 @@ typedef struct {
  * g_ids is n x R with degrees g_deg.  out_ids / out_d2 are nq x k, padded
  * with -1 / +inf.  With Q = X, query_entry[u] = u and exclude[u] = u this is
  * the search phase of OptKCNA (Alg. 5, Phase 3): KANNSearch(G, u, k, L, u),
- * u not being its own candidate. */
+ * u not being its own candidate.
+ * With a record (P2K), a candidate found there takes the recorded distance
+ * instead of its row: the search, its results and its pool are the same as
+ * without it, provided every recorded distance is the canonical value for
+ * that query row (as pool_d2 of a search of the same row is). */
 pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
                     const int32_t *g_ids, int32_t R, const int32_t *g_deg,
                     const float *Q, int64_t nq, int64_t ldq,

@@ -79,10 +79,28 @@ constexpr int ST_DIMS = 32;
 constexpr int ST_STRIDE = 36;
 constexpr size_t ST_BYTES = sizeof(float) * PG_WAVE * ST_STRIDE;
 
-// LDS bytes of one query's slice: query vector, pool keys, pool flags
-__host__ __device__ inline size_t search_slice_bytes(int d, int L) {
-    return ((sizeof(float) * (size_t)((d + 3) & ~3) + sizeof(uint64_t) * (size_t)L + (size_t)L) + 15) &
+// LDS bytes of one query's slice: query vector, pool keys, record table (RT
+// ids and distances), pool flags
+__host__ __device__ inline size_t search_slice_bytes(int d, int L, int RT) {
+    return ((sizeof(float) * (size_t)((d + 3) & ~3) + sizeof(uint64_t) * (size_t)L +
+             (sizeof(int32_t) + sizeof(float)) * (size_t)RT + (size_t)L) +
+            15) &
            ~(size_t)15;
+}
+
+// P2K record and pool output (all optional)
+struct SearchRecord {
+    const int32_t *ids;        // nq x len, -1 pads
+    const float *d2;
+    int len;
+    int bits;                  // log2 of the LDS table size (0: no record)
+    int32_t *pool_ids;         // nq x L
+    float *pool_d2;
+    unsigned long long *counts;  // computed, taken from the record
+};
+
+__device__ __forceinline__ uint32_t record_slot(int32_t id, int bits) {
+    return ((uint32_t)id * 0x9E3779B1u) >> (32 - bits);
 }
 
 template <int HW>
@@ -94,21 +112,46 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
                                                const int32_t *__restrict__ query_entry,
                                                const int32_t *__restrict__ exclude, int k, int L,
                                                int32_t *__restrict__ out_ids,
-                                               float *__restrict__ out_d2) {
+                                               float *__restrict__ out_d2, SearchRecord rec) {
     constexpr int QPW = PG_WAVE / HW;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
     const int s = lane / HW, sl = lane % HW, base = s * HW;
-    unsigned char *slice = smem + (size_t)s * search_slice_bytes(d, L);
+    const int RT = rec.bits ? 1 << rec.bits : 0;
+    unsigned char *slice = smem + (size_t)s * search_slice_bytes(d, L, RT);
     float *qv = reinterpret_cast<float *>(slice);
     uint64_t *pa = reinterpret_cast<uint64_t *>(qv + ((d + 3) & ~3));
-    uint8_t *fa = reinterpret_cast<uint8_t *>(pa + L);
-    float *tile = reinterpret_cast<float *>(smem + QPW * search_slice_bytes(d, L));
+    int32_t *tid = reinterpret_cast<int32_t *>(pa + L);
+    float *td = reinterpret_cast<float *>(tid + RT);
+    uint8_t *fa = reinterpret_cast<uint8_t *>(td + RT);
+    float *tile = reinterpret_cast<float *>(smem + QPW * search_slice_bytes(d, L, RT));
     const int64_t qi = (int64_t)blockIdx.x * QPW + s;
     const bool live = qi < nq;
     if (live)
         for (int j = sl; j < d; j += HW) qv[j] = Q[qi * ldq + j];
+    // the record as an open-addressing table (at most half full)
+    if (RT) {
+        for (int j = sl; j < RT; j += HW) tid[j] = -1;
+        __builtin_amdgcn_wave_barrier();
+        if (live)
+            for (int j = sl; j < rec.len; j += HW) {
+                const int32_t id = rec.ids[qi * rec.len + j];
+                if (id < 0 || id >= n) continue;
+                const float dv = rec.d2[qi * rec.len + j];
+                uint32_t h = record_slot(id, rec.bits);
+                while (true) {
+                    const int32_t old = atomicCAS(&tid[h], -1, id);
+                    if (old == -1) {
+                        td[h] = dv;
+                        break;
+                    }
+                    if (old == id) break;
+                    h = (h + 1) & (RT - 1);
+                }
+            }
+    }
     __builtin_amdgcn_wave_barrier();
+    unsigned long long n_comp = 0, n_reuse = 0;
     int size = 0;   // pool size of this lane's query (uniform over its segment)
     int lowest;     // lowest insertion point of the current step
 
@@ -116,13 +159,34 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
     // filter, sort, compact, then the in-place merge
     auto prepare = [&](int32_t id) {
         if (id >= n) id = -1;
+        // P2K: a candidate in the record takes the recorded distance
+        bool found = false;
+        float dfound = 0.f;
+        if (RT && id >= 0) {
+            uint32_t h = record_slot(id, rec.bits);
+            while (true) {
+                const int32_t t = tid[h];
+                if (t == id) {
+                    found = true;
+                    dfound = td[h];
+                    break;
+                }
+                if (t == -1) break;
+                h = (h + 1) & (RT - 1);
+            }
+        }
+        if (rec.counts) {
+            n_comp += __popcll(__ballot(id >= 0 && !found));
+            n_reuse += __popcll(__ballot(found));
+        }
+        const int32_t gid = found ? -1 : id;
         // canonical distance chain of each lane's row to its query; the rows
         // of the wave arrive one 32-dimension slice at a time, eight lanes per
         // row reading whole 128-byte lines, through the LDS tile, the next
         // slice loading while the current one is summed
         int32_t rid[PG_WAVE / 8];
 #pragma unroll
-        for (int i = 0; i < PG_WAVE / 8; ++i) rid[i] = __shfl(id, i * 8 + (lane >> 3), PG_WAVE);
+        for (int i = 0; i < PG_WAVE / 8; ++i) rid[i] = __shfl(gid, i * 8 + (lane >> 3), PG_WAVE);
         const int part = (lane & 7) * 4;
         float4 v[PG_WAVE / 8];
         auto fetch = [&](int c) {
@@ -159,7 +223,7 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
             }
             __builtin_amdgcn_wave_barrier();
         }
-        uint64_t key = id >= 0 ? pack_key(acc, id) : KEY_INF;
+        uint64_t key = id >= 0 ? pack_key(found ? dfound : acc, id) : KEY_INF;
         int at = 0;
         if (key != KEY_INF && size == L && key >= pa[L - 1]) key = KEY_INF;
         if (key != KEY_INF && size > 0) {
@@ -273,7 +337,16 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
         }
         if (active) start = min(first + 1, lowest);
     }
+    if (rec.counts && lane == 0) {
+        atomicAdd(&rec.counts[0], n_comp);
+        atomicAdd(&rec.counts[1], n_reuse);
+    }
     if (!live) return;
+    if (rec.pool_ids)
+        for (int p = sl; p < L; p += HW) {
+            rec.pool_ids[qi * L + p] = p < size ? key_id(pa[p]) : -1;
+            rec.pool_d2[qi * L + p] = p < size ? key_d2(pa[p]) : __int_as_float(0x7f800000);
+        }
     // position of the excluded node in the pool (it appears at most once)
     int skip = 0x7fffffff;
     if (exclude) {
@@ -324,17 +397,27 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
     if (nq == 0) return PG_OK;
     // two queries per wave when a node's out-neighbours fit 32 lanes and two
     // LDS slices stay within 64 KB
-    const size_t slice = search_slice_bytes(d, p->L);
+    if (p->record_L < 0 || p->record_L > 1024 || (p->record_L > 0 && (!p->record_ids || !p->record_d2)) ||
+        (!p->pool_ids != !p->pool_d2)) {
+        set_error("pg_search: record needs ids and d2 with 0 <= record_L <= 1024; pool_ids and pool_d2 go together");
+        return PG_EINVAL;
+    }
+    SearchRecord rec{p->record_L ? p->record_ids : nullptr, p->record_d2, p->record_L, 0, p->pool_ids, p->pool_d2,
+                     p->counts};
+    if (p->record_L > 0)
+        while ((1 << rec.bits) < 2 * p->record_L) ++rec.bits;
+    const int RT = rec.bits ? 1 << rec.bits : 0;
+    const size_t slice = search_slice_bytes(d, p->L, RT);
     const bool pair = R <= 32 && 2 * slice + ST_BYTES <= 65536;
     TimedLaunch tl(ctx, K_SEARCH, -1.0);
     if (pair)
         hipLaunchKernelGGL(k_search<32>, dim3((unsigned)((nq + 1) / 2)), dim3(64), 2 * slice + ST_BYTES, ctx->stream, X,
                            ldx, d, n, g_ids, R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry,
-                           p->exclude, p->k, p->L, out_ids, out_d2);
+                           p->exclude, p->k, p->L, out_ids, out_d2, rec);
     else
         hipLaunchKernelGGL(k_search<64>, dim3((unsigned)nq), dim3(64), slice + ST_BYTES, ctx->stream, X, ldx, d, n, g_ids,
                            R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry, p->exclude, p->k,
-                           p->L, out_ids, out_d2);
+                           p->L, out_ids, out_d2, rec);
     PG_HIP(hipGetLastError());
     return PG_OK;
 }

@@ -49,7 +49,9 @@ class PruneParams(ctypes.Structure):
 
 class SearchParams(ctypes.Structure):
     _fields_ = [("k", c_int32), ("L", c_int32), ("n_entry", c_int32), ("entry_ids", c_void_p),
-                ("query_entry", c_void_p), ("exclude", c_void_p)]
+                ("query_entry", c_void_p), ("exclude", c_void_p), ("record_ids", c_void_p),
+                ("record_d2", c_void_p), ("record_L", c_int32), ("pool_ids", c_void_p),
+                ("pool_d2", c_void_p), ("counts", c_void_p)]
 
 
 EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
@@ -253,12 +255,18 @@ def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair
     return {"ids": g_ids, "d2": g_d2, "deg": g_deg, "ep": ep, "roots": roots[:nroots.value]}
 
 
-def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, ctx=None):
-    """Alg. 1 beam search for every row of Q: returns (ids, d2).
+def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, record=None,
+           pool_out=False, counts=None, ctx=None):
+    """Alg. 1 beam search for every row of Q: returns (ids, d2), plus the final
+    pools (pool_ids, pool_d2), nq x L, when pool_out is set.
 
     entries: shared entering points; query_entry (nq ids, optional) gives each
     query its own single entering point instead; exclude (nq ids, optional)
-    leaves one node out of each query's results."""
+    leaves one node out of each query's results.  record (optional pair
+    (ids, d2), nq x r): distances of the same query rows recorded by an
+    earlier search (its pools), reused instead of gathering rows (P2K,
+    Section 5.4); the results do not change.  counts (optional int64 device
+    tensor of 2) is added the distances computed and the ones reused."""
     lib = load_library()
     X, Q = _dev_f32(X, "X"), _dev_f32(Q, "Q")
     g_ids, g_deg = _dev_i32(g_ids, "g_ids"), _dev_i32(g_deg, "g_deg")
@@ -274,33 +282,58 @@ def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, ct
         exclude = _dev_i32(exclude.reshape(-1), "exclude")
         if exclude.numel() != nq:
             raise ValueError("exclude needs one id per query")
+    rec_ids = rec_d2 = None
+    if record is not None:
+        rec_ids, rec_d2 = _dev_i32(record[0], "record ids"), _dev_f32(record[1], "record d2")
+        if rec_ids.dim() != 2 or rec_ids.shape[0] != nq or tuple(rec_d2.shape) != tuple(rec_ids.shape):
+            raise ValueError("record must be two nq x r tensors")
+    if counts is not None and (counts.dtype != torch.int64 or counts.numel() < 2 or not counts.is_cuda):
+        raise ValueError("counts must be a CUDA int64 tensor of 2")
     ids = torch.empty((nq, k), dtype=torch.int32, device=X.device)
     d2 = torch.empty((nq, k), dtype=torch.float32, device=X.device)
+    pool_ids = pool_d2 = None
+    if pool_out:
+        pool_ids = torch.empty((nq, L), dtype=torch.int32, device=X.device)
+        pool_d2 = torch.empty((nq, L), dtype=torch.float32, device=X.device)
     p = SearchParams(k=k, L=L, n_entry=entries.numel() if entries is not None else 0,
                      entry_ids=entries.data_ptr() if entries is not None else None,
                      query_entry=query_entry.data_ptr() if query_entry is not None else None,
-                     exclude=exclude.data_ptr() if exclude is not None else None)
+                     exclude=exclude.data_ptr() if exclude is not None else None,
+                     record_ids=rec_ids.data_ptr() if rec_ids is not None else None,
+                     record_d2=rec_d2.data_ptr() if rec_d2 is not None else None,
+                     record_L=rec_ids.shape[1] if rec_ids is not None else 0,
+                     pool_ids=pool_ids.data_ptr() if pool_out else None,
+                     pool_d2=pool_d2.data_ptr() if pool_out else None,
+                     counts=counts.data_ptr() if counts is not None else None)
     ctx = ctx or context(X.device.index)
     _check(lib.pg_search(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(g_ids), g_ids.shape[1],
                          _ptr(g_deg), _ptr(Q), nq, Q.stride(0), ctypes.byref(p), _ptr(ids), _ptr(d2)),
            "pg_search")
+    if pool_out:
+        return ids, d2, pool_ids, pool_d2
     return ids, d2
 
 
-def search_self(X, g_ids, g_deg, k, L, ctx=None):
+def search_self(X, g_ids, g_deg, k, L, record=None, pool_out=False, counts=None, ctx=None):
     """Search phase of OptKCNA (Alg. 5): KANNSearch(G, u, k, L, u) for every
-    point u, u not being its own candidate.  Returns (ids, d2), n x k."""
+    point u, u not being its own candidate.  Returns (ids, d2), n x k (plus
+    the pools with pool_out; record and counts as in search())."""
     n = X.shape[0]
     selfid = torch.arange(n, dtype=torch.int32, device=X.device)
-    return search(X, g_ids, g_deg, X, None, k, L, query_entry=selfid, exclude=selfid, ctx=ctx)
+    return search(X, g_ids, g_deg, X, None, k, L, query_entry=selfid, exclude=selfid, record=record,
+                  pool_out=pool_out, counts=counts, ctx=ctx)
 
 
-def opt_kcna(X, cand, k, L, M, alpha_deg, cand_d2=None, ctx=None):
+def opt_kcna(X, cand, k, L, M, alpha_deg, cand_d2=None, record=None, return_pool=False, counts=None,
+             ctx=None):
     """OptKCNA (Alg. 5): the alpha-PG of the candidate lists (prune with M and
     alpha, reverse re-prune, connect), then a search from every point on it.
-    Returns the new candidate lists (ids, d2), n x k."""
+    Returns the new candidate lists (ids, d2), n x k, and with return_pool the
+    search pools too (the P2K record of the next round)."""
     g = prune(X, cand, M, alpha_deg=alpha_deg, cand_d2=cand_d2, ctx=ctx)
-    return search_self(X, g["ids"], g["deg"], k, L, ctx=ctx)
+    r = search_self(X, g["ids"], g["deg"], k, L, record=record, pool_out=return_pool, counts=counts,
+                    ctx=ctx)
+    return r if return_pool else (r[0], r[1])
 
 
 def quality_sample_size(n, eps, l=1):
@@ -326,22 +359,31 @@ def quality_examination(X, cand, k, sample, ctx=None):
 
 
 def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0, delta=0.001,
-             target=None, sample=None, ctx=None, **knn_kw):
+             target=None, sample=None, p2k=False, counts=None, ctx=None, **knn_kw):
     """IterNSG (Alg. 6): NN-Descent lists, rounds of OptKCNA with angle
     alpha_deg, then the refinement of Alg. 2 with RNG pruning.  Without
     `target` it runs `iterations` rounds; with `target` the quality
     examination on the nodes `sample` runs before each round and the rounds
     stop once the estimate reaches it (or after `iterations`).  Returns the
     graph dict of prune() plus the final candidate lists ("cand", "cand_d2"),
-    the rounds run, the estimates and the kNN statistics."""
+    the rounds run, the estimates and the kNN statistics.  With p2k, every
+    round's self-search reuses the distances recorded in the previous round's
+    pools (Section 5.4, P2K); the graph is the same.  counts (optional int64
+    device tensor of 2) is added the distances the searches computed and
+    reused."""
     cand, cd2, st = knn_build(X, K, S=S, max_iters=max_iters, seed=seed, delta=delta, ctx=ctx, **knn_kw)
-    rounds, quality = 0, []
+    rounds, quality, record = 0, [], None
     while rounds < iterations:
         if target is not None:
             quality.append(quality_examination(X, cand, k, sample, ctx=ctx))
             if quality[-1] >= target:
                 break
-        cand, cd2 = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, ctx=ctx)
+        if p2k:
+            cand, cd2, pi, pd = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, record=record,
+                                         return_pool=True, counts=counts, ctx=ctx)
+            record = (pi, pd)
+        else:
+            cand, cd2 = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, counts=counts, ctx=ctx)
         rounds += 1
     g = prune(X, cand, R, cand_d2=cd2, ctx=ctx)
     g["cand"], g["cand_d2"], g["knn_stats"] = cand, cd2, st
@@ -390,7 +432,7 @@ def _complete_layer(Xi, M, ctx):
 
 
 def opt_hnsw(X, U, k0, ef, M, alpha_deg, iterations=2, S=None, max_iters=12, seed=0, delta=0.001,
-             ctx=None, **knn_kw):
+             p2k=False, ctx=None, **knn_kw):
     """OptHNSW (Alg. 7): layers from the draws U, then every layer D_i with
     more than M nodes built by IterNSG(D_i, k0, ef, ef, M, alpha) on its own
     rows, smaller layers as complete graphs; the entry point is the smallest
@@ -416,7 +458,7 @@ def opt_hnsw(X, U, k0, ef, M, alpha_deg, iterations=2, S=None, max_iters=12, see
             K = min(k0, m - 1)
             Si = min((K + 1) // 2 if S is None else S, K)
             g = iter_nsg(Xi, K, M, ef - 1, ef, alpha_deg, iterations, S=Si, max_iters=max_iters,
-                         seed=seed, stop_updates=int(delta * m * K), ctx=ctx, **knn_kw)
+                         seed=seed, stop_updates=int(delta * m * K), p2k=p2k, ctx=ctx, **knn_kw)
             ids, deg = g["ids"], g["deg"]
         pos = torch.full((n,), -1, dtype=torch.int32, device=X.device)
         pos[nodes.long()] = torch.arange(m, dtype=torch.int32, device=X.device)

@@ -441,6 +441,39 @@ def test_search_self_bit_exact(pg, oracle, datagen):
     assert np.array_equal(host(d2), rd2.astype(np.float32))
 
 
+def test_search_record_reuses_distances_without_changing_results(pg, oracle, datagen):
+    # P2K: pools of a search on one graph serve as the record of a search on
+    # another graph; the results equal the search without a record (and the
+    # oracle's), and part of the distances come from the record
+    X, _ = datagen.sift_like(2500, 0, d=32, n_clusters=15, sigma=10.0, seed=42)
+    cand, _ = oracle.exact_knn(X, X, 20, exclude=np.arange(2500))
+    g1 = oracle.refine(X, cand, 12, alpha_deg=65.0)
+    ids1, _ = oracle.search_self(X, g1["ids"], g1["deg"], 16, 40)[:2]
+    g2 = oracle.refine(X, ids1, 12, alpha_deg=65.0)
+    Xd = dev(X)
+    _, _, pi, pd = pg.search_self(Xd, dev(g1["ids"]), dev(g1["deg"]), 16, 40, pool_out=True)
+    # a record with padding, a repeat and an out-of-range id must not matter
+    pi[:, -1] = -1
+    pi[:, -2] = pi[:, 0]
+    pd[:, -2] = pd[:, 0]
+    pi[::7, -3] = 2500
+    c0 = torch.zeros(2, dtype=torch.int64, device="cuda")
+    c1 = torch.zeros(2, dtype=torch.int64, device="cuda")
+    a = pg.search_self(Xd, dev(g2["ids"]), dev(g2["deg"]), 16, 40, pool_out=True, counts=c0)
+    b = pg.search_self(Xd, dev(g2["ids"]), dev(g2["deg"]), 16, 40, record=(pi, pd), pool_out=True,
+                       counts=c1)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    rid, rd2, _ = oracle.search_self(X, g2["ids"], g2["deg"], 16, 40)
+    assert np.array_equal(host(b[0]), rid)
+    assert np.array_equal(host(b[1]), rd2.astype(np.float32))
+    c0, c1 = host(c0), host(c1)
+    log("computed without record", c0, "with record", c1)
+    assert c0[1] == 0 and c1[1] > 0
+    assert c1[0] + c1[1] == c0[0]
+    assert c1[0] < c0[0]
+
+
 @pytest.mark.parametrize("nn,d,nc,sig,K,S,k,L,R,alpha", [
     (3000, 32, 20, 12.0, 16, 8, 16, 32, 16, 65.0),
     (2000, 64, 10, 20.0, 24, 12, 24, 40, 20, 62.0),
@@ -450,6 +483,13 @@ def test_iter_nsg_bit_exact(pg, oracle, datagen, nn, d, nc, sig, K, S, k, L, R, 
     X, _ = datagen.sift_like(nn, 0, d=d, n_clusters=nc, sigma=sig, seed=41)
     stop = int(0.001 * nn * K)
     g = pg.iter_nsg(dev(X), K, R, k, L, alpha, 2, S=S, max_iters=8, seed=3, stop_updates=stop)
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    gp = pg.iter_nsg(dev(X), K, R, k, L, alpha, 2, S=S, max_iters=8, seed=3, stop_updates=stop, p2k=True,
+                     counts=cnt)
+    for key in ("ids", "d2", "deg", "ep", "roots", "cand", "cand_d2"):
+        assert torch.equal(g[key], gp[key]), key  # P2K leaves the graph unchanged
+    log("P2K computed / reused", host(cnt))
+    assert host(cnt)[1] > 0
     r = oracle.iter_nsg(X, K, S, 8, 3, stop, k, L, R, alpha, 2)
     assert np.array_equal(host(g["cand"]), r["cand"])
     assert np.array_equal(host(g["ids"]), r["ids"])
