@@ -321,10 +321,13 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         log(f"[bench]   updates {st['updates']}\n[bench]   pairs {st['pairs']}\n"
             f"[bench]   proposals {st['proposals']}")
     entries = torch.cat([g["ep"], g["roots"]]).contiguous()
+    # rows for the search: an FP16 copy when it holds X exactly (same results)
+    h16, exact16 = pg.half_rows(Xd, ctx=ctx)
+    x16 = h16 if exact16 else None
     chosen, rec = None, 0.0
     ladder = []
     for L in L_LADDER:
-        f, _ = pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, L, ctx=ctx)
+        f, _ = pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, L, x16=x16, ctx=ctx)
         r = recall(f.cpu().numpy(), gt)
         ladder.append((L, r))
         log(f"[bench] L={L} recall@10={r:.4f}")
@@ -344,7 +347,8 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
     for _ in range(args.steps):
         ids, st, g = build()
         entries = torch.cat([g["ep"], g["roots"]]).contiguous()
-        pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, chosen, ctx=ctx)
+        h16, exact16 = pg.half_rows(Xd, ctx=ctx)
+        pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, chosen, x16=h16 if exact16 else None, ctx=ctx)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt_ = {name: ctx.kernel_time(name) for name in
@@ -358,14 +362,14 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record()
-        pg.search(Xd, g["ids"], g["deg"], Qd[i:i + 1], entries, 10, chosen, ctx=ctx)
+        pg.search(Xd, g["ids"], g["deg"], Qd[i:i + 1], entries, 10, chosen, x16=x16, ctx=ctx)
         s1.record()
         s1.synchronize()
         lat.append(s0.elapsed_time(s1))
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
     s0.record()
-    pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, chosen, ctx=ctx)
+    pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, chosen, x16=x16, ctx=ctx)
     s1.record()
     s1.synchronize()
     qps = Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)
@@ -376,7 +380,7 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         "join_path": st["join_path"], "L": chosen,
         "recall@10": rec, "knn_recall_sample": knn_recall, "search_ladder": ladder,
         "nndescent_iters": st["iters"], "connect_roots": int(len(g["roots"])),
-        "qps_batch": qps,
+        "qps_batch": qps, "search_rows": "fp16 (exact copy)" if exact16 else "fp32",
         "query_latency_ms_batch1": {"p50": float(np.percentile(lat, 50)),
                                     "p99": float(np.percentile(lat, 99))},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_.items()},

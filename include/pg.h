@@ -257,6 +257,12 @@ typedef struct {
     unsigned long long *counts; /* optional, device, 2 values added to:
                                    distances computed, distances taken from
                                    the record */
+    const uint16_t *x16;        /* optional, device: an FP16 copy of X made by
+                                   pg_half_rows that reported every element
+                                   exact; rows are then gathered from it (half
+                                   the bytes) and widened, so every distance and
+                                   result is unchanged.  A copy that is not exact
+                                   changes the distances: do not pass it. */
 } pg_search_params;
 
 /* KANNSearch of Alg. 1 for every query row, starting from the entering
@@ -274,6 +280,14 @@ pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t l
                     const int32_t *g_ids, int32_t R, const int32_t *g_deg,
                     const float *Q, int64_t nq, int64_t ldq,
                     const pg_search_params *p, int32_t *out_ids, float *out_d2);
+
+/* FP16 copy of the rows of X for pg_search: X16 (device, n rows of
+ * (d + 7) / 8 * 8 halves, zero padded, 16-byte aligned) receives the rounded
+ * values; *exact (device int32) becomes 1 if every element converted exactly
+ * (integers up to 2048 in magnitude, for instance), else 0.  Only an exact
+ * copy may be passed to the search. */
+pg_status pg_half_rows(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx, uint16_t *X16,
+                       int32_t *exact);
 
 /* ------------------------------------------------------------------ */
 /* Global HNSW construction (Alg. 7): layer assignment                 */

@@ -78,6 +78,10 @@ __device__ __forceinline__ void seg_sort(uint64_t &k, int &p) {
 constexpr int ST_DIMS = 32;
 constexpr int ST_STRIDE = 36;
 constexpr size_t ST_BYTES = sizeof(float) * PG_WAVE * ST_STRIDE;
+// FP16 rows: 64 dimensions per slice, 72 halves per staged row (same bytes)
+constexpr int ST_DIMS16 = 64;
+constexpr int ST_STRIDE16 = 72;
+static_assert(sizeof(uint16_t) * ST_STRIDE16 == sizeof(float) * ST_STRIDE, "one tile serves both row types");
 
 // LDS bytes of one query's slice: query vector, pool keys, record table (RT
 // ids and distances), pool flags
@@ -103,7 +107,7 @@ __device__ __forceinline__ uint32_t record_slot(int32_t id, int bits) {
     return ((uint32_t)id * 0x9E3779B1u) >> (32 - bits);
 }
 
-template <int HW>
+template <int HW, bool H16>
 __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int64_t ldx, int d,
                                                int64_t n, const int32_t *__restrict__ g, int R,
                                                const int32_t *__restrict__ deg,
@@ -112,7 +116,8 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
                                                const int32_t *__restrict__ query_entry,
                                                const int32_t *__restrict__ exclude, int k, int L,
                                                int32_t *__restrict__ out_ids,
-                                               float *__restrict__ out_d2, SearchRecord rec) {
+                                               float *__restrict__ out_d2, SearchRecord rec,
+                                               const _Float16 *__restrict__ X16, int64_t ld16) {
     constexpr int QPW = PG_WAVE / HW;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -187,41 +192,83 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
         int32_t rid[PG_WAVE / 8];
 #pragma unroll
         for (int i = 0; i < PG_WAVE / 8; ++i) rid[i] = __shfl(gid, i * 8 + (lane >> 3), PG_WAVE);
-        const int part = (lane & 7) * 4;
-        float4 v[PG_WAVE / 8];
-        auto fetch = [&](int c) {
-            const int w = min(ST_DIMS, d - c);
-#pragma unroll
-            for (int i = 0; i < PG_WAVE / 8; ++i) {
-                v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (rid[i] >= 0 && part < w)
-                    v[i] = *reinterpret_cast<const float4 *>(X + (int64_t)rid[i] * ldx + c + part);
-            }
-        };
         float acc = 0.f;
-        fetch(0);
-        for (int c = 0; c < d; c += ST_DIMS) {
-            const int w = min(ST_DIMS, d - c);
+        if constexpr (H16) {
+            // an exact FP16 copy of the rows: 64-dimension slices, eight
+            // lanes per row each reading 16 bytes of one 128-byte line; the
+            // halves stay 16-bit in the tile and are widened when summed
+            const int part = (lane & 7) * 8;
+            uint4 v[PG_WAVE / 8];
+            auto fetch = [&](int c) {
+                const int w = min(ST_DIMS16, d - c);
 #pragma unroll
-            for (int i = 0; i < PG_WAVE / 8; ++i)
-                *reinterpret_cast<float4 *>(tile + (i * 8 + (lane >> 3)) * ST_STRIDE + part) = v[i];
-            // the next slice is in flight while this one is summed
-            if (c + ST_DIMS < d) fetch(c + ST_DIMS);
-            __builtin_amdgcn_wave_barrier();
-            for (int j = 0; j < w; j += 4) {
-                const float4 x = *reinterpret_cast<const float4 *>(tile + lane * ST_STRIDE + j);
-                const float4 y = *reinterpret_cast<const float4 *>(qv + c + j);
-                float t;
-                t = y.x - x.x;
-                acc = fmaf(t, t, acc);
-                t = y.y - x.y;
-                acc = fmaf(t, t, acc);
-                t = y.z - x.z;
-                acc = fmaf(t, t, acc);
-                t = y.w - x.w;
-                acc = fmaf(t, t, acc);
+                for (int i = 0; i < PG_WAVE / 8; ++i) {
+                    v[i] = make_uint4(0u, 0u, 0u, 0u);
+                    if (rid[i] >= 0 && part < w)
+                        v[i] = *reinterpret_cast<const uint4 *>(X16 + (int64_t)rid[i] * ld16 + c + part);
+                }
+            };
+            uint16_t *tile16 = reinterpret_cast<uint16_t *>(tile);
+            fetch(0);
+            for (int c = 0; c < d; c += ST_DIMS16) {
+                const int w = min(ST_DIMS16, d - c);
+#pragma unroll
+                for (int i = 0; i < PG_WAVE / 8; ++i)
+                    *reinterpret_cast<uint4 *>(tile16 + (i * 8 + (lane >> 3)) * ST_STRIDE16 + part) = v[i];
+                if (c + ST_DIMS16 < d) fetch(c + ST_DIMS16);
+                __builtin_amdgcn_wave_barrier();
+                for (int j = 0; j < w; j += 8) {
+                    const uint4 hx = *reinterpret_cast<const uint4 *>(tile16 + lane * ST_STRIDE16 + j);
+                    const float4 y0 = *reinterpret_cast<const float4 *>(qv + c + j);
+                    const float4 y1 = *reinterpret_cast<const float4 *>(qv + c + j + 4);
+                    const uint32_t hw[4] = {hx.x, hx.y, hx.z, hx.w};
+                    const float yy[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+                    const int ne = min(8, w - j);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const uint16_t bits = (uint16_t)(e & 1 ? hw[e >> 1] >> 16 : hw[e >> 1] & 0xffff);
+                        const float t = yy[e] - (float)__builtin_bit_cast(_Float16, bits);
+                        if (e < ne) acc = fmaf(t, t, acc);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
             }
-            __builtin_amdgcn_wave_barrier();
+        } else {
+            const int part = (lane & 7) * 4;
+            float4 v[PG_WAVE / 8];
+            auto fetch = [&](int c) {
+                const int w = min(ST_DIMS, d - c);
+#pragma unroll
+                for (int i = 0; i < PG_WAVE / 8; ++i) {
+                    v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (rid[i] >= 0 && part < w)
+                        v[i] = *reinterpret_cast<const float4 *>(X + (int64_t)rid[i] * ldx + c + part);
+                }
+            };
+            fetch(0);
+            for (int c = 0; c < d; c += ST_DIMS) {
+                const int w = min(ST_DIMS, d - c);
+#pragma unroll
+                for (int i = 0; i < PG_WAVE / 8; ++i)
+                    *reinterpret_cast<float4 *>(tile + (i * 8 + (lane >> 3)) * ST_STRIDE + part) = v[i];
+                // the next slice is in flight while this one is summed
+                if (c + ST_DIMS < d) fetch(c + ST_DIMS);
+                __builtin_amdgcn_wave_barrier();
+                for (int j = 0; j < w; j += 4) {
+                    const float4 x = *reinterpret_cast<const float4 *>(tile + lane * ST_STRIDE + j);
+                    const float4 y = *reinterpret_cast<const float4 *>(qv + c + j);
+                    float t;
+                    t = y.x - x.x;
+                    acc = fmaf(t, t, acc);
+                    t = y.y - x.y;
+                    acc = fmaf(t, t, acc);
+                    t = y.z - x.z;
+                    acc = fmaf(t, t, acc);
+                    t = y.w - x.w;
+                    acc = fmaf(t, t, acc);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         uint64_t key = id >= 0 ? pack_key(found ? dfound : acc, id) : KEY_INF;
         int at = 0;
@@ -409,15 +456,71 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
     const int RT = rec.bits ? 1 << rec.bits : 0;
     const size_t slice = search_slice_bytes(d, p->L, RT);
     const bool pair = R <= 32 && 2 * slice + ST_BYTES <= 65536;
+    if (p->x16 && ((uintptr_t)p->x16 & 15)) {
+        set_error("pg_search: x16 must be 16-byte aligned");
+        return PG_EINVAL;
+    }
+    const _Float16 *x16 = reinterpret_cast<const _Float16 *>(p->x16);
+    const int64_t ld16 = ((int64_t)d + 7) & ~(int64_t)7;
     TimedLaunch tl(ctx, K_SEARCH, -1.0);
-    if (pair)
-        hipLaunchKernelGGL(k_search<32>, dim3((unsigned)((nq + 1) / 2)), dim3(64), 2 * slice + ST_BYTES, ctx->stream, X,
-                           ldx, d, n, g_ids, R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry,
-                           p->exclude, p->k, p->L, out_ids, out_d2, rec);
+    const dim3 g2((unsigned)((nq + 1) / 2)), g1((unsigned)nq);
+    const size_t l2 = 2 * slice + ST_BYTES, l1 = slice + ST_BYTES;
+#define PG_SEARCH_ARGS                                                                                          \
+    X, ldx, d, n, g_ids, R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry, p->exclude, p->k, p->L, \
+        out_ids, out_d2, rec, x16, ld16
+    if (pair && x16)
+        hipLaunchKernelGGL((k_search<32, true>), g2, dim3(64), l2, ctx->stream, PG_SEARCH_ARGS);
+    else if (pair)
+        hipLaunchKernelGGL((k_search<32, false>), g2, dim3(64), l2, ctx->stream, PG_SEARCH_ARGS);
+    else if (x16)
+        hipLaunchKernelGGL((k_search<64, true>), g1, dim3(64), l1, ctx->stream, PG_SEARCH_ARGS);
     else
-        hipLaunchKernelGGL(k_search<64>, dim3((unsigned)nq), dim3(64), slice + ST_BYTES, ctx->stream, X, ldx, d, n, g_ids,
-                           R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry, p->exclude, p->k,
-                           p->L, out_ids, out_d2, rec);
+        hipLaunchKernelGGL((k_search<64, false>), g1, dim3(64), l1, ctx->stream, PG_SEARCH_ARGS);
+#undef PG_SEARCH_ARGS
+    PG_HIP(hipGetLastError());
+    return PG_OK;
+}
+
+namespace pgi {
+
+// FP16 copy of the rows of X (row stride d rounded up to 8, zero padded);
+// *exact becomes 0 if any element does not survive the round trip
+__global__ __launch_bounds__(256) void k_half_rows(const float *__restrict__ X, int64_t n, int d, int64_t ldx,
+                                                   _Float16 *__restrict__ X16, int64_t ld16,
+                                                   int32_t *__restrict__ exact) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (t < n * ld16) {
+        const int64_t r = t / ld16;
+        const int c = (int)(t % ld16);
+        float x = 0.f;
+        if (c < d) x = X[r * ldx + c];
+        const _Float16 h = (_Float16)x;
+        X16[t] = h;
+        bad = (float)h != x;
+    }
+    if (__ballot(bad) != 0 && lane_id() == 0) atomicAnd(exact, 0);
+}
+
+__global__ void k_set_flag(int32_t *__restrict__ p) { *p = 1; }
+
+}  // namespace pgi
+
+extern "C" pg_status pg_half_rows(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                  uint16_t *X16, int32_t *exact) {
+    if (!ctx || !X || !X16 || !exact) {
+        set_error("pg_half_rows: NULL argument");
+        return PG_EINVAL;
+    }
+    if (n < 1 || d < 1 || ldx < d) {
+        set_error("pg_half_rows: bad sizes n=%lld d=%d ldx=%lld", (long long)n, d, (long long)ldx);
+        return PG_EINVAL;
+    }
+    const int64_t ld16 = ((int64_t)d + 7) & ~(int64_t)7;
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, ctx->stream, exact);
+    const int64_t total = n * ld16;
+    hipLaunchKernelGGL(k_half_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, ctx->stream, X, n, d, ldx,
+                       reinterpret_cast<_Float16 *>(X16), ld16, exact);
     PG_HIP(hipGetLastError());
     return PG_OK;
 }

@@ -51,12 +51,13 @@ class SearchParams(ctypes.Structure):
     _fields_ = [("k", c_int32), ("L", c_int32), ("n_entry", c_int32), ("entry_ids", c_void_p),
                 ("query_entry", c_void_p), ("exclude", c_void_p), ("record_ids", c_void_p),
                 ("record_d2", c_void_p), ("record_L", c_int32), ("pool_ids", c_void_p),
-                ("pool_d2", c_void_p), ("counts", c_void_p)]
+                ("pool_d2", c_void_p), ("counts", c_void_p), ("x16", c_void_p)]
 
 
 EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
            "pg_ctx_kernel_time", "pg_ctx_reset_timing", "pg_knn_build_workspace", "pg_knn_build",
-           "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search", "pg_hnsw_levels"]
+           "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search", "pg_hnsw_levels",
+           "pg_half_rows"]
 
 _lib = None
 
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     lib.pg_search.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, P, P, c_int64, c_int64,
                               POINTER(SearchParams), P, P]
     lib.pg_hnsw_levels.argtypes = [P, P, c_int64, c_int32, P, P]
+    lib.pg_half_rows.argtypes = [P, P, c_int64, c_int32, c_int64, P, P]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("pg_version", "pg_last_error"):
@@ -255,8 +257,22 @@ def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair
     return {"ids": g_ids, "d2": g_d2, "deg": g_deg, "ep": ep, "roots": roots[:nroots.value]}
 
 
+def half_rows(X, ctx=None):
+    """FP16 copy of the rows of X for search(): returns (X16, exact).  Pass
+    X16 to search() only when exact is True."""
+    lib = load_library()
+    X = _dev_f32(X, "X")
+    n, d = X.shape
+    ld16 = (d + 7) // 8 * 8
+    x16 = torch.empty((n, ld16), dtype=torch.float16, device=X.device)
+    flag = torch.empty(1, dtype=torch.int32, device=X.device)
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_half_rows(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(x16), _ptr(flag)), "pg_half_rows")
+    return x16, bool(flag.item())
+
+
 def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, record=None,
-           pool_out=False, counts=None, ctx=None):
+           pool_out=False, counts=None, x16=None, ctx=None):
     """Alg. 1 beam search for every row of Q: returns (ids, d2), plus the final
     pools (pool_ids, pool_d2), nq x L, when pool_out is set.
 
@@ -266,7 +282,9 @@ def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, re
     (ids, d2), nq x r): distances of the same query rows recorded by an
     earlier search (its pools), reused instead of gathering rows (P2K,
     Section 5.4); the results do not change.  counts (optional int64 device
-    tensor of 2) is added the distances computed and the ones reused."""
+    tensor of 2) is added the distances computed and the ones reused.  x16:
+    an exact FP16 copy of X from half_rows() (rows gathered at half the
+    bytes, results unchanged)."""
     lib = load_library()
     X, Q = _dev_f32(X, "X"), _dev_f32(Q, "Q")
     g_ids, g_deg = _dev_i32(g_ids, "g_ids"), _dev_i32(g_deg, "g_deg")
@@ -289,6 +307,9 @@ def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, re
             raise ValueError("record must be two nq x r tensors")
     if counts is not None and (counts.dtype != torch.int64 or counts.numel() < 2 or not counts.is_cuda):
         raise ValueError("counts must be a CUDA int64 tensor of 2")
+    if x16 is not None and (x16.dtype != torch.float16 or tuple(x16.shape) != (n, (d + 7) // 8 * 8)
+                            or not x16.is_contiguous() or x16.device != X.device):
+        raise ValueError("x16 must be the contiguous (n, d rounded up to 8) float16 copy from half_rows()")
     ids = torch.empty((nq, k), dtype=torch.int32, device=X.device)
     d2 = torch.empty((nq, k), dtype=torch.float32, device=X.device)
     pool_ids = pool_d2 = None
@@ -304,7 +325,8 @@ def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, re
                      record_L=rec_ids.shape[1] if rec_ids is not None else 0,
                      pool_ids=pool_ids.data_ptr() if pool_out else None,
                      pool_d2=pool_d2.data_ptr() if pool_out else None,
-                     counts=counts.data_ptr() if counts is not None else None)
+                     counts=counts.data_ptr() if counts is not None else None,
+                     x16=_ptr(x16) if x16 is not None else None)
     ctx = ctx or context(X.device.index)
     _check(lib.pg_search(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(g_ids), g_ids.shape[1],
                          _ptr(g_deg), _ptr(Q), nq, Q.stride(0), ctypes.byref(p), _ptr(ids), _ptr(d2)),
@@ -314,25 +336,25 @@ def search(X, g_ids, g_deg, Q, entries, k, L, query_entry=None, exclude=None, re
     return ids, d2
 
 
-def search_self(X, g_ids, g_deg, k, L, record=None, pool_out=False, counts=None, ctx=None):
+def search_self(X, g_ids, g_deg, k, L, record=None, pool_out=False, counts=None, x16=None, ctx=None):
     """Search phase of OptKCNA (Alg. 5): KANNSearch(G, u, k, L, u) for every
     point u, u not being its own candidate.  Returns (ids, d2), n x k (plus
     the pools with pool_out; record and counts as in search())."""
     n = X.shape[0]
     selfid = torch.arange(n, dtype=torch.int32, device=X.device)
     return search(X, g_ids, g_deg, X, None, k, L, query_entry=selfid, exclude=selfid, record=record,
-                  pool_out=pool_out, counts=counts, ctx=ctx)
+                  pool_out=pool_out, counts=counts, x16=x16, ctx=ctx)
 
 
 def opt_kcna(X, cand, k, L, M, alpha_deg, cand_d2=None, record=None, return_pool=False, counts=None,
-             ctx=None):
+             x16=None, ctx=None):
     """OptKCNA (Alg. 5): the alpha-PG of the candidate lists (prune with M and
     alpha, reverse re-prune, connect), then a search from every point on it.
     Returns the new candidate lists (ids, d2), n x k, and with return_pool the
     search pools too (the P2K record of the next round)."""
     g = prune(X, cand, M, alpha_deg=alpha_deg, cand_d2=cand_d2, ctx=ctx)
     r = search_self(X, g["ids"], g["deg"], k, L, record=record, pool_out=return_pool, counts=counts,
-                    ctx=ctx)
+                    x16=x16, ctx=ctx)
     return r if return_pool else (r[0], r[1])
 
 
@@ -359,7 +381,7 @@ def quality_examination(X, cand, k, sample, ctx=None):
 
 
 def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0, delta=0.001,
-             target=None, sample=None, p2k=False, counts=None, ctx=None, **knn_kw):
+             target=None, sample=None, p2k=False, counts=None, half=True, ctx=None, **knn_kw):
     """IterNSG (Alg. 6): NN-Descent lists, rounds of OptKCNA with angle
     alpha_deg, then the refinement of Alg. 2 with RNG pruning.  Without
     `target` it runs `iterations` rounds; with `target` the quality
@@ -370,9 +392,14 @@ def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0,
     round's self-search reuses the distances recorded in the previous round's
     pools (Section 5.4, P2K); the graph is the same.  counts (optional int64
     device tensor of 2) is added the distances the searches computed and
-    reused."""
+    reused.  With half (the default), the searches gather rows from an FP16
+    copy of X whenever that copy is exact (same results)."""
     cand, cd2, st = knn_build(X, K, S=S, max_iters=max_iters, seed=seed, delta=delta, ctx=ctx, **knn_kw)
     rounds, quality, record = 0, [], None
+    x16 = None
+    if half and iterations > 0:
+        h, exact = half_rows(X, ctx=ctx)
+        x16 = h if exact else None
     while rounds < iterations:
         if target is not None:
             quality.append(quality_examination(X, cand, k, sample, ctx=ctx))
@@ -380,10 +407,10 @@ def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0,
                 break
         if p2k:
             cand, cd2, pi, pd = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, record=record,
-                                         return_pool=True, counts=counts, ctx=ctx)
+                                         return_pool=True, counts=counts, x16=x16, ctx=ctx)
             record = (pi, pd)
         else:
-            cand, cd2 = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, counts=counts, ctx=ctx)
+            cand, cd2 = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, counts=counts, x16=x16, ctx=ctx)
         rounds += 1
     g = prune(X, cand, R, cand_d2=cd2, ctx=ctx)
     g["cand"], g["cand_d2"], g["knn_stats"] = cand, cd2, st

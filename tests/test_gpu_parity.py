@@ -379,6 +379,37 @@ def test_search_wide_rows_bit_exact(pg, oracle, datagen, R, nq):
         assert np.array_equal(host(d2), rd2.astype(np.float32)), L
 
 
+def test_search_fp16_rows_equal_fp32_rows(pg, oracle, datagen):
+    # an exact FP16 copy of integer data: identical results, pools and
+    # counts; float data is reported inexact
+    X, Q = datagen.sift_like(4000, 301, d=36, n_clusters=10, sigma=10.0, seed=9)
+    cand = _exact_lists(oracle, X, 24)
+    r = oracle.refine(X, cand, 12)
+    entries = np.concatenate([[r["ep"]], r["roots"]]).astype(np.int32)
+    x16, exact = pg.half_rows(dev(X))
+    assert exact and tuple(x16.shape) == (4000, 40)
+    assert torch.equal(x16[:, :36].float(), dev(X)) and not x16[:, 36:].any()
+    for L in (10, 64):
+        a = pg.search(dev(X), dev(r["ids"]), dev(r["deg"]), dev(Q), dev(entries), 10, L, pool_out=True)
+        b = pg.search(dev(X), dev(r["ids"]), dev(r["deg"]), dev(Q), dev(entries), 10, L, pool_out=True, x16=x16)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+        rid, _, _ = oracle.search(X, r["ids"], r["deg"], Q, entries, 10, L)
+        assert np.array_equal(host(b[0]), rid)
+    # self-search on a wide graph (one query per wave) with FP16 rows
+    wide = _exact_lists(oracle, X, 48)
+    a = pg.search_self(dev(X), dev(wide), dev(np.full(4000, 48, np.int32)), 8, 20)
+    b = pg.search_self(dev(X), dev(wide), dev(np.full(4000, 48, np.int32)), 8, 20, x16=x16)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    Xf, _ = datagen.gist_like(500, 0, d=40, seed=3)
+    _, exact = pg.half_rows(dev(Xf))
+    assert not exact
+    Xb = X.copy()
+    Xb[5, 3] = 2049.0  # an integer FP16 cannot hold
+    _, exact = pg.half_rows(dev(Xb))
+    assert not exact
+
+
 def test_search_edge_cases(pg, oracle):
     X = np.arange(12, dtype=np.float32).repeat(4).reshape(12, 4)
     g = np.full((12, 2), -1, np.int32)
