@@ -30,6 +30,10 @@ WORKLOADS = {
     # SIFT-shaped: 1M x 128, 100 Gaussian clusters (sigma 20) rounded to [0,255]
     "sift1m": dict(n=1_000_000, nq=10_000, d=128, K=64, R=32, S=32, iters=12, seed=2,
                    gen="sift_like", desc="sift-like 1Mx128 mixture-of-100, K=64 R=32 FP32"),
+    # GIST-shaped precision mode: 1M x 960 float data (Gamma(2, 0.05) + 50 offsets);
+    # the FP16 path is the mixed one (16-bit tiles prefilter, FP32 recheck)
+    "gist1m": dict(n=1_000_000, nq=1_000, d=960, K=64, R=32, S=32, iters=12, seed=3,
+                   gen="gist_like", desc="gist-like 1Mx960 Gamma(2,0.05)+50 offsets, K=64 R=32 FP32 storage"),
     # tiny: 10k x 128 integers
     "tiny": dict(n=10_000, nq=100, d=128, K=32, R=32, S=16, iters=12, seed=0,
                  gen="uniform_int", desc="uniform-int 10kx128, K=32 R=32 FP32"),
@@ -59,7 +63,7 @@ def measured_traffic(path_name):
     return float(m.group(1)) if m else None
 
 
-def roofline(join_path, work, launches, total_ms, name):
+def roofline(join_path, work, launches, total_ms, name, workload):
     """Roofline entry of the join kernel: flops or bytes per launch over its mean duration."""
     avg_ms = total_ms / max(launches, 1)
     per_launch = work / max(launches, 1)
@@ -71,7 +75,9 @@ def roofline(join_path, work, launches, total_ms, name):
         bound, unit, peak, scale = "hbm", "GB/s", PEAK_HBM_GBS, 1e9
     achieved = per_launch / (avg_ms / 1000.0) / scale if launches else 0.0
     return {"kernel": "join", "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": measured_traffic(name),
+            "frac": achieved / peak,
+            # counters were taken on the sift-like workload only
+            "traffic": measured_traffic(name) if workload == "sift1m" else None,
             "work_per_launch": per_launch,
             "work_unit": "flops" if scale == 1e12 else "bytes",
             "avg_launch_ms": avg_ms, "launches": launches}
@@ -81,6 +87,8 @@ def gen_data(w):
     from paper_2410_01231_amd import datagen
     if w["gen"] == "sift_like":
         return datagen.sift_like(w["n"], w["nq"], d=w["d"], seed=w["seed"])
+    if w["gen"] == "gist_like":
+        return datagen.gist_like(w["n"], w["nq"], d=w["d"], seed=w["seed"])
     X = datagen.uniform_int(w["n"], w["d"], seed=w["seed"])
     Q = datagen.uniform_int(w["nq"], w["d"], seed=w["seed"] + 1)
     return X, Q
@@ -320,7 +328,7 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
             f"join {st['join_path']}, roots {len(g['roots'])}, retries {st['retries']}, "
             f"spilled {st['spilled']}")
         log(f"[bench]   updates {st['updates']}\n[bench]   pairs {st['pairs']}\n"
-            f"[bench]   proposals {st['proposals']}")
+            f"[bench]   proposals {st['proposals']}\n[bench]   rechecked {st['rechecked']}")
     entries = torch.cat([g["ep"], g["roots"]]).contiguous()
     # rows for the search: an FP16 copy when it holds X exactly (same results)
     h16, exact16 = pg.half_rows(Xd, ctx=ctx)
@@ -381,11 +389,12 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         "join_path": st["join_path"], "L": chosen,
         "recall@10": rec, "knn_recall_sample": knn_recall, "search_ladder": ladder,
         "nndescent_iters": st["iters"], "connect_roots": int(len(g["roots"])),
+        "rechecked_fraction": sum(st["rechecked"]) / max(1, sum(st["pairs"])),
         "qps_batch": qps, "search_rows": "fp16 (exact copy)" if exact16 else "fp32",
         "query_latency_ms_batch1": {"p50": float(np.percentile(lat, 50)),
                                     "p99": float(np.percentile(lat, 99))},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_.items()},
-        "roofline": roofline(st["join_path"], join_work, join_n, join_ms, path["name"]),
+        "roofline": roofline(st["join_path"], join_work, join_n, join_ms, path["name"], args.workload),
     }
 
 

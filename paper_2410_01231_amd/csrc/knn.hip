@@ -906,6 +906,16 @@ __device__ __forceinline__ mf_f32x16 gram_tile(const float *__restrict__ X, int6
 }
 
 constexpr int MW = 4;  // sources (waves) per workgroup in the MFMA join
+// mixed path: recheck list (a 32 x 32 tile has at most 1024 pairs) and the
+// rechecked distances (16 registers x 64 lanes)
+constexpr int JR_LIST = 1024;
+
+// LDS bytes of one join wave: per member kth, sbase, ids, cnt, base, mk, nrm,
+// thr; the mixed path adds the recheck list and distances
+__host__ __device__ inline size_t join_mfma_wave_bytes(int mps, bool mix) {
+    return (size_t)mps * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4) +
+           (mix ? (size_t)JR_LIST * sizeof(uint16_t) + (size_t)16 * PG_WAVE * sizeof(float) : 0);
+}
 
 // MFMA local join for data on which the norm expansion is exact (see k_prep):
 // one wave per source, 32 x 32 Gram tiles of (new members) x (all members),
@@ -933,7 +943,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     if (u < 0) return;
     unsigned long long *cslot = stripe_of(counters);
     const int64_t seg_begin = (int64_t)(blockIdx.x % NSTRIPE) * seg, seg_end = seg_begin + seg;
-    unsigned char *region = smem + (size_t)wv * MPS * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4);
+    unsigned char *region = smem + (size_t)wv * join_mfma_wave_bytes(MPS, MIX);
     uint64_t *kth = reinterpret_cast<uint64_t *>(region);
     int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
     int32_t *ids = reinterpret_cast<int32_t *>(sbase + MPS);
@@ -942,6 +952,9 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     int32_t *mk = base + MPS;
     float *nrm = reinterpret_cast<float *>(mk + MPS);
     float *thr = nrm + MPS;  // d2 of the member's cut when it takes proposals, else -1
+    // mixed: the tile's pairs to recheck (q << 6 | lane) and their direct-form distances
+    uint16_t *rlist = reinterpret_cast<uint16_t *>(thr + MPS);
+    float *rdx = reinterpret_cast<float *>(rlist + JR_LIST);
 
     const int nn = jn_c[u], no = jo_c[u];
     const int m = nn + no;
@@ -978,20 +991,66 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
             const float nc = nrm[cm < mp ? cm : 0];
             const float thc = thr[cm < mp ? cm : 0];
             float dx[MIX ? 16 : 1];  // mixed: direct-form distances of the rechecked pairs
+            uint32_t rmask = 0;      // mixed: registers whose pair is rechecked
+            if constexpr (MIX) {
+                // Pairs whose 16-bit estimate lies within the rigorous bound of
+                // an end's cut are rechecked in the FP32 direct form.  They are
+                // gathered from the whole wave and spread one per lane, so the
+                // long chains run in parallel rather than one register at a time.
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
+                    dx[q] = __int_as_float(0x7f800000);
+                    if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
+                    const float d2e = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                    const float cut = fmaxf(mk[r] ? key_d2(kth[r]) : -1.0f, mk[cm] ? key_d2(kth[cm]) : -1.0f);
+                    if (cut < 0.0f || !(d2e <= mixed_bound(mx, cut, nrm[r], nc, g[q]))) continue;
+                    rmask |= 1u << q;
+                }
+                const int nr = __popc(rmask);
+                int ro = nr;
+#pragma unroll
+                for (int o = 1; o < PG_WAVE; o <<= 1) {
+                    const int t = __shfl_up(ro, o, PG_WAVE);
+                    if (lane >= o) ro += t;
+                }
+                const int rtot = __shfl(ro, PG_WAVE - 1, PG_WAVE);
+                ro -= nr;
+                if (rtot > 0) {
+                    {
+                        uint32_t mm = rmask;
+                        int e = ro;
+                        while (mm) {
+                            const int q = __builtin_ctz(mm);
+                            mm &= mm - 1;
+                            rlist[e++] = (uint16_t)((q << 6) | lane);
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    for (int e = lane; e < rtot; e += PG_WAVE) {
+                        const int ent = rlist[e], q = ent >> 6, src = ent & 63;
+                        const int rr = 32 * rb + 8 * (q / 4) + 4 * (src >> 5) + (q % 4);
+                        const int cc = 32 * cb + (src & 31);
+                        rdx[src * 16 + q] = dist_chain(X + (int64_t)ids[rr] * ldx, X + (int64_t)ids[cc] * ldx, d);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        if ((rmask >> q) & 1u) dx[q] = rdx[lane * 16 + q];
+                    __builtin_amdgcn_wave_barrier();
+                    local_rechk += (unsigned long long)nr;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
-                if (MIX) dx[MIX ? q : 0] = __int_as_float(0x7f800000);
                 float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
                 // a key below an end's cut has d2 <= the cut's d2: most pairs stop here
                 if (!MIX && !(d2 <= thr[r]) && !(d2 <= thc)) continue;
                 if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
                 if (MIX) {
-                    const float cut = fmaxf(mk[r] ? key_d2(kth[r]) : -1.0f, mk[cm] ? key_d2(kth[cm]) : -1.0f);
-                    if (cut < 0.0f || !(d2 <= mixed_bound(mx, cut, nrm[r], nc, g[q]))) continue;
-                    d2 = dist_chain(X + (int64_t)ids[r] * ldx, X + (int64_t)ids[cm] * ldx, d);
-                    dx[MIX ? q : 0] = d2;
-                    ++local_rechk;
+                    if (!((rmask >> q) & 1u)) continue;  // not rechecked: outside the bound
+                    d2 = dx[MIX ? q : 0];
                 }
                 const uint64_t kw = pack_key(d2, ids[cm]), kv = pack_key(d2, ids[r]);
                 if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
@@ -1069,9 +1128,9 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     if (lane == 0 && local_rechk) atomicAdd(&cslot[C_RECHECK], local_rechk);
 }
 
-static size_t join_mfma_lds_bytes(int maxm) {
+static size_t join_mfma_lds_bytes(int maxm, bool mix) {
     const int mps = (maxm + 31) / 32 * 32;
-    return (size_t)MW * mps * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4);
+    return (size_t)MW * join_mfma_wave_bytes(mps, mix);
 }
 
 // ---------------------------------------------------------------------------
@@ -1613,7 +1672,9 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         PG_HIP(hipGetLastError());
     }
     const int maxm = 3 * S + K;
-    const size_t lds = path == PG_JOIN_VALU ? join_lds_bytes(maxm) : join_mfma_lds_bytes(maxm);
+    const size_t lds = path == PG_JOIN_VALU ? join_lds_bytes(maxm)
+                                            : join_mfma_lds_bytes(maxm, path == PG_JOIN_MIXED_FP16 ||
+                                                                            path == PG_JOIN_MIXED_BF16);
     int iters = 0;
     int64_t prev_props = -1;
     for (int t = 1; t <= p->max_iters; ++t) {
