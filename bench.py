@@ -180,6 +180,15 @@ def main():
     results = {}
     for path in args.paths.split(","):
         results[path] = run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, PATHS[path])
+    # kNN-list entries and graph edges that differ from the FP32 build
+    ref = next((results[p] for p in ("fp32", "fp32-valu") if p in results), None)
+    for p in results:
+        if ref is not None and results[p] is not ref:
+            results[p]["knn_entries_differing_from_fp32"] = int((results[p]["_ids"] != ref["_ids"]).sum())
+            results[p]["graph_edges_differing_from_fp32"] = int((results[p]["_graph"] != ref["_graph"]).sum())
+    for p in results:
+        results[p].pop("_ids")
+        results[p].pop("_graph")
     # headline: the fastest path whose graph reached the recall target
     ok = [p for p in results if results[p]["recall@10"] >= 0.95] or list(results)
     best = max(ok, key=lambda p: results[p]["points_per_s"])
@@ -306,6 +315,9 @@ PATHS = {
     "fp16": {"name": "fp16", "precision": 1, "dtype": "f16-mfma/f32-acc"},
     "bf16": {"name": "bf16", "precision": 2, "dtype": "bf16-mfma/f32-acc"},
     "fp32-valu": {"name": "fp32-valu", "precision": 3, "dtype": "f32"},
+    # the precision mode as stated: FP16 tiles, FP32 recheck within a 1e-3
+    # relative margin of the cut only (not rigorous on float data)
+    "fp16-stated": {"name": "fp16-stated", "precision": 1, "dtype": "f16-mfma/f32-acc", "margin_rel": -1e-3},
 }
 
 
@@ -315,7 +327,7 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
 
     def build():
         ids, d2, st = pg.knn_build(Xd, K, S=S, max_iters=w["iters"], seed=1, delta=0.001,
-                                   precision=prec, ctx=ctx)
+                                   precision=prec, margin_rel=path.get("margin_rel", 0.0), ctx=ctx)
         g = pg.prune(Xd, ids, R, cand_d2=d2, ctx=ctx)
         return ids, st, g
 
@@ -384,6 +396,7 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
     qps = Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)
 
     return {
+        "_ids": ids, "_graph": g["ids"],
         "points_per_s": n * args.steps / elapsed,
         "ms_per_step": 1000.0 * elapsed / args.steps,
         "join_path": st["join_path"], "L": chosen,
