@@ -325,10 +325,13 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
     n, K, R, S = w["n"], w["K"], w["R"], w["S"]
     prec = path["precision"]
 
+    last = {}
+
     def build():
         ids, d2, st = pg.knn_build(Xd, K, S=S, max_iters=w["iters"], seed=1, delta=0.001,
                                    precision=prec, margin_rel=path.get("margin_rel", 0.0), ctx=ctx)
         g = pg.prune(Xd, ids, R, cand_d2=d2, ctx=ctx)
+        last["d2"] = d2
         return ids, st, g
 
     # ---- warm-up and recall calibration (untimed)
@@ -359,6 +362,13 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         chosen, rec = L_LADDER[-1], ladder[-1][1]
     kl = ids.cpu().numpy()[samp]
     knn_recall = float(np.mean([len(set(a) & set(b)) / K for a, b in zip(kl, kt)]))
+    # distance error of the stored list distances against FP64 (first 200 sampled nodes)
+    sub = samp[:200]
+    xs = Xd[torch.from_numpy(sub).cuda().long()].double()
+    kl_d2 = last["d2"].double()[torch.from_numpy(sub).cuda().long()]
+    nb = Xd[ids[torch.from_numpy(sub).cuda().long()].long()].double()
+    exact = ((xs[:, None, :] - nb) ** 2).sum(-1)
+    d2_err = float(((kl_d2 - exact).abs() / exact.clamp_min(1e-300)).max())
 
     # ---- timed steps
     ctx.set_timing(True)
@@ -401,6 +411,7 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         "ms_per_step": 1000.0 * elapsed / args.steps,
         "join_path": st["join_path"], "L": chosen,
         "recall@10": rec, "knn_recall_sample": knn_recall, "search_ladder": ladder,
+        "knn_d2_max_rel_error_vs_fp64": d2_err,
         "nndescent_iters": st["iters"], "connect_roots": int(len(g["roots"])),
         "rechecked_fraction": sum(st["rechecked"]) / max(1, sum(st["pairs"])),
         "qps_batch": qps, "search_rows": "fp16 (exact copy)" if exact16 else "fp32",
