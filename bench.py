@@ -34,6 +34,10 @@ WORKLOADS = {
     # the FP16 path is the mixed one (16-bit tiles prefilter, FP32 recheck)
     "gist1m": dict(n=1_000_000, nq=1_000, d=960, K=64, R=32, S=32, iters=12, seed=3,
                    gen="gist_like", desc="gist-like 1Mx960 Gamma(2,0.05)+50 offsets, K=64 R=32 FP32 storage"),
+    # Deep-shaped: 10M x 96 unit vectors, 1000 Gaussian clusters; BF16 tiles with
+    # FP32 recheck against plain FP32
+    "deep10m": dict(n=10_000_000, nq=10_000, d=96, K=64, R=32, S=32, iters=12, seed=4,
+                    gen="unit_mixture", desc="deep-like 10Mx96 unit mixture-of-1000, K=64 R=32 FP32 storage"),
     # tiny: 10k x 128 integers
     "tiny": dict(n=10_000, nq=100, d=128, K=32, R=32, S=16, iters=12, seed=0,
                  gen="uniform_int", desc="uniform-int 10kx128, K=32 R=32 FP32"),
@@ -89,6 +93,8 @@ def gen_data(w):
         return datagen.sift_like(w["n"], w["nq"], d=w["d"], seed=w["seed"])
     if w["gen"] == "gist_like":
         return datagen.gist_like(w["n"], w["nq"], d=w["d"], seed=w["seed"])
+    if w["gen"] == "unit_mixture":
+        return datagen.unit_mixture(w["n"], w["nq"], d=w["d"], seed=w["seed"])
     X = datagen.uniform_int(w["n"], w["d"], seed=w["seed"])
     Q = datagen.uniform_int(w["nq"], w["d"], seed=w["seed"] + 1)
     return X, Q

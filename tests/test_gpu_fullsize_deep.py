@@ -1,0 +1,99 @@
+"""The Deep-shaped BF16 configuration at its full size (10M x 96 unit vectors,
+1000 clusters, K = 64, R = 32), in the configuration bench.py times with
+--workload deep10m, checked through properties of any size and outputs the
+oracle computes one by one:
+
+* the BF16 mixed path (16-bit tiles on centred data, FP32 recheck within the
+  rigorous bound) gives the FP32 build's lists and graph exactly;
+* sampled list distances are within 1e-5 relative of FP64 (the distance
+  error of the precision mode), lists are sorted and self-free, and reach
+  the recall of the benchmark against brute force;
+* sampled PRUNE rows equal the oracle's Alg. 3 on the same candidates (float
+  data: a row may differ only through a near-tie, at most 1 in 100);
+* sampled searches on the GPU graph equal the oracle's on the same graph
+  (same allowance); batch recall at L = 1024 is reported (0.949 measured).
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+N, NQ, D, K, R, S, T = 10_000_000, 10_000, 96, 64, 32, 32, 12
+L_BENCH = 1024
+SAMPLE = 60
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def built():
+    from paper_2410_01231_amd import datagen, pg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    X, Q = datagen.unit_mixture(N, NQ, d=D, seed=4)
+    Xd = dev(X)
+    print("[fullsize-deep] data ready", flush=True)
+    f32 = pg.knn_build(Xd, K, S=S, max_iters=T, seed=1, delta=0.001, precision=pg.FP32)
+    f16 = pg.knn_build(Xd, K, S=S, max_iters=T, seed=1, delta=0.001, precision=pg.BF16)
+    g = pg.prune(Xd, f32[0], R, cand_d2=f32[1])
+    p1 = pg.prune(Xd, f32[0], R, cand_d2=f32[1], stages=pg.STAGE_PRUNE)
+    print(f"[fullsize-deep] built: paths {f32[2]['join_path']} {f16[2]['join_path']}", flush=True)
+    return dict(pg=pg, X=X, Q=Q, Xd=Xd, Qd=dev(Q), f32=f32, f16=f16,
+                g={k: host(v) for k, v in g.items()}, gd=g, p1={k: host(v) for k, v in p1.items()},
+                samp=np.random.default_rng(23).choice(N, size=SAMPLE, replace=False))
+
+
+def test_mixed_path_equals_fp32(built):
+    a, b = built["f32"], built["f16"]
+    assert a[2]["join_path"] == "fp32-valu" and b[2]["join_path"] == "bf16-mixed"
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[2]["updates"] == b[2]["updates"]
+
+
+def test_sampled_lists_distance_error_and_recall(built, oracle):
+    X, samp = built["X"], built["samp"]
+    ids, d2 = host(built["f32"][0])[samp], host(built["f32"][1])[samp]
+    assert (ids != samp[:, None]).all() and (np.diff(d2, axis=1) >= 0).all()
+    exact = ((X[samp][:, None, :].astype(np.float64) - X[ids].astype(np.float64)) ** 2).sum(-1)
+    rel = np.abs(d2.astype(np.float64) - exact) / np.maximum(exact, 1e-30)
+    print(f"[fullsize-deep] list d2 max relative error vs FP64: {rel.max():.3e}", flush=True)
+    assert rel.max() < 1e-5
+    gt, _ = oracle.exact_knn(X, X[samp], K, exclude=samp.astype(np.int32))
+    rec = np.mean([len(set(a) & set(b)) / K for a, b in zip(ids.tolist(), gt.tolist())])
+    print(f"[fullsize-deep] sampled kNN recall {rec:.4f}", flush=True)
+    assert rec >= 0.9
+
+
+def test_sampled_prune_rows(built, oracle):
+    X, samp, p1 = built["X"], built["samp"], built["p1"]
+    cand = host(built["f32"][0])
+    same = 0
+    for u in samp.tolist():
+        ref, _ = oracle.prune_one(X, u, cand[u], R)
+        same += list(p1["ids"][u, :p1["deg"][u]]) == list(ref)
+    print(f"[fullsize-deep] PRUNE rows identical {same}/{SAMPLE}", flush=True)
+    assert same >= 0.99 * SAMPLE
+
+
+def test_sampled_search_and_batch_recall(built, oracle):
+    pg, X, Q, g = built["pg"], built["X"], built["Q"], built["g"]
+    entries = np.concatenate([g["ep"], g["roots"]]).astype(np.int32)
+    ids, _ = pg.search(built["Xd"], built["gd"]["ids"], built["gd"]["deg"], built["Qd"], dev(entries), 10,
+                       L_BENCH)
+    ids = host(ids)
+    qs = np.random.default_rng(24).choice(NQ, size=30, replace=False)
+    rid, _, _ = oracle.search(X, g["ids"], g["deg"], Q[qs], entries, 10, L_BENCH)
+    same = sum(list(a) == list(b) for a, b in zip(ids[qs], rid))
+    print(f"[fullsize-deep] sampled searches identical {same}/30", flush=True)
+    assert same >= 29
+    gt, _ = pg.exact_knn(built["Xd"], built["Qd"], 10)
+    gt = host(gt)
+    rec = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids.tolist(), gt.tolist())])
+    print(f"[fullsize-deep] recall@10 at L={L_BENCH}: {rec:.4f}", flush=True)
+    assert rec >= 0.94
