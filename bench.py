@@ -19,6 +19,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -143,6 +144,11 @@ def main():
                     help="also build the global HNSW (Alg. 7, FastHNSW) with ef=EF, M=R, k0=K, "
                          "alpha 65 degrees and 2 OptKCNA rounds per layer on the fastest path, "
                          "and report its build time and layered-search recall")
+    ap.add_argument("--serve", type=int, default=0, metavar="JOBS",
+                    help="also run the serving mix: JOBS collections (N log-uniform in [1e3, 2e5], "
+                         "d in {96, 128, 384, 768}, unit vectors in 20 clusters, K = R = 32) with 4 "
+                         "query batches each, first saturated, then Poisson arrivals at half that rate")
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--paths", default="fp32,fp16",
                     help="comma-separated join paths to measure: fp32, fp16, bf16, fp32-valu")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -220,6 +226,8 @@ def main():
         out["iter_nsg"] = run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[best])
     if args.hnsw:
         out["fast_hnsw"] = run_hnsw(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[best])
+    if args.serve:
+        out["serving"] = run_serve(args)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_sample} points")
         out["cpu_baseline"] = cpu_baseline(w, X, args.cpu_sample)
@@ -313,6 +321,72 @@ def run_hnsw(args, w, pg, torch, ctx, Xd, Qd, gt, path):
     return {"ef": ef, "M": R, "k0": K, "alpha_deg": 65.0, "rounds": 2, "layer_sizes": sizes,
             "build_ms": 1000.0 * build_s, "points_per_s": w["n"] / build_s, "ef_search": chosen,
             "search_ladder": ladder, "qps_batch": Qd.shape[0] / qs}
+
+
+def run_serve(args):
+    """The serving mix (continuous batching of build jobs and query batches,
+    admission by HBM footprint): saturated throughput, then latencies under
+    Poisson arrivals at half the saturated job rate."""
+    from paper_2410_01231_amd import datagen
+    from paper_2410_01231_amd.serve import BuildJob, QueryBatch, Server, percentiles
+    rng = np.random.default_rng(5)
+    jobs, batches = [], []
+    for i in range(args.serve):
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e5)))))
+        d = int(rng.choice([96, 128, 384, 768]))
+        sizes = rng.integers(1, 513, size=4)
+        X, Q = datagen.unit_mixture(n, int(sizes.sum()), d=d, n_clusters=20, seed=100 + i)
+        jobs.append(BuildJob(f"j{i}", X, K=32, R=32, S=16, max_iters=12, seed=1))
+        cuts = np.concatenate([[0], np.cumsum(sizes)])
+        batches.append([QueryBatch(f"j{i}", Q[cuts[b]:cuts[b + 1]], k=10, L=64) for b in range(4)])
+    points = sum(j.X.shape[0] for j in jobs)
+    log(f"[bench] serving mix: {len(jobs)} jobs, {points} points")
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def run(arrivals):
+        srv = Server(budget, workers=8)
+        done_q = {j.job_id: 0 for j in jobs}
+        lock = threading.Lock()
+
+        def query_done(job_id):
+            def cb(_):
+                with lock:
+                    done_q[job_id] += 1
+                    last = done_q[job_id] == 4
+                if last:
+                    srv.release(job_id)
+            return cb
+        fb, fq = [], []
+        t0 = time.perf_counter()
+        for j, qs, at in zip(jobs, batches, arrivals):
+            delay = t0 + at - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            fb.append(srv.submit_build(j))
+            for q in qs:
+                f = srv.submit_query(q)
+                f.add_done_callback(query_done(j.job_id))
+                fq.append(f)
+        blat = [f.result()[1].latency for f in fb]
+        qres = [f.result()[1] for f in fq]
+        wall = time.perf_counter() - t0
+        srv.close()
+        log(f"[bench] serving run: {wall:.2f} s, peak ledger {srv.peak_in_use / 2**30:.1f} GiB")
+        return wall, blat, qres, srv.peak_in_use
+
+    wall, _, _, peak = run([0.0] * len(jobs))
+    rate = len(jobs) / wall
+    gaps = rng.exponential(1.0 / (0.5 * rate), size=len(jobs))
+    wall2, blat, qres, peak2 = run(np.cumsum(gaps) - gaps[0])
+
+    def ms(v):
+        return {k: (1000.0 * x if x is not None else None) for k, x in percentiles(v).items()}
+    return {"jobs": len(jobs), "points": points, "budget_bytes": budget,
+            "saturated_s": wall, "saturated_jobs_per_s": rate, "saturated_points_per_s": points / wall,
+            "peak_in_use_bytes": max(peak, peak2), "arrival_rate_jobs_per_s": 0.5 * rate,
+            "poisson_s": wall2, "build_latency_ms": ms(blat),
+            "query_latency_ms": ms([t.latency for t in qres]),
+            "query_service_ms": ms([t.service for t in qres])}
 
 
 # join paths: precision code of pg_knn_build, dtype the join computes in

@@ -172,6 +172,25 @@ def _dev_i32(t, name):
     return t.contiguous()
 
 
+def knn_workspace_bytes(n, d, K, S=None, max_iters=12, precision=FP32):
+    """Workspace bytes pg_knn_build needs for n rows of d dimensions."""
+    lib = load_library()
+    S = (K + 1) // 2 if S is None else S
+    p = KnnParams(K=K, S=S, max_iters=max_iters, precision=precision)
+    ws = c_size_t()
+    _check(lib.pg_knn_build_workspace(ctypes.byref(p), n, d, ctypes.byref(ws)), "workspace")
+    return int(ws.value)
+
+
+def prune_workspace_bytes(n, d, C, R, alpha_deg=60.0):
+    """Workspace bytes pg_prune needs for n candidate lists of C ids."""
+    lib = load_library()
+    p = PruneParams(R=R, alpha_deg=float(alpha_deg), stages=STAGES_ALL)
+    ws = c_size_t()
+    _check(lib.pg_prune_workspace(ctypes.byref(p), n, d, C, ctypes.byref(ws)), "workspace")
+    return int(ws.value)
+
+
 def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001, exact=False,
               bucket_cap=0, chunks=0, precision=FP32, margin_rel=0.0, ctx=None):
     """NN-Descent kNN lists of the rows of X: returns (ids, d2, stats dict)."""

@@ -1,0 +1,100 @@
+"""Admission of the serving loop, driven on the CPU with a fake runner and
+fake footprints: FIFO order against the HBM budget, rejection of requests
+larger than the budget, resident graphs held until release, queries waiting
+for their collection, and a failing request leaving the server running."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2410_01231_amd.serve import AdmissionError, BuildJob, QueryBatch, Server
+
+
+class Fake:
+    def __init__(self, sizes):
+        self.sizes = sizes                  # job_id -> (running bytes, resident bytes)
+        self.gates = {k: threading.Event() for k in sizes}
+        self.started = []
+        self.lock = threading.Lock()
+
+    def footprint(self, kind, payload):
+        if kind == "query":
+            return 1, 0
+        return self.sizes[payload.job_id]
+
+    def runner(self, kind, payload, graph):
+        with self.lock:
+            self.started.append(f"{kind}:{payload.job_id}")
+        if kind == "build":
+            if payload.job_id == "bad":
+                raise ValueError("broken job")
+            assert self.gates[payload.job_id].wait(5.0)
+            return {"graph_of": payload.job_id}
+        return ("answer", payload.job_id, graph["graph_of"])
+
+
+def job(name):
+    return BuildJob(name, np.zeros((4, 4), np.float32))
+
+
+def wait_until(cond, timeout=5.0):
+    t0 = time.time()
+    while not cond():
+        assert time.time() - t0 < timeout, "timed out"
+        time.sleep(0.005)
+
+
+def test_fifo_admission_and_rejection():
+    f = Fake({"A": (60, 0), "B": (50, 0), "C": (30, 0), "D": (120, 0)})
+    srv = Server(100, workers=4, runner=f.runner, footprint=f.footprint)
+    fa, fb, fc = srv.submit_build(job("A")), srv.submit_build(job("B")), srv.submit_build(job("C"))
+    fd = srv.submit_build(job("D"))
+    with pytest.raises(AdmissionError):
+        fd.result(timeout=1)
+    wait_until(lambda: f.started == ["build:A"])
+    time.sleep(0.1)
+    assert f.started == ["build:A"]          # B does not fit beside A, C waits behind B
+    f.gates["A"].set()
+    fa.result(timeout=5)
+    wait_until(lambda: len(f.started) == 3)
+    assert f.started[1:] == ["build:B", "build:C"]   # 50 + 30 fit together
+    f.gates["B"].set()
+    f.gates["C"].set()
+    fb.result(timeout=5)
+    fc.result(timeout=5)
+    srv.close()
+    assert srv.admission_log == ["build:A", "build:B", "build:C"]
+    assert srv.peak_in_use <= 100
+
+
+def test_resident_graph_held_until_release_and_queries_wait():
+    f = Fake({"A": (60, 40), "B": (70, 10)})
+    srv = Server(100, workers=4, runner=f.runner, footprint=f.footprint)
+    fa = srv.submit_build(job("A"))
+    fq = srv.submit_query(QueryBatch("A", np.zeros((2, 4), np.float32)))
+    time.sleep(0.1)
+    assert f.started == ["build:A"]          # the query waits for A's graph
+    f.gates["A"].set()
+    (graph, _), (ans, _) = fa.result(timeout=5), fq.result(timeout=5)
+    assert ans == ("answer", "A", "A")
+    fb = srv.submit_build(job("B"))
+    time.sleep(0.15)
+    assert "build:B" not in f.started        # A's resident 40 + 70 > 100
+    srv.release("A")
+    wait_until(lambda: "build:B" in f.started)
+    f.gates["B"].set()
+    fb.result(timeout=5)
+    srv.close()
+
+
+def test_failing_request_does_not_stop_the_server():
+    f = Fake({"bad": (10, 0), "A": (10, 0)})
+    srv = Server(100, workers=2, runner=f.runner, footprint=f.footprint)
+    fbad = srv.submit_build(job("bad"))
+    with pytest.raises(ValueError):
+        fbad.result(timeout=5)
+    f.gates["A"].set()
+    (g, timing) = srv.submit_build(job("A")).result(timeout=5)
+    assert g == {"graph_of": "A"} and timing.latency >= timing.service >= 0
+    srv.close()
