@@ -485,6 +485,9 @@ constexpr int JW = 2;            // sources (waves) per workgroup
 constexpr int JT = JW * PG_WAVE;
 constexpr int JDC = 16;          // dims per LDS chunk
 constexpr int TRW = 4, TCL = 8;  // micro-tile: 4 new members x 8 members
+// float4 staging loads per lane and chunk for a join set of at most 160
+// members (3S + K with S <= 32, K <= 64)
+constexpr int JPF = (160 * (JDC / 4) + PG_WAVE - 1) / PG_WAVE;
 
 // LDS column stride (floats) for a join set of at most maxm members: a
 // multiple of 4 (16-byte reads), padded off a multiple of 8.
@@ -559,6 +562,13 @@ __global__ __launch_bounds__(JT) void k_join(
     int T = 0;
     for (int rb = 0; rb < RB; ++rb) T += CB - (rb >> 1);
     unsigned long long local_props = 0;
+    // the member row behind each of this lane's staging loads
+    int32_t fid[JPF];
+#pragma unroll
+    for (int j = 0; j < JPF; ++j) {
+        const int e = lane + PG_WAVE * j;
+        fid[j] = e < mp * (JDC / 4) ? ids[e / (JDC / 4)] : -1;
+    }
     for (int round0 = 0; round0 < T; round0 += PG_WAVE) {
         float acc[TRW][TCL];
         int brb = -1, bcb = 0;
@@ -578,20 +588,34 @@ __global__ __launch_bounds__(JT) void k_join(
         for (int a = 0; a < TRW; ++a)
 #pragma unroll
             for (int c = 0; c < TCL; ++c) acc[a][c] = 0.0f;
+        // the rows of the next chunk load while the current one is summed
+        float4 v[JPF];
+        auto fetch = [&](int c0) {
+            const int dl = min(JDC, d - c0);
+#pragma unroll
+            for (int j = 0; j < JPF; ++j) {
+                const int q = (lane + PG_WAVE * j) % (JDC / 4);
+                v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (fid[j] >= 0 && 4 * q < dl)
+                    v[j] = *reinterpret_cast<const float4 *>(X + (int64_t)fid[j] * ldx + c0 + 4 * q);
+            }
+        };
+        fetch(0);
         for (int c0 = 0; c0 < d; c0 += JDC) {
             const int dl = min(JDC, d - c0);
             __builtin_amdgcn_wave_barrier();
-            for (int e = lane; e < mp * (JDC / 4); e += PG_WAVE) {
-                const int q = e % (JDC / 4), i = e / (JDC / 4);
-                const int32_t id = ids[i];
-                float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (id >= 0 && 4 * q < dl)
-                    val = *reinterpret_cast<const float4 *>(X + (int64_t)id * ldx + c0 + 4 * q);
-                tile[(4 * q + 0) * MPS + i] = val.x;
-                tile[(4 * q + 1) * MPS + i] = val.y;
-                tile[(4 * q + 2) * MPS + i] = val.z;
-                tile[(4 * q + 3) * MPS + i] = val.w;
+#pragma unroll
+            for (int j = 0; j < JPF; ++j) {
+                const int e = lane + PG_WAVE * j;
+                if (e < mp * (JDC / 4)) {
+                    const int q = e % (JDC / 4), i = e / (JDC / 4);
+                    tile[(4 * q + 0) * MPS + i] = v[j].x;
+                    tile[(4 * q + 1) * MPS + i] = v[j].y;
+                    tile[(4 * q + 2) * MPS + i] = v[j].z;
+                    tile[(4 * q + 3) * MPS + i] = v[j].w;
+                }
             }
+            if (c0 + JDC < d) fetch(c0 + JDC);
             __builtin_amdgcn_wave_barrier();
             if (brb >= 0) {
                 const float *rp = tile + TRW * brb;
