@@ -85,9 +85,25 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
     uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, PG_WAVE);
     return ((uint64_t)hi << 32) | lo;
 }
+// Value held by lane (lane ^ m).  Distances 1, 2 and 8 stay inside the VALU
+// (DPP quad permutes and a row rotation by 8, which is the exchange of the two
+// row halves); 4 and 16 are swizzles in bitmask mode (and 31, xor m, applied
+// within each half-wave); other distances go through the LDS crossbar.  The
+// fast forms need a constant m, which they get once the callers' loops over
+// distances are unrolled.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int m) {
+    switch (m) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror 8
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+    default: return (uint32_t)__shfl_xor((int)v, m, PG_WAVE);
+    }
+}
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, PG_WAVE);
-    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, PG_WAVE);
+    const uint32_t lo = xor_lane((uint32_t)v, m);
+    const uint32_t hi = xor_lane((uint32_t)(v >> 32), m);
     return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
@@ -103,15 +119,13 @@ __device__ __forceinline__ void wave_sort(uint64_t &k, int &p) {
     for (int size = 2; size <= PG_WAVE; size <<= 1) {
 #pragma unroll
         for (int j = size >> 1; j > 0; j >>= 1) {
-            uint64_t ok = shfl_xor64(k, j);
-            int op = __shfl_xor(p, j, PG_WAVE);
-            bool asc = (lane & size) == 0;
-            bool lower = (lane & j) == 0;
-            bool take = (lower == asc) ? (ok < k) : (ok > k);
-            if (take) {
-                k = ok;
-                p = op;
-            }
+            const uint64_t ok = shfl_xor64(k, j);
+            const int op = (int)xor_lane((uint32_t)p, j);
+            const bool asc = (lane & size) == 0;
+            const bool lower = (lane & j) == 0;
+            const bool take = (lower == asc) ? (ok < k) : (ok > k);
+            k = take ? ok : k;
+            p = take ? op : p;
         }
     }
 }
@@ -125,14 +139,12 @@ __device__ __forceinline__ void wave_bitonic_merge(uint64_t &k, int &p) {
     const int lane = lane_id();
 #pragma unroll
     for (int j = PG_WAVE / 2; j > 0; j >>= 1) {
-        uint64_t ok = shfl_xor64(k, j);
-        int op = __shfl_xor(p, j, PG_WAVE);
-        bool lower = (lane & j) == 0;
-        bool take = lower ? (ok < k) : (ok > k);
-        if (take) {
-            k = ok;
-            p = op;
-        }
+        const uint64_t ok = shfl_xor64(k, j);
+        const int op = (int)xor_lane((uint32_t)p, j);
+        const bool lower = (lane & j) == 0;
+        const bool take = lower ? (ok < k) : (ok > k);
+        k = take ? ok : k;
+        p = take ? op : p;
     }
 }
 
@@ -142,10 +154,9 @@ __device__ __forceinline__ void wave_merge_lowest(uint64_t &a, int &pa, uint64_t
     const int lane = lane_id();
     uint64_t br = shfl64(b, PG_WAVE - 1 - lane);
     int pbr = __shfl(pb, PG_WAVE - 1 - lane, PG_WAVE);
-    if (br < a) {
-        a = br;
-        pa = pbr;
-    }
+    const bool lt = br < a;
+    a = lt ? br : a;
+    pa = lt ? pbr : pa;
     wave_bitonic_merge(a, pa);
 }
 

@@ -61,14 +61,12 @@ __device__ __forceinline__ void seg_sort(uint64_t &k, int &p) {
 #pragma unroll
         for (int j = size >> 1; j > 0; j >>= 1) {
             const uint64_t ok = shfl_xor64(k, j);
-            const int op = __shfl_xor(p, j, PG_WAVE);
+            const int op = (int)xor_lane((uint32_t)p, j);
             const bool asc = (sl & size) == 0;
             const bool lower = (sl & j) == 0;
             const bool take = (lower == asc) ? (ok < k) : (ok > k);
-            if (take) {
-                k = ok;
-                p = op;
-            }
+            k = take ? ok : k;
+            p = take ? op : p;
         }
     }
 }
