@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void k_build_join(
         }
         int pa = 0;
         wave_sort(a, pa);
-        const uint64_t prev = shfl64(a, max(lane - 1, 0));
+        const uint64_t prev = from_lane_below64(a);
         const int nn = wave_compact(a, pa, a != KEY_INF && (lane == 0 || prev != a));
         if (lane < nn) jn[v * JN + lane] = (int32_t)a;
         // old set
@@ -1182,7 +1182,7 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
     const int64_t s0 = soff ? soff[v] : 0;
     const int sc = soff ? (int)(soff[v + 1] - s0) : 0;
     for (int b0 = 0; b0 < cc + sc; b0 += PG_WAVE) {
-        const uint64_t kth = shfl64(a, K - 1);
+        const uint64_t kth = readlane64(a, K - 1);
         const int e = b0 + lane;
         uint64_t bk = KEY_INF;
         if (e < cc)
@@ -1196,11 +1196,11 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
             // few survivors: insert them one by one (rank by ballot, shift up)
             for (uint64_t rem = vm; rem; rem &= rem - 1) {
                 const uint64_t x = readlane64(bk, __ffsll((long long)rem) - 1);
-                if (x >= shfl64(a, K - 1)) continue;  // not among the K smallest
+                if (x >= readlane64(a, K - 1)) continue;  // not among the K smallest
                 if (__ballot(a == x)) continue;       // already in the list
                 const int at = __popcll(__ballot(a < x));
-                const uint64_t up = shfl64(a, max(lane - 1, 0));
-                const int fup = __shfl(fl, max(lane - 1, 0), PG_WAVE);
+                const uint64_t up = from_lane_below64(a);
+                const int fup = (int)from_lane_below((uint32_t)fl);
                 if (lane > at) {
                     a = up;
                     fl = fup;
@@ -1217,7 +1217,7 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
         }
         int pb = 3;
         wave_sort(bk, pb);
-        const uint64_t prev = shfl64(bk, max(lane - 1, 0));
+        const uint64_t prev = from_lane_below64(bk);
         const bool dup = lane > 0 && prev == bk;
         const bool in_list = wave_contains(a, bk);
         const bool valid = bk != KEY_INF && !dup && !in_list;

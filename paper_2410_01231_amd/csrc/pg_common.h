@@ -106,6 +106,16 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
     const uint32_t hi = xor_lane((uint32_t)(v >> 32), m);
     return ((uint64_t)hi << 32) | lo;
 }
+// Value held by lane - 1, lane 0 keeping its own: a DPP shift of the whole
+// wave right by one lane (lane 0 has no source and keeps `old`).
+__device__ __forceinline__ uint32_t from_lane_below(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x138, 0xF, 0xF, false);  // wave_shr 1
+}
+__device__ __forceinline__ uint64_t from_lane_below64(uint64_t v) {
+    const uint32_t lo = from_lane_below((uint32_t)v);
+    const uint32_t hi = from_lane_below((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
     uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64) void k_prune(
             }
             int pos = idx;
             wave_sort(key, pos);
-            const uint64_t prev = shfl64(key, max(lane - 1, 0));
+            const uint64_t prev = from_lane_below64(key);
             const bool valid = key != KEY_INF && !(lane > 0 && prev == key);
             const int cl = wave_count_less(top, key);
             const uint64_t at = shfl64(top, min(cl, PG_WAVE - 1));
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             if (first && m <= PG_WAVE) {
                 // a list that is already sorted, distinct and valid (a kNN
                 // list, a PRUNE result) is the round as it stands
-                const uint64_t prv = shfl64(key, max(lane - 1, 0));
+                const uint64_t prv = from_lane_below64(key);
                 const bool bad = idx < m && (key == KEY_INF || (lane > 0 && !(prv < key)));
                 if (__ballot(bad) == 0) {
                     top = key;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             }
             int pos = idx;
             wave_sort(key, pos);
-            const uint64_t prev = shfl64(key, max(lane - 1, 0));
+            const uint64_t prev = from_lane_below64(key);
             const bool valid = key != KEY_INF && !(lane > 0 && prev == key);
             const int cl = wave_count_less(top, key);
             const uint64_t at = shfl64(top, min(cl, PG_WAVE - 1));
@@ -762,6 +762,44 @@ __global__ __launch_bounds__(256) void k_root_lists(const float *__restrict__ X,
     }
 }
 
+// Running C smallest keys of one root over a stream of 64-key slices (one
+// key per lane, KEY_INF = none).  `top` is ascending, one key per lane.  Keys
+// below the list's C-th are gathered in `pend` (lanes < np) and sorted into
+// the list once 64 are waiting, so a slice costs a compare and a ballot
+// unless it holds such keys.  The threshold lags the pending keys, which only
+// lets more keys through: the result is the C smallest keys of the stream.
+__device__ __forceinline__ void topacc_flush(uint64_t &top, uint64_t &pend, int &np) {
+    if (np == 0) return;
+    int pp = 0, pt = 0;
+    wave_sort(pend, pp);
+    wave_merge_lowest(top, pt, pend, pp);
+    pend = KEY_INF;
+    np = 0;
+}
+
+__device__ __forceinline__ void topacc_add(uint64_t &top, uint64_t &pend, int &np, uint64_t k, int C) {
+    const int lane = lane_id();
+    bool pass = k < readlane64(top, C - 1);
+    uint64_t m = __ballot(pass);
+    if (m == 0) return;
+    if (np + __popcll(m) > PG_WAVE) {
+        topacc_flush(top, pend, np);
+        pass = k < readlane64(top, C - 1);
+        m = __ballot(pass);
+        if (m == 0) return;
+    }
+    const int cnt = __popcll(m);
+    // a permutation of the lanes: passing keys to lanes np .. np + cnt - 1 in
+    // lane order, the others to the remaining lanes
+    const int below = __popcll(m & lanemask_lt());
+    const int rest = lane - below;
+    const int dst = pass ? np + below : (rest < np ? rest : rest + cnt);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst * 4, (int)(uint32_t)k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst * 4, (int)(uint32_t)(k >> 32));
+    if (lane >= np && lane < np + cnt) pend = ((uint64_t)hi << 32) | lo;
+    np += cnt;
+}
+
 // Nearest nodes of F for the queued roots.  Block (x, y) scans chunk x of F
 // for queued roots [GQ y, GQ y + GQ): every thread takes one free node per
 // tile and computes the canonical distance chains to those roots; a node
@@ -791,9 +829,14 @@ __global__ __launch_bounds__(256) void k_global_topg(const float *__restrict__ X
         bq[q] = q < nq ? queue[q0 + q] : -1;
         rq[q] = roots[q < nq ? bq[q] : queue[q0]];
     }
-    uint64_t top[PER_WAVE];
+    uint64_t top[PER_WAVE], pend[PER_WAVE];
+    int np[PER_WAVE];
 #pragma unroll
-    for (int s = 0; s < PER_WAVE; ++s) top[s] = KEY_INF;
+    for (int s = 0; s < PER_WAVE; ++s) {
+        top[s] = KEY_INF;
+        pend[s] = KEY_INF;
+        np[s] = 0;
+    }
     const int32_t f0 = (int32_t)blockIdx.x * chunk, f1 = min(nf, f0 + chunk);
     for (int32_t t = f0; t < f1; t += TG_TILE) {
         const int32_t i = t + (int32_t)threadIdx.x;
@@ -826,18 +869,13 @@ __global__ __launch_bounds__(256) void k_global_topg(const float *__restrict__ X
         for (int s = 0; s < PER_WAVE; ++s) {
             const int q = wv * PER_WAVE + s;
 #pragma unroll
-            for (int c = 0; c < TG_TILE; c += PG_WAVE) {
-                uint64_t k = kb[q][c + lane];
-                if (__ballot(k < readlane64(top[s], C - 1)) == 0) continue;
-                int pk = 0, pt = 0;
-                wave_sort(k, pk);
-                wave_merge_lowest(top[s], pt, k, pk);
-            }
+            for (int c = 0; c < TG_TILE; c += PG_WAVE) topacc_add(top[s], pend[s], np[s], kb[q][c + lane], C);
         }
         __syncthreads();
     }
 #pragma unroll
     for (int s = 0; s < PER_WAVE; ++s) {
+        topacc_flush(top[s], pend[s], np[s]);
         const int q = wv * PER_WAVE + s;
         if (q >= nq) continue;
         if (nchunk == 1) {
@@ -845,6 +883,98 @@ __global__ __launch_bounds__(256) void k_global_topg(const float *__restrict__ X
             if (lane < C - nv) keys[(int64_t)(bq[q] - b0) * C + nv + lane] = top[s];
         } else if (lane < C) {
             part[((int64_t)(q0 + q) * nchunk + blockIdx.x) * C + lane] = top[s];
+        }
+    }
+}
+
+// The same scan on data that pass the exactness test of the 16-bit path:
+// block (x, y) takes queued roots [GQM y, GQM y + GQM) and chunk x of F.  Each
+// wave forms 32 x 32 Gram tiles (the block's roots x 32 free nodes) with the
+// roots' fragments held in registers; d2 = n_r + n_p - 2 r.p equals the
+// canonical chain on such data.  A step's four tiles go through LDS to the
+// waves that keep the running lists, GQM / 4 roots each.
+constexpr int GQM = 32;
+template <int KS>  // 16-dimension k-steps held in registers: d16 <= 16 KS
+__global__ __launch_bounds__(256) void k_global_topg_mfma(
+    const _Float16 *__restrict__ x16, int d16, const float *__restrict__ norms, int R,
+    const int32_t *__restrict__ roots, const int32_t *__restrict__ tt, const int32_t *__restrict__ deg,
+    const int32_t *__restrict__ F, int32_t nf, int32_t chunk, int32_t nchunk, const int32_t *__restrict__ queue,
+    const int32_t *__restrict__ qvalid, int32_t nqueued, int32_t b0, int C, uint64_t *__restrict__ keys,
+    uint64_t *__restrict__ part) {
+    constexpr int OWN = GQM / 4;
+    __shared__ uint64_t kb[GQM][4 * 32];
+    __shared__ float rn[GQM];
+    __shared__ int32_t rturn[GQM];
+    const int lane = lane_id(), wv = (int)(threadIdx.x >> 6), h = lane >> 5, l32 = lane & 31;
+    const int q0 = (int)blockIdx.y * GQM;
+    const int nq = min(GQM, nqueued - q0);
+    if (threadIdx.x < GQM) {
+        const int q = (int)threadIdx.x;
+        const int32_t b = queue[q0 + min(q, nq - 1)];
+        rturn[q] = q < nq ? b : -1;
+        rn[q] = norms[roots[b]];
+    }
+    // A operand: root of row l32 (rows past nq repeat the last root, masked below)
+    pm_f16x8 A[KS];
+    {
+        const int32_t r = roots[queue[q0 + min(l32, nq - 1)]];
+        const _Float16 *pa = x16 + (int64_t)r * d16 + 8 * h;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            A[s] = 16 * s < d16 ? *reinterpret_cast<const pm_f16x8 *>(pa + 16 * s) : pm_f16x8{};
+    }
+    uint64_t top[OWN], pend[OWN];
+    int np[OWN];
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        top[o] = KEY_INF;
+        pend[o] = KEY_INF;
+        np[o] = 0;
+    }
+    __syncthreads();
+    const int32_t f0 = (int32_t)blockIdx.x * chunk, f1 = min(nf, f0 + chunk);
+    for (int32_t t = f0; t < f1; t += 4 * 32) {
+        const int32_t i = t + wv * 32 + l32;
+        const bool in = i < f1;
+        const int32_t p = in ? F[i] : F[f0];
+        const _Float16 *pb = x16 + (int64_t)p * d16 + 8 * h;
+        pm_f16x8 B[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            B[s] = 16 * s < d16 ? *reinterpret_cast<const pm_f16x8 *>(pb + 16 * s) : pm_f16x8{};
+        pm_f32x16 acc;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc[g] = 0.f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (16 * s < d16) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[s], B[s], acc, 0, 0, 0);
+        const float npn = norms[p];
+        const int32_t tp = (in && deg[p] < R) ? tt[p] : INT32_MAX;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+            const int row = 8 * (g / 4) + 4 * h + (g % 4);
+            const float d2 = fmaxf(fmaf(-2.0f, acc[g], rn[row] + npn), 0.0f);
+            kb[row][wv * 32 + l32] = tp <= rturn[row] ? pack_key(d2, p) : KEY_INF;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const int q = wv * OWN + o;
+            topacc_add(top[o], pend[o], np[o], kb[q][lane], C);
+            topacc_add(top[o], pend[o], np[o], kb[q][PG_WAVE + lane], C);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        topacc_flush(top[o], pend[o], np[o]);
+        const int q = wv * OWN + o;
+        if (q >= nq) continue;
+        if (nchunk == 1) {
+            const int nv = qvalid[q0 + q];
+            if (lane < C - nv) keys[(int64_t)(rturn[q] - b0) * C + nv + lane] = top[o];
+        } else if (lane < C) {
+            part[((int64_t)(q0 + q) * nchunk + blockIdx.x) * C + lane] = top[o];
         }
     }
 }
@@ -1012,6 +1142,7 @@ struct PruneLayout {
         part, cpart, cen, apd, api, scan_tmp, x16, norms, exflags, total;
     int d16;
     int64_t ncb, nab;
+    int64_t part_keys;  // keys the per-chunk lists of the scan over F can hold
 };
 
 static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d) {
@@ -1045,7 +1176,8 @@ static PruneLayout prune_layout(const pg_prune_params *p, int64_t n, int d) {
     // keeps chunks x root groups below 2 TG_BLOCKS
     const int64_t groups = (nb + GQ - 1) / GQ;
     const int64_t part_blocks = std::min<int64_t>(2 * TG_BLOCKS, groups * ((n + TG_MIN_CHUNK - 1) / TG_MIN_CHUNK));
-    L.part = take(sizeof(uint64_t) * 64 * GQ * part_blocks);
+    L.part_keys = 64 * GQ * part_blocks;
+    L.part = take(sizeof(uint64_t) * L.part_keys);
     L.cpart = take(sizeof(double) * L.ncb * d);
     L.cen = take(sizeof(double) * d);
     L.apd = take(sizeof(double) * L.nab);
@@ -1133,9 +1265,11 @@ static pg_status write_to(pg_ctx *ctx, T *dev, T value) {
 }
 
 // The connect step (see the comment above ConnState).
+// exact16: x16 and the norms hold the exact 16-bit copy (see k_prune_prep),
+// so the scan over F may take its distances from MFMA Gram tiles.
 static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float *X, int64_t n, int d,
                          int64_t ldx, const int32_t *cand, int C, int R, int32_t *g_ids, float *g_d2,
-                         int32_t *g_deg, const int32_t *ep, int32_t *roots, int32_t *n_roots) {
+                         int32_t *g_deg, const int32_t *ep, int32_t *roots, int32_t *n_roots, bool exact16) {
     hipStream_t st = ctx->stream;
     int32_t *cnt = (int32_t *)(w + L.cnt), *U = (int32_t *)(w + L.rev), *visited = (int32_t *)(w + L.visited),
             *fa = (int32_t *)(w + L.fa), *fb = (int32_t *)(w + L.fb), *queue = (int32_t *)(w + L.empty),
@@ -1203,14 +1337,29 @@ static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float
         int32_t ne = 0;
         PG_TRY(read_back(ctx, &ne, &cs->n_empty));
         if (ne > 0 && nf > 0) {
-            const int64_t groups = (ne + GQ - 1) / GQ;
+            const bool mf = exact16 && L.d16 <= 256;
+            const int gq = mf ? GQM : GQ;
+            const int64_t groups = (ne + gq - 1) / gq;
             int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((TG_BLOCKS + groups - 1) / groups,
                                                                     (nf + TG_MIN_CHUNK - 1) / TG_MIN_CHUNK));
+            // the per-chunk lists (ne x nchunk lists of C keys) must fit their buffer
+            nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, L.part_keys / ((int64_t)ne * C)));
             const int64_t chunk = ((nf + nchunk - 1) / nchunk + TG_TILE - 1) / TG_TILE * TG_TILE;
             nchunk = (nf + chunk - 1) / chunk;
-            hipLaunchKernelGGL(k_global_topg, dim3((unsigned)nchunk, (unsigned)groups), dim3(256), 0, st, X, ldx, d,
-                               R, rts, tt, g_deg, F, nf, (int32_t)chunk, (int32_t)nchunk, queue, qvalid, ne, b0, C,
-                               keys, part);
+            const _Float16 *x16 = (const _Float16 *)(w + L.x16);
+            const float *nrm = (const float *)(w + L.norms);
+            if (mf && L.d16 <= 128)
+                hipLaunchKernelGGL(k_global_topg_mfma<8>, dim3((unsigned)nchunk, (unsigned)groups), dim3(256), 0, st,
+                                   x16, L.d16, nrm, R, rts, tt, g_deg, F, nf, (int32_t)chunk, (int32_t)nchunk, queue,
+                                   qvalid, ne, b0, C, keys, part);
+            else if (mf)
+                hipLaunchKernelGGL(k_global_topg_mfma<16>, dim3((unsigned)nchunk, (unsigned)groups), dim3(256), 0, st,
+                                   x16, L.d16, nrm, R, rts, tt, g_deg, F, nf, (int32_t)chunk, (int32_t)nchunk, queue,
+                                   qvalid, ne, b0, C, keys, part);
+            else
+                hipLaunchKernelGGL(k_global_topg, dim3((unsigned)nchunk, (unsigned)groups), dim3(256), 0, st, X, ldx,
+                                   d, R, rts, tt, g_deg, F, nf, (int32_t)chunk, (int32_t)nchunk, queue, qvalid, ne, b0,
+                                   C, keys, part);
             PG_HIP(hipGetLastError());
             if (nchunk > 1) {
                 hipLaunchKernelGGL(k_topg_merge, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, st, part,
@@ -1362,7 +1511,7 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
     if (n_roots) *n_roots = 0;
     if (p->stages & PG_STAGE_CONNECT) {
         TimedLaunch tl(ctx, K_CONNECT, -1.0);
-        PG_TRY(connect(ctx, L, w, X, n, d, ldx, cand_ids, C, R, g_ids, g_d2, g_deg, ep, roots, n_roots));
+        PG_TRY(connect(ctx, L, w, X, n, d, ldx, cand_ids, C, R, g_ids, g_d2, g_deg, ep, roots, n_roots, exact16));
     }
     return PG_OK;
 }
