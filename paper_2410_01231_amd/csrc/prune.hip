@@ -624,8 +624,6 @@ struct ConnState {
 
 // roots handled per batch of key lists
 constexpr int32_t CONNECT_BATCH = 16384;
-// roots per step of the matching wave
-constexpr int MATCH_STEP = 16;
 // roots with fewer usable candidates than this get the nearest free nodes
 // appended to their key lists
 constexpr int GLOBAL_TAIL_BELOW = 1;
@@ -999,13 +997,20 @@ __global__ __launch_bounds__(256) void k_topg_merge(const uint64_t *__restrict__
     if (lane < C - nv) keys[(int64_t)(queue[qi] - b0) * C + nv + lane] = top;
 }
 
-// Roots in turn order, MATCH_STEP at a time: each takes the first key of its
-// list whose node is still below degree R and appends the edge p -> r there.
-// Degrees are read once per step (after the previous step's atomics have
-// landed) and corrected by the picks made earlier in the same step.  A root
-// whose list has no such node stops the wave (stop_root >= 0, nearest reset);
-// the host then runs the exact scan over F for it and restarts the wave.  A
-// wave started after a failed scan reports the overflow (stop_root = -2).
+// Roots in turn order: each takes the first key of its list whose node is
+// still below degree R and appends the edge p -> r there.  Windows of 64
+// roots, one per lane: every lane finds the first listed node below R in the
+// degrees at the window's start, and counts the earlier lanes that took the
+// same node.  Up to the first lane whose node that count fills (or whose list
+// has no such node), every lane's choice is the rule's own: the nodes before
+// it in its list were already at R, and its node still has room after the
+// earlier picks.  That prefix is written at once; the root after it then
+// decides with the degrees it left, over its whole list.  A root whose list
+// has no node below R stops the wave (stop_root >= 0, nearest reset); the
+// host then runs the exact scan over F for it and restarts the wave.  A wave
+// started after a failed scan reports the overflow (stop_root = -2).
+constexpr int MATCH_PROBE = 8;  // listed keys a lane examines per round
+
 __global__ __launch_bounds__(64) void k_match(const int32_t *__restrict__ roots, int32_t b0, int32_t b1,
                                               const uint64_t *__restrict__ keys, int C, int R, int32_t *g,
                                               float *gd, int32_t *deg, ConnState *cs) {
@@ -1014,46 +1019,77 @@ __global__ __launch_bounds__(64) void k_match(const int32_t *__restrict__ roots,
         if (lane == 0) cs->stop_root = -2;
         return;
     }
-    for (int32_t b = cs->idx; b < b1; b += MATCH_STEP) {
-        uint64_t kk[MATCH_STEP];
-        int32_t dv[MATCH_STEP], pick[MATCH_STEP];
+    int32_t b = cs->idx;
+    while (b < b1) {
+        const int32_t bi = b + lane;
+        const bool act = bi < b1;
+        int32_t p = -1, dp = 0;
+        float d2 = 0.f;
+        bool done = !act;
+        for (int j0 = 0; j0 < C && __ballot(!done) != 0; j0 += MATCH_PROBE) {
+            if (!done) {
+                uint64_t kq[MATCH_PROBE];
+                int32_t dq[MATCH_PROBE];
 #pragma unroll
-        for (int k = 0; k < MATCH_STEP; ++k)
-            kk[k] = (lane < C && b + k < b1) ? keys[(int64_t)(b + k - b0) * C + lane] : KEY_INF;
+                for (int t = 0; t < MATCH_PROBE; ++t)
+                    kq[t] = j0 + t < C ? keys[(int64_t)(bi - b0) * C + j0 + t] : KEY_INF;
 #pragma unroll
-        for (int k = 0; k < MATCH_STEP; ++k) dv[k] = kk[k] != KEY_INF ? ld_fresh(&deg[key_id(kk[k])]) : R;
+                for (int t = 0; t < MATCH_PROBE; ++t) dq[t] = kq[t] != KEY_INF ? ld_fresh(&deg[key_id(kq[t])]) : R;
 #pragma unroll
-        for (int k = 0; k < MATCH_STEP; ++k) {
-            pick[k] = -1;
-            if (b + k < b1) {
-                const int32_t pk = kk[k] != KEY_INF ? key_id(kk[k]) : -1;
-                int cur = dv[k];
-#pragma unroll
-                for (int j = 0; j < k; ++j) cur += (pk == pick[j]) ? 1 : 0;
-                const uint64_t ok = __ballot(pk >= 0 && cur < R);
-                if (ok == 0) {
-                    __threadfence();
-                    if (lane == 0) {
-                        cs->idx = b + k;
-                        cs->stop_root = roots[b + k];
-                        cs->stop_turn = b + k + 1;
-                        cs->nearest = KEY_INF;
+                for (int t = 0; t < MATCH_PROBE; ++t) {
+                    if (!done && dq[t] < R) {
+                        p = key_id(kq[t]);
+                        d2 = key_d2(kq[t]);
+                        dp = dq[t];
+                        done = true;
                     }
-                    return;
-                }
-                const int f = __ffsll((long long)ok) - 1;
-                const int32_t pp = __shfl(pk, f, PG_WAVE);
-                const int slot = __shfl(cur, f, PG_WAVE);
-                const uint64_t key = shfl64(kk[k], f);
-                pick[k] = pp;
-                if (lane == 0) {
-                    g[(int64_t)pp * R + slot] = roots[b + k];
-                    gd[(int64_t)pp * R + slot] = key_d2(key);
-                    atomicAdd(&deg[pp], 1);
                 }
             }
         }
+        // earlier lanes of the window that took the same node
+        int cnt = 0;
+#pragma unroll 8
+        for (int j = 0; j < PG_WAVE; ++j) {
+            const int32_t pj = __builtin_amdgcn_readlane(p, j);
+            cnt += (j < lane && pj == p) ? 1 : 0;
+        }
+        const bool ok = !act || (p >= 0 && dp + cnt < R);
+        const uint64_t bad = __ballot(!ok);
+        const int ncommit = bad != 0 ? __ffsll((long long)bad) - 1 : min(PG_WAVE, b1 - b);
+        if (lane < ncommit) {
+            const int slot = dp + cnt;
+            g[(int64_t)p * R + slot] = roots[bi];
+            gd[(int64_t)p * R + slot] = d2;
+            atomicAdd(&deg[p], 1);
+        }
         __threadfence();
+        b += ncommit;
+        if (bad == 0) continue;
+        // root b decides over its whole list with the degrees after the prefix
+        const uint64_t kk = lane < C ? keys[(int64_t)(b - b0) * C + lane] : KEY_INF;
+        const int32_t pk = kk != KEY_INF ? key_id(kk) : -1;
+        const int cur = pk >= 0 ? ld_fresh(&deg[pk]) : R;
+        const uint64_t okm = __ballot(pk >= 0 && cur < R);
+        if (okm == 0) {
+            if (lane == 0) {
+                cs->idx = b;
+                cs->stop_root = roots[b];
+                cs->stop_turn = b + 1;
+                cs->nearest = KEY_INF;
+            }
+            return;
+        }
+        const int f = __ffsll((long long)okm) - 1;  // wave-uniform
+        const int32_t pp = __builtin_amdgcn_readlane(pk, f);
+        const int slot = __builtin_amdgcn_readlane(cur, f);
+        const uint64_t key = readlane64(kk, f);
+        if (lane == 0) {
+            g[(int64_t)pp * R + slot] = roots[b];
+            gd[(int64_t)pp * R + slot] = key_d2(key);
+            atomicAdd(&deg[pp], 1);
+        }
+        __threadfence();
+        b += 1;
     }
     if (lane == 0) {
         cs->idx = b1;
