@@ -189,6 +189,24 @@ def main():
     kt, _ = pg.exact_knn(Xd, Xd[samp_d.long()], K, exclude=samp_d, ctx=ctx)
     kt = kt.cpu().numpy()
 
+    # the upload of X over PCIe, reported beside the HBM-resident build rate
+    # (the library takes device pointers, so it is never part of `value`)
+    Xh = torch.from_numpy(X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tmp = Xh.cuda()
+    torch.cuda.synchronize()
+    up_pageable = time.perf_counter() - t0
+    Xp = Xh.pin_memory()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tmp = Xp.to("cuda", non_blocking=True)
+    torch.cuda.synchronize()
+    up_pinned = time.perf_counter() - t0
+    del tmp, Xp
+    log(f"[bench] upload of X ({X.nbytes / 1e9:.2f} GB): pageable {1000 * up_pageable:.1f} ms, "
+        f"pinned {1000 * up_pinned:.1f} ms")
+
     results = {}
     for path in args.paths.split(","):
         results[path] = run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, PATHS[path])
@@ -219,6 +237,8 @@ def main():
         "recall@10": r["recall@10"], "knn_recall_sample": r["knn_recall_sample"],
         "qps_batch": r["qps_batch"], "query_latency_ms_batch1": r["query_latency_ms_batch1"],
         "roofline": r["roofline"],
+        "host_upload": {"bytes": int(X.nbytes), "pageable_ms": 1000.0 * up_pageable, "pinned_ms": 1000.0 * up_pinned,
+                        "points_per_s_with_pinned_upload": n / (r["ms_per_step"] / 1000.0 + up_pinned)},
         "paths": {p: {k: v for k, v in results[p].items() if k != "roofline"} | {"roofline": results[p]["roofline"]}
                   for p in results},
     }

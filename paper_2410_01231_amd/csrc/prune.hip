@@ -1010,6 +1010,7 @@ __global__ __launch_bounds__(256) void k_topg_merge(const uint64_t *__restrict__
 // host then runs the exact scan over F for it and restarts the wave.  A wave
 // started after a failed scan reports the overflow (stop_root = -2).
 constexpr int MATCH_PROBE = 8;  // listed keys a lane examines per round
+constexpr int STOP_CHAIN = 8;   // stops resolved per host synchronisation
 
 __global__ __launch_bounds__(64) void k_match(const int32_t *__restrict__ roots, int32_t b0, int32_t b1,
                                               const uint64_t *__restrict__ keys, int C, int R, int32_t *g,
@@ -1132,7 +1133,7 @@ __global__ __launch_bounds__(256) void k_bfs_step(const int32_t *__restrict__ g,
 }
 
 // exact scan for the stopped root: nearest node of F reached at its turn and
-// below degree R now
+// below degree R now (nothing when the wave has no stopped root)
 __global__ __launch_bounds__(256) void k_nearest_at(const float *__restrict__ X, int64_t ldx, int d, int R,
                                                     const int32_t *__restrict__ F, int32_t nf,
                                                     const int32_t *__restrict__ tt,
@@ -1140,6 +1141,7 @@ __global__ __launch_bounds__(256) void k_nearest_at(const float *__restrict__ X,
                                                     ConnState *__restrict__ cs) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t r = cs->stop_root, turn = cs->stop_turn;
+    if (r < 0) return;  // the same for every thread of the grid
     uint64_t key = KEY_INF;
     if (i < nf) {
         const int32_t p = F[i];
@@ -1157,6 +1159,7 @@ __global__ __launch_bounds__(256) void k_nearest_at(const float *__restrict__ X,
 __global__ void k_attach(int32_t *__restrict__ g, float *__restrict__ gd, int32_t *__restrict__ deg,
                          int R, ConnState *__restrict__ cs) {
     const int32_t r = cs->stop_root;
+    if (r < 0) return;  // no stopped root
     const unsigned long long key = cs->nearest;
     if (key == KEY_INF) {
         cs->overflow = 1;
@@ -1404,9 +1407,9 @@ static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float
             }
         }
         PG_TRY(write_to(ctx, &cs->idx, b0));
+        hipLaunchKernelGGL(k_match, dim3(1), dim3(64), 0, st, rts, b0, b1, keys, C, R, g_ids, g_d2, g_deg, cs);
+        PG_HIP(hipGetLastError());
         for (;;) {
-            hipLaunchKernelGGL(k_match, dim3(1), dim3(64), 0, st, rts, b0, b1, keys, C, R, g_ids, g_d2, g_deg, cs);
-            PG_HIP(hipGetLastError());
             int32_t stop = -1;
             PG_TRY(read_back(ctx, &stop, &cs->stop_root));
             if (stop == -1) break;
@@ -1414,8 +1417,15 @@ static pg_status connect(pg_ctx *ctx, const PruneLayout &L, char *w, const float
                 set_error("pg_prune: connect found every reachable node at degree R=%d", R);
                 return PG_EOVERFLOW;
             }
-            hipLaunchKernelGGL(k_nearest_at, dim3(nbf), dim3(256), 0, st, X, ldx, d, R, F, nf, tt, g_deg, cs);
-            hipLaunchKernelGGL(k_attach, dim3(1), dim3(1), 0, st, g_ids, g_d2, g_deg, R, cs);
+            // stops are resolved on the stream without waiting for each: the
+            // scan and the attach do nothing once the wave has no stopped
+            // root, and a wave restarted after the batch ends returns at once
+            for (int c = 0; c < STOP_CHAIN; ++c) {
+                hipLaunchKernelGGL(k_nearest_at, dim3(nbf), dim3(256), 0, st, X, ldx, d, R, F, nf, tt, g_deg, cs);
+                hipLaunchKernelGGL(k_attach, dim3(1), dim3(1), 0, st, g_ids, g_d2, g_deg, R, cs);
+                hipLaunchKernelGGL(k_match, dim3(1), dim3(64), 0, st, rts, b0, b1, keys, C, R, g_ids, g_d2, g_deg,
+                                   cs);
+            }
             PG_HIP(hipGetLastError());
         }
     }
