@@ -193,12 +193,15 @@ extern "C" pg_status pg_ctx_create(int device, void *hip_stream, pg_ctx **out) {
         return PG_EINVAL;
     }
     PG_HIP(hipSetDevice(device));
+    int ncu = 0;
+    PG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
     pg_ctx *c = new (std::nothrow) pg_ctx;
     if (!c) {
         set_error("pg_ctx_create: out of host memory");
         return PG_ENOMEM;
     }
     c->device = device;
+    c->num_cu = ncu;
     c->stream = (hipStream_t)hip_stream;
     c->timing = false;
     c->timing_state = new (std::nothrow) TimingState;

@@ -260,6 +260,7 @@ __device__ __forceinline__ float dist_chain(const float *__restrict__ a,
 // ---------------------------------------------------------------------------
 struct pg_ctx {
     int device;
+    int num_cu;  // compute units of the device
     hipStream_t stream;
     bool timing;
     void *timing_state;  // pgi::TimingState

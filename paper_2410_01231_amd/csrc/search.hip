@@ -76,10 +76,15 @@ __device__ __forceinline__ void seg_sort(uint64_t &k, int &p) {
 constexpr int ST_DIMS = 32;
 constexpr int ST_STRIDE = 36;
 constexpr size_t ST_BYTES = sizeof(float) * PG_WAVE * ST_STRIDE;
-// FP16 rows: 64 dimensions per slice, 72 halves per staged row (same bytes)
-constexpr int ST_DIMS16 = 64;
-constexpr int ST_STRIDE16 = 72;
-static_assert(sizeof(uint16_t) * ST_STRIDE16 == sizeof(float) * ST_STRIDE, "one tile serves both row types");
+// FP16 rows: SD dimensions per slice (SD / 8 lanes of 16 bytes per row), SD +
+// 8 halves per staged row.  The tile is smaller than the FP32 one, so more
+// waves fit a CU: 32-dimension slices for launches that fill the chip many
+// times over, 16 where the smaller tile lets a launch be resident at once.
+template <int SD>
+constexpr size_t st_bytes16() {
+    return sizeof(uint16_t) * PG_WAVE * (SD + 8);
+}
+static_assert(st_bytes16<32>() <= ST_BYTES, "the FP16 tile fits the FP32 one");
 
 // LDS bytes of one query's slice: query vector, pool keys, record table (RT
 // ids and distances), pool flags
@@ -105,7 +110,7 @@ __device__ __forceinline__ uint32_t record_slot(int32_t id, int bits) {
     return ((uint32_t)id * 0x9E3779B1u) >> (32 - bits);
 }
 
-template <int HW, bool H16>
+template <int HW, bool H16, int SD>
 __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int64_t ldx, int d,
                                                int64_t n, const int32_t *__restrict__ g, int R,
                                                const int32_t *__restrict__ deg,
@@ -195,15 +200,20 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
             // an exact FP16 copy of the rows: 64-dimension slices, eight
             // lanes per row each reading 16 bytes of one 128-byte line; the
             // halves stay 16-bit in the tile and are widened when summed
-            const int part = (lane & 7) * 8;
-            uint4 v[PG_WAVE / 8];
+            constexpr int ST_DIMS16 = SD, ST_STRIDE16 = SD + 8, ST_LANES16 = SD / 8;
+            constexpr int RPI = PG_WAVE / ST_LANES16;  // rows per load instruction
+            const int part = (lane % ST_LANES16) * 8;
+            int32_t rid16[PG_WAVE / RPI];
+#pragma unroll
+            for (int i = 0; i < PG_WAVE / RPI; ++i) rid16[i] = __shfl(gid, i * RPI + lane / ST_LANES16, PG_WAVE);
+            uint4 v[PG_WAVE / RPI];
             auto fetch = [&](int c) {
                 const int w = min(ST_DIMS16, d - c);
 #pragma unroll
-                for (int i = 0; i < PG_WAVE / 8; ++i) {
+                for (int i = 0; i < PG_WAVE / RPI; ++i) {
                     v[i] = make_uint4(0u, 0u, 0u, 0u);
-                    if (rid[i] >= 0 && part < w)
-                        v[i] = *reinterpret_cast<const uint4 *>(X16 + (int64_t)rid[i] * ld16 + c + part);
+                    if (rid16[i] >= 0 && part < w)
+                        v[i] = *reinterpret_cast<const uint4 *>(X16 + (int64_t)rid16[i] * ld16 + c + part);
                 }
             };
             uint16_t *tile16 = reinterpret_cast<uint16_t *>(tile);
@@ -211,8 +221,8 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
             for (int c = 0; c < d; c += ST_DIMS16) {
                 const int w = min(ST_DIMS16, d - c);
 #pragma unroll
-                for (int i = 0; i < PG_WAVE / 8; ++i)
-                    *reinterpret_cast<uint4 *>(tile16 + (i * 8 + (lane >> 3)) * ST_STRIDE16 + part) = v[i];
+                for (int i = 0; i < PG_WAVE / RPI; ++i)
+                    *reinterpret_cast<uint4 *>(tile16 + (i * RPI + lane / ST_LANES16) * ST_STRIDE16 + part) = v[i];
                 if (c + ST_DIMS16 < d) fetch(c + ST_DIMS16);
                 __builtin_amdgcn_wave_barrier();
                 for (int j = 0; j < w; j += 8) {
@@ -453,7 +463,8 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         while ((1 << rec.bits) < 2 * p->record_L) ++rec.bits;
     const int RT = rec.bits ? 1 << rec.bits : 0;
     const size_t slice = search_slice_bytes(d, p->L, RT);
-    const bool pair = R <= 32 && 2 * slice + ST_BYTES <= 65536;
+    const size_t stb = p->x16 ? st_bytes16<32>() : ST_BYTES;
+    const bool pair = R <= 32 && 2 * slice + stb <= 65536;
     if (p->x16 && ((uintptr_t)p->x16 & 15)) {
         set_error("pg_search: x16 must be 16-byte aligned");
         return PG_EINVAL;
@@ -462,18 +473,39 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
     const int64_t ld16 = ((int64_t)d + 7) & ~(int64_t)7;
     TimedLaunch tl(ctx, K_SEARCH, -1.0);
     const dim3 g2((unsigned)((nq + 1) / 2)), g1((unsigned)nq);
-    const size_t l2 = 2 * slice + ST_BYTES, l1 = slice + ST_BYTES;
+    const size_t l2 = 2 * slice + stb, l1 = slice + stb;
+    // FP16 rows: the narrower slices where they let the whole launch be
+    // resident at once and the wider ones do not
+    bool narrow = false;
+    const int64_t waves = pair ? (nq + 1) / 2 : nq;
+    if (x16 && waves > 4 * (int64_t)ctx->num_cu) {
+        const size_t nb = (pair ? 2 * slice : slice) + st_bytes16<16>();
+        int o32 = 0, o16 = 0;
+        if (pair) {
+            PG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, reinterpret_cast<const void *>(&k_search<32, true, 32>), 64, l2));
+            PG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o16, reinterpret_cast<const void *>(&k_search<32, true, 16>), 64, nb));
+        } else {
+            PG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, reinterpret_cast<const void *>(&k_search<64, true, 32>), 64, l1));
+            PG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o16, reinterpret_cast<const void *>(&k_search<64, true, 16>), 64, nb));
+        }
+        narrow = waves > (int64_t)o32 * ctx->num_cu && waves <= (int64_t)o16 * ctx->num_cu;
+    }
+    const size_t l2n = 2 * slice + st_bytes16<16>(), l1n = slice + st_bytes16<16>();
 #define PG_SEARCH_ARGS                                                                                          \
     X, ldx, d, n, g_ids, R, g_deg, Q, ldq, nq, p->entry_ids, p->n_entry, p->query_entry, p->exclude, p->k, p->L, \
         out_ids, out_d2, rec, x16, ld16
-    if (pair && x16)
-        hipLaunchKernelGGL((k_search<32, true>), g2, dim3(64), l2, ctx->stream, PG_SEARCH_ARGS);
+    if (pair && x16 && narrow)
+        hipLaunchKernelGGL((k_search<32, true, 16>), g2, dim3(64), l2n, ctx->stream, PG_SEARCH_ARGS);
+    else if (pair && x16)
+        hipLaunchKernelGGL((k_search<32, true, 32>), g2, dim3(64), l2, ctx->stream, PG_SEARCH_ARGS);
     else if (pair)
-        hipLaunchKernelGGL((k_search<32, false>), g2, dim3(64), l2, ctx->stream, PG_SEARCH_ARGS);
+        hipLaunchKernelGGL((k_search<32, false, 32>), g2, dim3(64), l2, ctx->stream, PG_SEARCH_ARGS);
+    else if (x16 && narrow)
+        hipLaunchKernelGGL((k_search<64, true, 16>), g1, dim3(64), l1n, ctx->stream, PG_SEARCH_ARGS);
     else if (x16)
-        hipLaunchKernelGGL((k_search<64, true>), g1, dim3(64), l1, ctx->stream, PG_SEARCH_ARGS);
+        hipLaunchKernelGGL((k_search<64, true, 32>), g1, dim3(64), l1, ctx->stream, PG_SEARCH_ARGS);
     else
-        hipLaunchKernelGGL((k_search<64, false>), g1, dim3(64), l1, ctx->stream, PG_SEARCH_ARGS);
+        hipLaunchKernelGGL((k_search<64, false, 32>), g1, dim3(64), l1, ctx->stream, PG_SEARCH_ARGS);
 #undef PG_SEARCH_ARGS
     PG_HIP(hipGetLastError());
     return PG_OK;
