@@ -43,7 +43,7 @@ WORKLOADS = {
     "tiny": dict(n=10_000, nq=100, d=128, K=32, R=32, S=16, iters=12, seed=0,
                  gen="uniform_int", desc="uniform-int 10kx128, K=32 R=32 FP32"),
 }
-L_LADDER = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+L_LADDER = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector and FP32 MFMA (dense)
 PEAK_HBM_GBS = 8000.0
 # HBM traffic of the join measured with rocprofv3 counters; only valid while

@@ -235,7 +235,10 @@ pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ld
 /* ------------------------------------------------------------------ */
 typedef struct {
     int32_t k;                  /* results per query, 1 <= k <= L (k < L with exclude) */
-    int32_t L;                  /* pool width, L <= 1024 */
+    int32_t L;                  /* pool width, L <= 2048; a query's LDS (4 d +
+                                   9 L bytes, plus 16 record_L with a record,
+                                   plus a 9 KB row tile) must stay within
+                                   64 KB, else PG_EUNSUPPORTED */
     int32_t n_entry;            /* number of shared entering points, >= 1 */
     const int32_t *entry_ids;   /* device, n_entry ids (repeats dropped) */
     const int32_t *query_entry; /* optional, device, nq ids: query q enters at

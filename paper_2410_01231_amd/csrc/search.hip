@@ -436,8 +436,8 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         set_error("pg_search: bad sizes n=%lld nq=%lld d=%d R=%d", (long long)n, (long long)nq, d, R);
         return PG_EINVAL;
     }
-    if (p->L < 1 || p->L > 1024 || p->k < 1 || p->k > p->L || (!p->query_entry && p->n_entry < 1)) {
-        set_error("pg_search: need 1 <= k <= L <= 1024 and n_entry >= 1 (k=%d L=%d n_entry=%d)", p->k,
+    if (p->L < 1 || p->L > 2048 || p->k < 1 || p->k > p->L || (!p->query_entry && p->n_entry < 1)) {
+        set_error("pg_search: need 1 <= k <= L <= 2048 and n_entry >= 1 (k=%d L=%d n_entry=%d)", p->k,
                   p->L, p->n_entry);
         return PG_EINVAL;
     }
@@ -464,6 +464,11 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
     const int RT = rec.bits ? 1 << rec.bits : 0;
     const size_t slice = search_slice_bytes(d, p->L, RT);
     const size_t stb = p->x16 ? st_bytes16<32>() : ST_BYTES;
+    if (slice + stb > 65536) {
+        set_error("pg_search: a query needs %zu bytes of LDS (d=%d, L=%d, record_L=%d), more than 64 KB", slice + stb,
+                  d, p->L, p->record_L);
+        return PG_EUNSUPPORTED;
+    }
     const bool pair = R <= 32 && 2 * slice + stb <= 65536;
     if (p->x16 && ((uintptr_t)p->x16 & 15)) {
         set_error("pg_search: x16 must be 16-byte aligned");

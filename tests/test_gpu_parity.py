@@ -362,6 +362,34 @@ def test_search_bit_exact(pg, oracle, datagen):
         assert np.array_equal(host(d2), rd2.astype(np.float32)), L
 
 
+def test_search_pools_above_1024_bit_exact(pg, oracle, datagen):
+    # pools of 1536 and 2048 on a 2500-node graph: the search takes in most of
+    # the graph; FP32 and FP16 rows, both query-per-wave layouts
+    X, Q = datagen.sift_like(2500, 37, d=64, n_clusters=6, sigma=14.0, seed=23)
+    cand = _exact_lists(oracle, X, 24)
+    r = oracle.refine(X, cand, 12)
+    entries = np.concatenate([[r["ep"]], r["roots"]]).astype(np.int32)
+    x16, exact = pg.half_rows(dev(X))
+    assert exact
+    for L in (1536, 2048):
+        rid, rd2, _ = oracle.search(X, r["ids"], r["deg"], Q, entries, 10, L)
+        for rows in (None, x16):
+            ids, d2 = pg.search(dev(X), dev(r["ids"]), dev(r["deg"]), dev(Q), dev(entries), 10, L, x16=rows)
+            assert np.array_equal(host(ids), rid), L
+            assert np.array_equal(host(d2), rd2.astype(np.float32)), L
+
+
+def test_search_rejects_queries_beyond_lds(pg, datagen):
+    # 8192-dimensional rows, a pool of 2048 and a record of 1024 need more
+    # than 64 KB of LDS per query: an error, before any launch
+    X, Q = datagen.sift_like(300, 3, d=8192, n_clusters=2, sigma=4.0, seed=5)
+    g = np.zeros((300, 4), np.int32)
+    deg = np.full(300, 4, np.int32)
+    rec = (dev(np.full((3, 1024), -1, np.int32)), dev(np.zeros((3, 1024), np.float32)))
+    with pytest.raises(pg.PgError, match="LDS"):
+        pg.search(dev(X), dev(g), dev(deg), dev(Q), dev(np.array([0], np.int32)), 10, 2048, record=rec)
+
+
 @pytest.mark.parametrize("R,nq", [(48, 301), (80, 129), (1, 7)])
 def test_search_wide_rows_bit_exact(pg, oracle, datagen, R, nq):
     # rows wider than 32 (one query per wave) and wider than 64 (neighbours in
