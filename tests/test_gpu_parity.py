@@ -254,6 +254,21 @@ def test_connect_alpha_graph_bit_exact(pg, oracle, datagen, R):
     assert np.array_equal(host(g["d2"]), r["d2"].astype(np.float32))
 
 
+def test_connect_alpha_graph_wide_exact_rows_bit_exact(pg, oracle, datagen):
+    # exact integer rows of 200 dimensions: the scan over F takes its
+    # distances from MFMA tiles with 13 16-dimension steps held in registers
+    X, _ = datagen.sift_like(4000, 0, d=200, n_clusters=40, sigma=20.0, seed=37)
+    cand = _exact_lists(oracle, X, 24)
+    g = pg.prune(dev(X), dev(cand), 12, alpha_deg=65.0)
+    r = oracle.refine(X, cand, 12, alpha_deg=65.0)
+    log("roots gpu", len(g["roots"]), "oracle", len(r["roots"]))
+    assert len(r["roots"]) > 100  # 265 (at R = 8 and 10 both sides report the overflow)
+    assert np.array_equal(host(g["roots"]), r["roots"])
+    assert np.array_equal(host(g["deg"]), r["deg"])
+    assert np.array_equal(host(g["ids"]), r["ids"])
+    assert np.array_equal(host(g["d2"]), r["d2"].astype(np.float32))
+
+
 def test_connect_overflow_is_reported(pg, oracle, datagen):
     # R = 2 on tight clusters: at some turn every reached node has degree R
     X, _ = datagen.sift_like(1500, 0, d=8, n_clusters=30, sigma=2.0, seed=15)
@@ -405,6 +420,28 @@ def test_search_wide_rows_bit_exact(pg, oracle, datagen, R, nq):
         rid, rd2, _ = oracle.search(X, g, deg, Q, entries, 10, L)
         assert np.array_equal(host(ids), rid), L
         assert np.array_equal(host(d2), rd2.astype(np.float32)), L
+
+
+def test_search_fp16_rows_in_large_batches_equal_fp32_rows(pg, oracle, datagen):
+    # batches of about 10k queries: the FP16 rows may be staged in 16-
+    # dimension slices (when that tile lets the whole launch be resident and
+    # the 32-dimension one does not); d = 36 leaves a ragged last slice
+    X, Q = datagen.sift_like(4000, 11000, d=36, n_clusters=10, sigma=10.0, seed=19)
+    cand = _exact_lists(oracle, X, 24)
+    r = oracle.refine(X, cand, 12)
+    entries = np.concatenate([[r["ep"]], r["roots"]]).astype(np.int32)
+    x16, exact = pg.half_rows(dev(X))
+    assert exact
+    for nq in (9000, 10000, 11000):
+        for L in (64, 192):
+            a = pg.search(dev(X), dev(r["ids"]), dev(r["deg"]), dev(Q[:nq]), dev(entries), 10, L, pool_out=True)
+            b = pg.search(dev(X), dev(r["ids"]), dev(r["deg"]), dev(Q[:nq]), dev(entries), 10, L, pool_out=True,
+                          x16=x16)
+            for x, y in zip(a, b):
+                assert torch.equal(x, y), (nq, L)
+    rid, rd2, _ = oracle.search(X, r["ids"], r["deg"], Q[:300], entries, 10, 192)
+    assert np.array_equal(host(b[0][:300]), rid)
+    assert np.array_equal(host(b[1][:300]), rd2.astype(np.float32))
 
 
 def test_search_fp16_rows_equal_fp32_rows(pg, oracle, datagen):
