@@ -484,7 +484,11 @@ __global__ void k_spill_scatter(const int32_t *__restrict__ spill_t, const uint6
 constexpr int JW = 2;            // sources (waves) per workgroup
 constexpr int JT = JW * PG_WAVE;
 constexpr int JDC = 16;          // dims per LDS chunk
-constexpr int TRW = 4, TCL = 8;  // micro-tile: 4 new members x 8 members
+constexpr int TRW = 4, TCL = 8;  // largest micro-tile: 4 new members x 8 members
+template <int R, int C>
+struct JoinTile {
+    static constexpr int rows = R, cols = C;
+};
 // float4 staging loads per lane and chunk for a join set of at most 160
 // members (3S + K with S <= 32, K <= 64)
 constexpr int JPF = (160 * (JDC / 4) + PG_WAVE - 1) / PG_WAVE;
@@ -557,10 +561,6 @@ __global__ __launch_bounds__(JT) void k_join(
     if (__ballot(anymark) == 0) return;  // a repeat pass serves none of this source's members
     __builtin_amdgcn_wave_barrier();
 
-    const int RB = (nn + TRW - 1) / TRW, CB = mp / TCL;
-    // micro-tiles (rb, cb) that hold a pair with col > row: cb >= rb / 2
-    int T = 0;
-    for (int rb = 0; rb < RB; ++rb) T += CB - (rb >> 1);
     unsigned long long local_props = 0;
     // the member row behind each of this lane's staging loads
     int32_t fid[JPF];
@@ -569,144 +569,188 @@ __global__ __launch_bounds__(JT) void k_join(
         const int e = lane + PG_WAVE * j;
         fid[j] = e < mp * (JDC / 4) ? ids[e / (JDC / 4)] : -1;
     }
-    for (int round0 = 0; round0 < T; round0 += PG_WAVE) {
-        float acc[TRW][TCL];
-        int brb = -1, bcb = 0;
-        {
-            int b = round0 + lane;
-            if (b < T) {
-                int rb = 0;
-                while (b >= CB - (rb >> 1)) {
-                    b -= CB - (rb >> 1);
-                    ++rb;
+    // micro-tiles of TR new members x TC members (TC = 2 TR) that hold a pair
+    // with col > row: cb >= rb / 2
+    auto tiles = [&](int tr, int tc) {
+        const int RB = (nn + tr - 1) / tr, CB = mp / tc;
+        int T = 0;
+        for (int rb = 0; rb < RB; ++rb) T += CB - (rb >> 1);
+        return T;
+    };
+    auto rounds = [&](auto shape) {
+        constexpr int TR = decltype(shape)::rows, TC = decltype(shape)::cols;
+        static_assert(TC == 2 * TR && TR * TC <= 32, "micro-tile shape");
+        // bit c of every row of a lane's pair mask
+        constexpr uint32_t col_bits = TR == 4 ? 0x01010101u : (TR == 2 ? 0x11u : 0x1u);
+        const int CB = mp / TC;
+        const int T = tiles(TR, TC);
+        for (int round0 = 0; round0 < T; round0 += PG_WAVE) {
+            float acc[TR][TC];
+            int brb = -1, bcb = 0;
+            {
+                int b = round0 + lane;
+                if (b < T) {
+                    int rb = 0;
+                    while (b >= CB - (rb >> 1)) {
+                        b -= CB - (rb >> 1);
+                        ++rb;
+                    }
+                    brb = rb;
+                    bcb = (rb >> 1) + b;
                 }
-                brb = rb;
-                bcb = (rb >> 1) + b;
             }
-        }
 #pragma unroll
-        for (int a = 0; a < TRW; ++a)
+            for (int a = 0; a < TR; ++a)
 #pragma unroll
-            for (int c = 0; c < TCL; ++c) acc[a][c] = 0.0f;
-        // the rows of the next chunk load while the current one is summed
-        float4 v[JPF];
-        auto fetch = [&](int c0) {
-            const int dl = min(JDC, d - c0);
+                for (int c = 0; c < TC; ++c) acc[a][c] = 0.0f;
+            // the rows of the next chunk load while the current one is summed
+            float4 v[JPF];
+            auto fetch = [&](int c0) {
+                const int dl = min(JDC, d - c0);
 #pragma unroll
-            for (int j = 0; j < JPF; ++j) {
-                const int q = (lane + PG_WAVE * j) % (JDC / 4);
-                v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (fid[j] >= 0 && 4 * q < dl)
-                    v[j] = *reinterpret_cast<const float4 *>(X + (int64_t)fid[j] * ldx + c0 + 4 * q);
+                for (int j = 0; j < JPF; ++j) {
+                    const int q = (lane + PG_WAVE * j) % (JDC / 4);
+                    v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (fid[j] >= 0 && 4 * q < dl)
+                        v[j] = *reinterpret_cast<const float4 *>(X + (int64_t)fid[j] * ldx + c0 + 4 * q);
+                }
+            };
+            fetch(0);
+            for (int c0 = 0; c0 < d; c0 += JDC) {
+                const int dl = min(JDC, d - c0);
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int j = 0; j < JPF; ++j) {
+                    const int e = lane + PG_WAVE * j;
+                    if (e < mp * (JDC / 4)) {
+                        const int q = e % (JDC / 4), i = e / (JDC / 4);
+                        tile[(4 * q + 0) * MPS + i] = v[j].x;
+                        tile[(4 * q + 1) * MPS + i] = v[j].y;
+                        tile[(4 * q + 2) * MPS + i] = v[j].z;
+                        tile[(4 * q + 3) * MPS + i] = v[j].w;
+                    }
+                }
+                if (c0 + JDC < d) fetch(c0 + JDC);
+                __builtin_amdgcn_wave_barrier();
+                if (brb >= 0) {
+                    const float *rp = tile + TR * brb;
+                    const float *cp = tile + TC * bcb;
+                    for (int k = 0; k < dl; ++k) {
+                        float rv[TR], cv[TC];
+                        if constexpr (TR == 4) {
+                            const float4 r4 = *reinterpret_cast<const float4 *>(rp + k * MPS);
+                            rv[0] = r4.x, rv[1] = r4.y, rv[2] = r4.z, rv[3] = r4.w;
+                        } else if constexpr (TR == 2) {
+                            const float2 r2 = *reinterpret_cast<const float2 *>(rp + k * MPS);
+                            rv[0] = r2.x, rv[1] = r2.y;
+                        } else {
+                            rv[0] = rp[k * MPS];
+                        }
+                        if constexpr (TC >= 4) {
+#pragma unroll
+                            for (int j = 0; j < TC; j += 4) {
+                                const float4 c4 = *reinterpret_cast<const float4 *>(cp + k * MPS + j);
+                                cv[j] = c4.x, cv[j + 1] = c4.y, cv[j + 2] = c4.z, cv[j + 3] = c4.w;
+                            }
+                        } else {
+                            const float2 c2 = *reinterpret_cast<const float2 *>(cp + k * MPS);
+                            cv[0] = c2.x, cv[1] = c2.y;
+                        }
+#pragma unroll
+                        for (int a = 0; a < TR; ++a)
+#pragma unroll
+                            for (int c = 0; c < TC; ++c) {
+                                const float t = rv[a] - cv[c];
+                                acc[a][c] = fmaf(t, t, acc[a][c]);
+                            }
+                    }
+                }
             }
-        };
-        fetch(0);
-        for (int c0 = 0; c0 < d; c0 += JDC) {
-            const int dl = min(JDC, d - c0);
+            // ---- emission: decide every pair once (bit masks), one LDS offset per
+            // (lane, member), reserve ranges per member, write
+            uint32_t to_row = 0, to_col = 0;  // bit a*8+c
+            int off_row[TR], off_col[TC];
+            if (brb >= 0) {
+#pragma unroll
+                for (int a = 0; a < TR; ++a) {
+                    const int r = TR * brb + a;
+#pragma unroll
+                    for (int c = 0; c < TC; ++c) {
+                        const int col = TC * bcb + c;
+                        if (r >= nn || col >= m || (col < nn && col <= r)) continue;
+                        const float d2 = acc[a][c];
+                        const uint64_t kw = pack_key(d2, ids[col]), kv = pack_key(d2, ids[r]);
+                        // a repeat pass (mark != null) skips keys already listed, so
+                        // every repeat inserts at least one new key into each node it serves
+                        if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
+                            to_row |= 1u << (a * TC + c);
+                        if (mk[col] && kv < kth[col] && !(mark && list_has(keys + (int64_t)ids[col] * K, K, kv)))
+                            to_col |= 1u << (a * TC + c);
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < TR; ++a) {
+                    const int c_r = __popc((to_row >> (a * TC)) & ((1u << TC) - 1u));
+                    off_row[a] = c_r ? atomicAdd(&cnt[TR * brb + a], c_r) : 0;
+                }
+#pragma unroll
+                for (int c = 0; c < TC; ++c) {
+                    const int c_c = __popc(to_col & (col_bits << c));
+                    off_col[c] = c_c ? atomicAdd(&cnt[TC * bcb + c], c_c) : 0;
+                }
+            }
             __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int j = 0; j < JPF; ++j) {
-                const int e = lane + PG_WAVE * j;
-                if (e < mp * (JDC / 4)) {
-                    const int q = e % (JDC / 4), i = e / (JDC / 4);
-                    tile[(4 * q + 0) * MPS + i] = v[j].x;
-                    tile[(4 * q + 1) * MPS + i] = v[j].y;
-                    tile[(4 * q + 2) * MPS + i] = v[j].z;
-                    tile[(4 * q + 3) * MPS + i] = v[j].w;
-                }
-            }
-            if (c0 + JDC < d) fetch(c0 + JDC);
+            local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
             __builtin_amdgcn_wave_barrier();
             if (brb >= 0) {
-                const float *rp = tile + TRW * brb;
-                const float *cp = tile + TCL * bcb;
-                for (int k = 0; k < dl; ++k) {
-                    const float4 r4 = *reinterpret_cast<const float4 *>(rp + k * MPS);
-                    const float4 ca = *reinterpret_cast<const float4 *>(cp + k * MPS);
-                    const float4 cb = *reinterpret_cast<const float4 *>(cp + k * MPS + 4);
-                    const float rv[TRW] = {r4.x, r4.y, r4.z, r4.w};
-                    const float cv[TCL] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
-                    for (int a = 0; a < TRW; ++a)
+                for (int a = 0; a < TR; ++a) {
+                    const int r = TR * brb + a;
 #pragma unroll
-                        for (int c = 0; c < TCL; ++c) {
-                            const float t = rv[a] - cv[c];
-                            acc[a][c] = fmaf(t, t, acc[a][c]);
+                    for (int c = 0; c < TC; ++c) {
+                        const int col = TC * bcb + c;
+                        const uint32_t bit = 1u << (a * TC + c);
+                        if (!((to_row | to_col) & bit)) continue;
+                        const float d2 = acc[a][c];
+                        if (to_row & bit) {
+                            const int32_t v = ids[r];
+                            const int slot = base[r] + off_row[a]++;
+                            const uint64_t kw = pack_key(d2, ids[col]);
+                            if (slot < B)
+                                bucket[(int64_t)v * B + slot] = kw;
+                            else
+                                spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k,
+                                          seg_end, ovf_next, cslot);
                         }
-                }
-            }
-        }
-        // ---- emission: decide every pair once (bit masks), one LDS offset per
-        // (lane, member), reserve ranges per member, write
-        uint32_t to_row = 0, to_col = 0;  // bit a*8+c
-        int off_row[TRW], off_col[TCL];
-        if (brb >= 0) {
-#pragma unroll
-            for (int a = 0; a < TRW; ++a) {
-                const int r = TRW * brb + a;
-#pragma unroll
-                for (int c = 0; c < TCL; ++c) {
-                    const int col = TCL * bcb + c;
-                    if (r >= nn || col >= m || (col < nn && col <= r)) continue;
-                    const float d2 = acc[a][c];
-                    const uint64_t kw = pack_key(d2, ids[col]), kv = pack_key(d2, ids[r]);
-                    // a repeat pass (mark != null) skips keys already listed, so
-                    // every repeat inserts at least one new key into each node it serves
-                    if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
-                        to_row |= 1u << (a * TCL + c);
-                    if (mk[col] && kv < kth[col] && !(mark && list_has(keys + (int64_t)ids[col] * K, K, kv)))
-                        to_col |= 1u << (a * TCL + c);
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < TRW; ++a) {
-                const int c_r = __popc((to_row >> (a * TCL)) & 0xFFu);
-                off_row[a] = c_r ? atomicAdd(&cnt[TRW * brb + a], c_r) : 0;
-            }
-#pragma unroll
-            for (int c = 0; c < TCL; ++c) {
-                const int c_c = __popc(to_col & (0x01010101u << c));
-                off_col[c] = c_c ? atomicAdd(&cnt[TCL * bcb + c], c_c) : 0;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
-        __builtin_amdgcn_wave_barrier();
-        if (brb >= 0) {
-#pragma unroll
-            for (int a = 0; a < TRW; ++a) {
-                const int r = TRW * brb + a;
-#pragma unroll
-                for (int c = 0; c < TCL; ++c) {
-                    const int col = TCL * bcb + c;
-                    const uint32_t bit = 1u << (a * TCL + c);
-                    if (!((to_row | to_col) & bit)) continue;
-                    const float d2 = acc[a][c];
-                    if (to_row & bit) {
-                        const int32_t v = ids[r];
-                        const int slot = base[r] + off_row[a]++;
-                        const uint64_t kw = pack_key(d2, ids[col]);
-                        if (slot < B)
-                            bucket[(int64_t)v * B + slot] = kw;
-                        else
-                            spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k,
-                                      seg_end, ovf_next, cslot);
-                    }
-                    if (to_col & bit) {
-                        const int32_t w = ids[col];
-                        const int slot = base[col] + off_col[c]++;
-                        const uint64_t kv = pack_key(d2, ids[r]);
-                        if (slot < B)
-                            bucket[(int64_t)w * B + slot] = kv;
-                        else
-                            spill_put(w, kv, sbase[col] + (slot - max(base[col], B)), spill_t, spill_k,
-                                      seg_end, ovf_next, cslot);
+                        if (to_col & bit) {
+                            const int32_t w = ids[col];
+                            const int slot = base[col] + off_col[c]++;
+                            const uint64_t kv = pack_key(d2, ids[r]);
+                            if (slot < B)
+                                bucket[(int64_t)w * B + slot] = kv;
+                            else
+                                spill_put(w, kv, sbase[col] + (slot - max(base[col], B)), spill_t, spill_k,
+                                          seg_end, ovf_next, cslot);
+                        }
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-    }
+    };
+    // Every lane takes one micro-tile per round, and a round costs its wave the
+    // full dimension loop whatever the number of busy lanes.  Small join sets
+    // (few new members) leave most lanes idle with 4 x 8 tiles; 2 x 4 and 1 x 2
+    // tiles spread the same pairs over more lanes.  The smallest shape that
+    // needs no more rounds than 4 x 8 is taken (the rows are staged once per
+    // round).
+    const int r48 = (tiles(4, 8) + PG_WAVE - 1) / PG_WAVE;
+    if ((tiles(1, 2) + PG_WAVE - 1) / PG_WAVE <= r48)
+        rounds(JoinTile<1, 2>{});
+    else if ((tiles(2, 4) + PG_WAVE - 1) / PG_WAVE <= r48)
+        rounds(JoinTile<2, 4>{});
+    else
+        rounds(JoinTile<4, 8>{});
     // one atomic per wave
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) {
