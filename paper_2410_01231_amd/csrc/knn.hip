@@ -510,10 +510,11 @@ static size_t join_lds_bytes(int maxm) { return JW * join_wave_lds(maxm); }
 
 // Local join, one wave per source u.  The join set (new members first, then
 // old) is staged dim-major in the wave's LDS region, tile[k][i] = x_i[c0 + k],
-// JDC dims at a time: a lane's 8 consecutive members at one dim are two
-// conflict-free 16-byte reads and its 4 new members one (shared by the lanes
-// of the same row block).  The pair set is covered by micro-tiles of 4 new
-// members x 8 members, one per lane per round; every pair's squared distance
+// JDC dims at a time: with 4 x 8 micro-tiles a lane's 8 consecutive members
+// at one dim are two conflict-free 16-byte reads and its 4 new members one
+// (shared by the lanes of the same row block).  The pair set is covered by
+// micro-tiles of 4 x 8, 2 x 4 or 1 x 2 (new members x members, the smallest
+// shape that needs no more rounds), one per lane per round; every pair's squared distance
 // accumulates in registers in the canonical order (dims ascending, one fma
 // per dim).  Proposals are counted per (lane, member), ranges are reserved
 // per member in the node's bucket (then the spill list), and written.
