@@ -206,24 +206,26 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
             int32_t rid16[PG_WAVE / RPI];
 #pragma unroll
             for (int i = 0; i < PG_WAVE / RPI; ++i) rid16[i] = __shfl(gid, i * RPI + lane / ST_LANES16, PG_WAVE);
-            uint4 v[PG_WAVE / RPI];
-            auto fetch = [&](int c) {
+            constexpr int NV = PG_WAVE / RPI;
+            // two slices in flight: va and vb alternate, each refilled two
+            // slices ahead as soon as it is in the tile
+            uint4 va[NV], vb[NV];
+            auto fetch = [&](uint4 (&v)[NV], int c) {
                 const int w = min(ST_DIMS16, d - c);
 #pragma unroll
-                for (int i = 0; i < PG_WAVE / RPI; ++i) {
+                for (int i = 0; i < NV; ++i) {
                     v[i] = make_uint4(0u, 0u, 0u, 0u);
                     if (rid16[i] >= 0 && part < w)
                         v[i] = *reinterpret_cast<const uint4 *>(X16 + (int64_t)rid16[i] * ld16 + c + part);
                 }
             };
             uint16_t *tile16 = reinterpret_cast<uint16_t *>(tile);
-            fetch(0);
-            for (int c = 0; c < d; c += ST_DIMS16) {
+            auto slice = [&](uint4 (&v)[NV], int c) {
                 const int w = min(ST_DIMS16, d - c);
 #pragma unroll
-                for (int i = 0; i < PG_WAVE / RPI; ++i)
+                for (int i = 0; i < NV; ++i)
                     *reinterpret_cast<uint4 *>(tile16 + (i * RPI + lane / ST_LANES16) * ST_STRIDE16 + part) = v[i];
-                if (c + ST_DIMS16 < d) fetch(c + ST_DIMS16);
+                if (c + 2 * ST_DIMS16 < d) fetch(v, c + 2 * ST_DIMS16);
                 __builtin_amdgcn_wave_barrier();
                 for (int j = 0; j < w; j += 8) {
                     const uint4 hx = *reinterpret_cast<const uint4 *>(tile16 + lane * ST_STRIDE16 + j);
@@ -240,6 +242,12 @@ __global__ __launch_bounds__(64) void k_search(const float *__restrict__ X, int6
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
+            };
+            fetch(va, 0);
+            if (ST_DIMS16 < d) fetch(vb, ST_DIMS16);
+            for (int c = 0; c < d; c += 2 * ST_DIMS16) {
+                slice(va, c);
+                if (c + ST_DIMS16 < d) slice(vb, c + ST_DIMS16);
             }
         } else {
             const int part = (lane & 7) * 4;
