@@ -91,7 +91,11 @@ __global__ __launch_bounds__(NSTRIPE) void k_counters_clear(unsigned long long *
 // ---------------------------------------------------------------------------
 // init: K distinct random neighbours, hash4(seed, 0, u, attempt) mod (n-1)
 // ---------------------------------------------------------------------------
+// Rows come from X, or, when X16 is given (an exact FP16 copy, rows of d16
+// halves), from the copy at half the bytes: the values, and so the chains,
+// are the same.
 __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64_t ldx, int d,
+                                              const _Float16 *__restrict__ X16, int d16,
                                               int64_t n, int K, uint64_t seed,
                                               uint64_t *__restrict__ keys,
                                               uint64_t *__restrict__ newm,
@@ -135,7 +139,17 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
             const int r = v / vpr, c = (v - r * vpr) * 4;
             const int64_t rid = r < PG_WAVE ? (r < K ? (int64_t)acc[r] : -1) : u;
             float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (rid >= 0) x = *reinterpret_cast<const float4 *>(X + rid * ldx + c0 + c);
+            if (rid >= 0) {
+                if (X16) {
+                    const uint2 h = *reinterpret_cast<const uint2 *>(X16 + rid * d16 + c0 + c);
+                    x = make_float4((float)__builtin_bit_cast(_Float16, (uint16_t)(h.x & 0xffffu)),
+                                    (float)__builtin_bit_cast(_Float16, (uint16_t)(h.x >> 16)),
+                                    (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y & 0xffffu)),
+                                    (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y >> 16)));
+                } else {
+                    x = *reinterpret_cast<const float4 *>(X + rid * ldx + c0 + c);
+                }
+            }
             *reinterpret_cast<float4 *>(rs + r * IST + c) = x;
         }
         __builtin_amdgcn_wave_barrier();
@@ -1652,12 +1666,6 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
 
     PG_HIP(hipMemsetAsync(pcnt, 0, sizeof(int32_t) * n, st));
     PG_HIP(hipMemsetAsync(mark_next, 0, n, st));
-    {
-        TimedLaunch tl(ctx, K_INIT, (double)n * K * (8.0 + 4.0 * d));
-        hipLaunchKernelGGL(k_init, dim3(wave_blocks), dim3(256), 0, st, X, ldx, d, n, K, p->seed,
-                           keys, newm, insm);
-        PG_HIP(hipGetLastError());
-    }
     // ---- a1: precision prep and exactness test; choose the join path
     _Float16 *xh = (_Float16 *)(w + L.x16);
     __bf16 *xb = (__bf16 *)(w + L.x16);
@@ -1717,6 +1725,14 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
                 mx.sqd = sqrtf((float)d);
             }
         }
+    }
+    // ---- a2: init (rows from the exact FP16 copy where the join uses it)
+    {
+        TimedLaunch tl(ctx, K_INIT, (double)n * K * (8.0 + 4.0 * d));
+        const _Float16 *x16i = path == PG_JOIN_MFMA_FP16 ? xh : nullptr;
+        hipLaunchKernelGGL(k_init, dim3(wave_blocks), dim3(256), 0, st, X, ldx, d, x16i, L.d16, n, K, p->seed,
+                           keys, newm, insm);
+        PG_HIP(hipGetLastError());
     }
     if (stats) stats->join_path = path;
     // ---- locality order of the join sources (nearest of P pivot rows)
