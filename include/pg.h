@@ -56,13 +56,15 @@ typedef enum {
 /* Arithmetic of the NN-Descent distance tiles.  Every list entry holds the
  * FP32 direct-form distance (the canonical chain: s = fmaf(x_i - y_i,
  * x_i - y_i, s) over i ascending), whatever the tiles compute in.
- *   PG_FP32: on data where it is provably exact (integer values, squared
- *     norms <= 2^23) the tiles run as FP32 MFMA norm expansions, otherwise as
+ *   PG_FP32: on data where it is provably exact (integer values with
+ *     squared norms <= 2^23 and no negative value, or squared norms <= 2^22,
+ *     so that every squared distance is an integer <= 2^24) the tiles run as
+ *     FP32 MFMA norm expansions, otherwise as
  *     the direct form on the vector ALUs.  PG_FP32_VALU: always the direct
  *     form.
  *   PG_FP16 / PG_BF16: 16-bit MFMA tiles with FP32 accumulation.  On integer
- *     data where they are exact (|x| <= 2048 for FP16, <= 256 for BF16,
- *     squared norms <= 2^23) they give the distances directly.  Otherwise
+ *     data where they are exact (|x| <= 2048 for FP16, <= 256 for BF16, and
+ *     the norm condition of PG_FP32) they give the distances directly.  Otherwise
  *     (mixed precision) the tiles run on the mean-centred data and only
  *     prefilter: every pair whose estimate lies within the error bound
  *     (see margin_rel) of the cut of either end is recomputed in the direct
@@ -205,7 +207,12 @@ pg_status pg_prune_workspace(const pg_prune_params *p, int64_t n, int32_t d, int
  * NULL the distances are computed here.  Results are the same either way.
  *
  * Stage PRUNE: N(u) <- Prune(u, C(u), R) for every u (Alg. 3 and, for
- * alpha > 60, the alpha test of Section 4.1).  Stage REVERSE:
+ * alpha > 60, the alpha test of Section 4.1).  The alpha test is the law of
+ * cosines on the squared distances a = d2(u,w), b = d2(v,w), c = d2(u,v):
+ * w occludes v when (a + b) - c < kappa * sqrt(a * b), kappa = 2 cos(alpha)
+ * (0 at 90 degrees), decided as that expression evaluates in IEEE double from
+ * the FP32 distances (an FP32 evaluation decides when it is provably the
+ * same; otherwise the double one runs).  Stage REVERSE:
  * N(u) <- Prune(u, N(u) U {v : u in N(v)}, R), every node reading the PRUNE
  * result.  Entry point: the node closest to the centroid of X (argmin of
  * (d2, id); centroid summed in double).  Stage CONNECT: with ep as the start,
@@ -215,7 +222,8 @@ pg_status pg_prune_workspace(const pg_prune_params *p, int64_t n, int32_t d, int
  * nodes; then everything r reaches counts as reached.  Extra edges are
  * appended after the pruned ones.
  *
- * When X holds integers with |x| <= 2048 and squared norms <= 2^23 (tested
+ * When X holds integers with |x| <= 2048 and squared norms <= 2^23 with no
+ * negative value, or <= 2^22 (tested
  * on the device), the pairwise distances of PRUNE (given cand_d2) and
  * REVERSE come from FP16 MFMA Gram tiles, which are exact there.
  *

@@ -24,14 +24,50 @@ constexpr int PRG = 16;          // rows per register group
 constexpr int PDC = 64;          // dims per chunk
 constexpr int PSTR = PDC + 4;    // LDS row stride
 
-__device__ __forceinline__ bool occludes(float a, float b, float c, int strict, int use_angle,
-                                         float kappa) {
+// The alpha test of Section 4.1.  With a = d2(u,w), b = d2(v,w), c = d2(u,v)
+// the law of cosines gives  angle(u w v) > alpha  <=>  a + b - c < kappa sqrt(a b),
+// kappa = 2 cos(alpha).  The decision is defined as that inequality evaluated
+// in IEEE double from the three FP32 squared distances, in this order:
+// t = (a + b) - c, r = kappa_d * sqrt(a * b), with kappa_d the double value of
+// 2 cos(alpha) (0 exactly at 90 degrees).  The kernels first evaluate it in
+// FP32.  Each of t and r is then within 4 ulp-units of (a + b + c) of its
+// double value (t: two roundings of sums of nonnegative terms; r: the
+// product, a square root within 2 ulp, kappa rounded to FP32 and the final
+// product, with |r| <= a + b), and the double evaluation is within 2^-50 of
+// the same scale of the real one, so outside the band
+// |t - r| > 2^-20 (a + b + c) the FP32 answer is the double answer.  Inside
+// the band, and whenever a b leaves the normal FP32 range, the double
+// evaluation decides.  Where the distances are exact (integer data) both
+// sides of a comparison with a double-precision reference therefore take the
+// same decision.
+struct AngleTest {
+    int on;      // alpha > 60: the test applies (at or below 60 it is implied)
+    float kf;    // kappa rounded to FP32
+    double kd;   // kappa in double
+};
+
+__device__ __noinline__ bool angle_in_band(float a, float b, float c, double kd) {
+    return ((double)a + (double)b - (double)c) < kd * sqrt((double)a * (double)b);
+}
+
+__device__ __forceinline__ bool angle_exceeds(float a, float b, float c, const AngleTest &at) {
+    const float p = a * b;
+    const float t = (a + b) - c;
+    const float r = at.kf * sqrtf(p);
+    const float band = 0x1p-20f * ((a + b) + c);
+    const bool normal = p >= 0x1p-120f && p <= 0x1p120f;
+    if (normal && t < r - band) return true;
+    if (normal && t > r + band) return false;
+    return angle_in_band(a, b, c, at.kd);
+}
+
+__device__ __forceinline__ bool occludes(float a, float b, float c, int strict, const AngleTest &at) {
     // w (a = d2(u,w)) visited before v (c = d2(u,v)); b = d2(v,w)
     if (!(b < c)) return false;
     if (strict && !(a < c)) return false;
-    if (!use_angle) return true;
+    if (!at.on) return true;
     if (b == 0.0f) return true;
-    return (a + b - c) < kappa * sqrtf(a * b);
+    return angle_exceeds(a, b, c, at);
 }
 
 // Distances to u come from src1_d2 / src2_d2 when given (they must be the
@@ -40,7 +76,7 @@ __global__ __launch_bounds__(64) void k_prune(
     const float *__restrict__ X, int64_t ldx, int d, int64_t n, const int32_t *__restrict__ src1,
     const float *__restrict__ src1_d2, int C1, const int32_t *__restrict__ src1_deg,
     const int64_t *__restrict__ src2_off, const int32_t *__restrict__ src2, const float *__restrict__ src2_d2,
-    int R, float kappa, int use_angle, int strict,
+    int R, AngleTest at, int strict,
     const float *__restrict__ tab, int32_t *__restrict__ out_ids, float *__restrict__ out_d2,
     int32_t *__restrict__ out_deg) {
     __shared__ __align__(16) float rows[PRG * PSTR];
@@ -159,7 +195,7 @@ __global__ __launch_bounds__(64) void k_prune(
                         const int rp = is_kept ? kept_pos[row] : chunk_pos[ci];
                         b = tu[(int64_t)(rp + 1) * (C1 + 1) + (tpos + 1)];
                     }
-                    const bool cnd = occludes(a, b, myc, strict, use_angle, kappa);
+                    const bool cnd = occludes(a, b, myc, strict, at);
                     if (is_kept)
                         occk |= cnd;
                     else if (cnd)
@@ -197,14 +233,17 @@ __global__ __launch_bounds__(64) void k_prune(
 }
 
 // ---------------------------------------------------------------------------
-// Exact 16-bit path.  For integer-valued X with |x| <= 2048 and squared norms
-// <= 2^23, FP16 holds every coordinate exactly and every product and partial
-// sum of a dot product is an integer below 2^24, so with FP32 accumulation
-// d2(v, w) = n_v + n_w - 2 v.w equals the canonical chain bit for bit.  The
-// prune then takes the pairwise distances of a round from 32 x 32 MFMA Gram
-// tiles over rows staged once in LDS.
+// Exact 16-bit path.  For integer-valued X with |x| <= 2048, FP16 holds every
+// coordinate exactly.  With squared norms <= 2^23 every product and partial
+// sum of a dot product is an integer of magnitude at most 2^23; the squared
+// distance is at most 2^24 when no coordinate is negative (then v.w >= 0 and
+// d2 <= n_v + n_w), or when every squared norm is at most 2^22.  Under either
+// condition, with FP32 accumulation, d2(v, w) = n_v + n_w - 2 v.w equals the
+// canonical chain bit for bit (every partial sum of the chain is an integer
+// <= 2^24).  The prune then takes the pairwise distances of a round from
+// 32 x 32 MFMA Gram tiles over rows staged once in LDS.
 // ---------------------------------------------------------------------------
-enum { PX_NONINT = 0, PX_MAXABS = 1, PX_MAXNORM = 2 };
+enum { PX_NONINT = 0, PX_MAXABS = 1, PX_MAXNORM = 2, PX_NEG = 3 };
 
 typedef float pm_f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 pm_f16x8 __attribute__((ext_vector_type(8)));
@@ -215,9 +254,9 @@ typedef _Float16 pm_f16x8 __attribute__((ext_vector_type(8)));
 __global__ __launch_bounds__(256) void k_prune_prep(const float *__restrict__ X, int64_t ldx, int d, int d16,
                                                     int64_t n, _Float16 *__restrict__ x16,
                                                     float *__restrict__ norms, unsigned int *__restrict__ ex) {
-    __shared__ unsigned int red[4][3];
+    __shared__ unsigned int red[4][4];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    bool nonint = false;
+    bool nonint = false, neg = false;
     float mabs = 0.f, mnorm = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < n; i += (int64_t)gridDim.x * 4) {
         const float *x = X + i * ldx;
@@ -225,6 +264,7 @@ __global__ __launch_bounds__(256) void k_prune_prep(const float *__restrict__ X,
         for (int k = lane; k < d16; k += PG_WAVE) {
             const float v = k < d ? x[k] : 0.f;
             nonint |= (v != rintf(v));
+            neg |= v < 0.f;
             mabs = fmaxf(mabs, fabsf(v));
             s = fmaf(v, v, s);
             x16[i * d16 + k] = (_Float16)v;
@@ -235,24 +275,28 @@ __global__ __launch_bounds__(256) void k_prune_prep(const float *__restrict__ X,
         mnorm = fmaxf(mnorm, s);
     }
     const unsigned int ni = __ballot(nonint) != 0 ? 1u : 0u;
+    const unsigned int ng = __ballot(neg) != 0 ? 1u : 0u;
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, o, PG_WAVE));
     if (lane == 0) {
         red[wv][0] = ni;
         red[wv][1] = __float_as_uint(mabs);
         red[wv][2] = __float_as_uint(mnorm);
+        red[wv][3] = ng;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned int a = 0, b = 0, c = 0;
+        unsigned int a = 0, b = 0, c = 0, e = 0;
         for (int w = 0; w < 4; ++w) {
             a |= red[w][0];
             b = max(b, red[w][1]);
             c = max(c, red[w][2]);
+            e |= red[w][3];
         }
         if (a) atomicOr(&ex[PX_NONINT], 1u);
         atomicMax(&ex[PX_MAXABS], b);
         atomicMax(&ex[PX_MAXNORM], c);
+        if (e) atomicOr(&ex[PX_NEG], 1u);
     }
 }
 
@@ -270,7 +314,7 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
     const _Float16 *__restrict__ X16, int d16, const float *__restrict__ norms, int64_t n,
     const int32_t *__restrict__ src1, const float *__restrict__ src1_d2, int C1,
     const int32_t *__restrict__ src1_deg, const int64_t *__restrict__ src2_off,
-    const int32_t *__restrict__ src2, const float *__restrict__ src2_d2, int R, float kappa, int use_angle,
+    const int32_t *__restrict__ src2, const float *__restrict__ src2_d2, int R, AngleTest at,
     int strict, int32_t *__restrict__ out_ids, float *__restrict__ out_d2, int32_t *__restrict__ out_deg) {
     __shared__ __align__(16) _Float16 rows[PM_ROWS * PM_RS];
     __shared__ uint64_t kept_key[PG_WAVE];
@@ -386,7 +430,7 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
                     bool cnd = false;
                     if (i < cm && j < cm && i < j) {
                         const float b = fmaxf(fmaf(-2.0f, t[g], cn[i] + nj), 0.0f);
-                        cnd = occludes(key_d2(chunk_key[i]), b, cj, strict, use_angle, kappa);
+                        cnd = occludes(key_d2(chunk_key[i]), b, cj, strict, at);
                     }
                     const uint64_t bm = __ballot(cnd);
                     const int i0 = 32 * rb + 8 * (g / 4) + (g % 4);
@@ -427,7 +471,7 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
                     bool cnd = false;
                     if (k < nk && j < cm) {
                         const float b = fmaxf(fmaf(-2.0f, t[g], kn[k] + nj), 0.0f);
-                        cnd = occludes(key_d2(kept_key[k]), b, cj, strict, use_angle, kappa);
+                        cnd = occludes(key_d2(kept_key[k]), b, cj, strict, at);
                     }
                     const uint64_t bm = __ballot(cnd);
                     occk |= ((bm & 0xFFFFFFFFull) | (bm >> 32)) << (32 * cb);
@@ -1486,9 +1530,13 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
     double *cpart = (double *)(w + L.cpart), *cen = (double *)(w + L.cen), *apd = (double *)(w + L.apd);
     hipStream_t st = ctx->stream;
     const int R = p->R;
-    const bool use_angle = p->alpha_deg > 60.0f;
-    const double a = (double)p->alpha_deg;
-    const float kappa = (a == 90.0) ? 0.0f : (float)(2.0 * cos(a * (M_PI / 180.0)));
+    AngleTest at;
+    {
+        const double a = (double)p->alpha_deg;
+        at.on = p->alpha_deg > 60.0f;
+        at.kd = (a == 90.0) ? 0.0 : 2.0 * cos(a * (M_PI / 180.0));
+        at.kf = (float)at.kd;
+    }
     const bool rev_stage = (p->stages & PG_STAGE_REVERSE) != 0;
 
     // exactness test of the 16-bit MFMA path (needs the distances to u given)
@@ -1507,7 +1555,8 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         float maxabs, maxnorm;
         memcpy(&maxabs, &he[PX_MAXABS], 4);
         memcpy(&maxnorm, &he[PX_MAXNORM], 4);
-        exact16 = he[PX_NONINT] == 0 && maxabs <= 2048.0f && maxnorm <= 8388608.0f;
+        exact16 = he[PX_NONINT] == 0 && maxabs <= 2048.0f &&
+                  (maxnorm <= 4194304.0f || (he[PX_NEG] == 0 && maxnorm <= 8388608.0f));
     }
     int32_t *s_ids = rev_stage ? p_ids : g_ids, *s_deg = rev_stage ? p_deg : g_deg;
     float *s_d2 = rev_stage ? p_d2 : g_d2;
@@ -1516,12 +1565,12 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         if (exact16 && cand_d2)
             hipLaunchKernelGGL(k_prune_mfma, dim3((unsigned)n), dim3(64), 0, st, x16, L.d16, nrm, n, cand_ids,
                                cand_d2, C, (const int32_t *)nullptr, (const int64_t *)nullptr,
-                               (const int32_t *)nullptr, (const float *)nullptr, R, kappa, (int)use_angle,
+                               (const int32_t *)nullptr, (const float *)nullptr, R, at,
                                p->strict_ties, s_ids, s_d2, s_deg);
         else
             hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, cand_ids, cand_d2, C,
                                (const int32_t *)nullptr, (const int64_t *)nullptr, (const int32_t *)nullptr,
-                               (const float *)nullptr, R, kappa, (int)use_angle, p->strict_ties, p->pair_d2,
+                               (const float *)nullptr, R, at, p->strict_ties, p->pair_d2,
                                s_ids, s_d2, s_deg);
         PG_HIP(hipGetLastError());
     }
@@ -1539,11 +1588,11 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         TimedLaunch tl(ctx, K_PRUNE, -1.0);
         if (exact16)
             hipLaunchKernelGGL(k_prune_mfma, dim3((unsigned)n), dim3(64), 0, st, x16, L.d16, nrm, n, p_ids, p_d2, R,
-                               p_deg, off, rev, rev_d2, R, kappa, (int)use_angle, p->strict_ties, g_ids, g_d2,
+                               p_deg, off, rev, rev_d2, R, at, p->strict_ties, g_ids, g_d2,
                                g_deg);
         else
             hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, p_ids, p_d2, R, p_deg,
-                               off, rev, rev_d2, R, kappa, (int)use_angle, p->strict_ties, (const float *)nullptr,
+                               off, rev, rev_d2, R, at, p->strict_ties, (const float *)nullptr,
                                g_ids, g_d2, g_deg);
         PG_HIP(hipGetLastError());
     }

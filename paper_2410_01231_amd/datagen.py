@@ -6,6 +6,9 @@ the HIP path and the oracle may be fed from it.  The paper's datasets (Table
 generators stand in for them:
 
 * ``uniform_int``  i.i.d. integers in [0, 255] stored as float32 (tiny case).
+* ``int_grid``     i.i.d. integers in [lo, hi] stored as float32 (small ranges
+                   give many equal distances and exact right angles; negative
+                   ranges give signed data).
 * ``sift_like``    mixture of Gaussian clusters with centres uniform in
                    [0, 255]^d and per-dimension sigma, rounded and clipped to
                    [0, 255] (SIFT-shaped, 128-d).
@@ -29,6 +32,11 @@ def _rng(seed: int, sub: int) -> np.random.Generator:
 def uniform_int(n: int, d: int, seed: int) -> np.ndarray:
     """floor(256 * U[0,1)) per coordinate, as float32."""
     return np.floor(_rng(seed, 0).random((n, d)) * 256.0).astype(np.float32)
+
+
+def int_grid(n: int, d: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Integers uniform in [lo, hi] per coordinate, as float32."""
+    return _rng(seed, 0).integers(lo, hi + 1, size=(n, d)).astype(np.float32)
 
 
 def _mixture_labels(rng, n, n_clusters):

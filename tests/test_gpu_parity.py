@@ -352,16 +352,96 @@ def test_prune_table_hook_float_bit_exact(pg, oracle, datagen):
     assert np.array_equal(host(g["ids"]), r_ids)
 
 
-def test_prune_alpha_float_decisions(pg, oracle, datagen):
-    # alpha > 60: the angle test is decided in float32 on the GPU and in double
-    # in the oracle; rows may differ only through a near-threshold decision
-    X = datagen.uniform_int(800, 16, seed=12)
-    cand = _exact_lists(oracle, X, 24)
-    g = pg.prune(dev(X), dev(cand), 12, alpha_deg=67.0, stages=pg.STAGE_PRUNE)
-    r = oracle.refine(X, cand, 12, alpha_deg=67.0, stages=oracle.STAGE_PRUNE)
-    same = (host(g["ids"]) == r["ids"]).all(1)
-    log("alpha rows identical", same.mean())
-    assert same.mean() > 0.995
+ALPHAS = [62.0, 65.0, 67.0, 89.0, 90.0, 120.0]
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+@pytest.mark.parametrize("data", ["uniform", "grid"])
+def test_prune_alpha_bit_exact(pg, oracle, datagen, alpha, data):
+    # alpha > 60 on integer data: the distances are exact on both sides and
+    # the GPU decides the angle test as the double-precision expression the
+    # oracle evaluates (FP32 only outside a proven band), so every row is
+    # identical.  The grid data (values 0..3) are full of equal distances and
+    # exact right and 120-degree angles, where decisions sit on the threshold.
+    # Both prune kernels: canonical chains (no candidate distances given) and
+    # the exact FP16 Gram path (given), PRUNE then REVERSE.
+    if data == "uniform":
+        X = datagen.uniform_int(800, 16, seed=12)
+    else:
+        X = datagen.int_grid(900, 8, 0, 3, seed=13)
+    n = len(X)
+    cand, cd2 = oracle.exact_knn(X, X, 24, exclude=np.arange(n, dtype=np.int32))
+    st_g = pg.STAGE_PRUNE | pg.STAGE_REVERSE
+    r1 = oracle.refine(X, cand, 12, alpha_deg=alpha, stages=oracle.STAGE_PRUNE)
+    r2 = oracle.refine(X, cand, 12, alpha_deg=alpha, stages=oracle.STAGE_PRUNE | oracle.STAGE_REVERSE)
+    for given in (None, cd2.astype(np.float32)):
+        kw = {} if given is None else {"cand_d2": dev(given)}
+        g1 = pg.prune(dev(X), dev(cand), 12, alpha_deg=alpha, stages=pg.STAGE_PRUNE, **kw)
+        g2 = pg.prune(dev(X), dev(cand), 12, alpha_deg=alpha, stages=st_g, **kw)
+        log("alpha", alpha, data, "given" if given is not None else "computed",
+            "rows identical", (host(g1["ids"]) == r1["ids"]).all(1).mean(),
+            (host(g2["ids"]) == r2["ids"]).all(1).mean())
+        assert np.array_equal(host(g1["ids"]), r1["ids"])
+        assert np.array_equal(host(g1["deg"]), r1["deg"])
+        assert np.array_equal(host(g2["ids"]), r2["ids"])
+        assert np.array_equal(host(g2["deg"]), r2["deg"])
+        assert np.array_equal(host(g2["d2"]), r2["d2"].astype(np.float32))
+
+
+def test_prune_alpha_table_hook_bit_exact(pg, oracle, datagen):
+    # identical candidate lists and identical float32 distances (the table
+    # hook) on float data: the alpha decisions are the same double-precision
+    # evaluation on both sides, so the edge sets are identical
+    X, _ = datagen.unit_mixture(400, 0, d=16, n_clusters=5, seed=16)
+    C = 20
+    cand = datagen.random_candidates(400, C, seed=16)
+    for u in range(400):
+        row = np.unique(cand[u][cand[u] != u])
+        extra = np.setdiff1d(np.arange(400), np.append(row, u))[: C - len(row)]
+        cand[u] = np.concatenate([row, extra])[:C]
+    pos = np.concatenate([np.arange(400)[:, None], cand], 1)
+    P = X.astype(np.float64)[pos]
+    tab = ((P[:, :, None, :] - P[:, None, :, :]) ** 2).sum(-1).astype(np.float32)
+    for alpha in ALPHAS:
+        g = pg.prune(dev(X), dev(cand), 8, alpha_deg=alpha, stages=pg.STAGE_PRUNE, pair_d2=dev(tab))
+        r_ids, r_d2, r_deg = oracle.prune_table(cand, tab, 8, alpha_deg=alpha)
+        assert np.array_equal(host(g["deg"]), r_deg), alpha
+        assert np.array_equal(host(g["ids"]), r_ids), alpha
+
+
+@pytest.mark.parametrize("lo,hi,d", [(-512, 511, 16), (-2048, 2047, 4), (-3, 3, 8)])
+def test_signed_integer_paths_identical(pg, oracle, datagen, lo, hi, d):
+    # signed integer data: the MFMA norm expansion is exact only while every
+    # squared distance stays at or below 2^24.  (-512, 511) in 16 dims passes
+    # the test (norms <= 2^22) and takes the MFMA paths; (-2048, 2047) in
+    # 4 dims reaches distances near 2^26, where FP32 sums round, and must
+    # keep the direct form (the FP16 request then runs the mixed path).
+    # Every precision gives the same lists and graph; where every distance is
+    # exact they are also the oracle's.
+    X = datagen.int_grid(1200, d, lo, hi, seed=lo & 0xFFFF)
+    K, S, T, R = 16, 8, 5, 10
+    exact = hi < 2047
+    if exact:
+        ro, rd2, _, _ = oracle.nndescent(X, K, S, T, 5, stop_updates=-1)
+        rg = oracle.refine(X, ro, R)
+    res = {}
+    for prec in (pg.FP32_VALU, pg.FP32, pg.FP16):
+        ids, d2, st = pg.knn_build(dev(X), K, S=S, max_iters=T, seed=5, stop_updates=-1, precision=prec)
+        g = pg.prune(dev(X), ids, R, cand_d2=d2)
+        log("signed", lo, hi, d, "precision", prec, "path", st["join_path"])
+        res[prec] = (host(ids), host(d2), host(g["ids"]), host(g["roots"]), st["join_path"])
+        if exact:
+            assert np.array_equal(res[prec][0], ro), prec
+            assert np.array_equal(res[prec][1], rd2.astype(np.float32)), prec
+            assert np.array_equal(res[prec][2], rg["ids"]), prec
+            assert np.array_equal(res[prec][3], rg["roots"]), prec
+    for prec in (pg.FP32, pg.FP16):
+        for a, b in zip(res[prec][:4], res[pg.FP32_VALU][:4]):
+            assert np.array_equal(a, b), prec
+    if exact:
+        assert res[pg.FP32][4] == "fp32-mfma" and res[pg.FP16][4] == "fp16-mfma"
+    else:
+        assert res[pg.FP32][4] == "fp32-valu" and res[pg.FP16][4] == "fp16-mixed"
 
 
 # ---------------------------------------------------------------- search
