@@ -778,12 +778,25 @@ __global__ __launch_bounds__(JT) void k_join(
 // ---------------------------------------------------------------------------
 // Stage and precision prep: 16-bit copies, canonical norms, exactness test.
 // For integer-valued data with every squared norm <= 2^23, each product and
-// every partial sum of a dot product is an integer below 2^24, so the MFMA
-// norm expansion n_x + n_y - 2 x.y (FP32 accumulation, any summation order)
-// equals the canonical chain distance exactly.  The test needs |x| <= 2048
-// for FP16 operands and |x| <= 256 for BF16 operands to be exact.
+// every partial sum of a dot product is an integer of magnitude at most 2^23,
+// and the norms add exactly.  The squared distance itself must also stay at
+// or below 2^24 for the single rounding of n_x + n_y - 2 x.y and the partial
+// sums of the chain to be exact: it is at most n_x + n_y <= 2^24 when no
+// coordinate is negative (x.y >= 0), and at most (|x| + |y|)^2 <= 2^24 when
+// every squared norm is at most 2^22.  So the MFMA norm expansion (FP32
+// accumulation, any summation order) equals the canonical chain distance
+// exactly when the values are integers and either no value is negative and
+// the squared norms are <= 2^23, or the squared norms are <= 2^22.  FP16
+// operands further need |x| <= 2048 and BF16 operands |x| <= 256.
 // ---------------------------------------------------------------------------
-enum { EX_NONINT = 0, EX_MAXABS = 1, EX_MAXNORM = 2 };
+enum { EX_NONINT = 0, EX_MAXABS = 1, EX_MAXNORM = 2, EX_NEG = 3 };
+
+// The exactness test above, from the flags of k_prep.
+static inline bool exact_integer_rows(const unsigned int he[4]) {
+    float maxnorm;
+    memcpy(&maxnorm, &he[EX_MAXNORM], 4);
+    return he[EX_NONINT] == 0 && (maxnorm <= 4194304.0f || (he[EX_NEG] == 0 && maxnorm <= 8388608.0f));
+}
 
 // Grid-stride over rows, one wave per row.  The norm is a lane-parallel tree
 // sum: it is only used where the data pass the exactness test, and there
@@ -793,9 +806,9 @@ __global__ __launch_bounds__(256) void k_prep(const float *__restrict__ X, int64
                                               int64_t n, int mode, _Float16 *__restrict__ xh,
                                               __bf16 *__restrict__ xb, float *__restrict__ norms,
                                               unsigned int *__restrict__ ex) {
-    __shared__ unsigned int red[4][3];
+    __shared__ unsigned int red[4][4];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
-    bool nonint = false;
+    bool nonint = false, neg = false;
     float mabs = 0.f, mnorm = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < n; i += (int64_t)gridDim.x * 4) {
         const float *x = X + i * ldx;
@@ -803,6 +816,7 @@ __global__ __launch_bounds__(256) void k_prep(const float *__restrict__ X, int64
         for (int k = lane; k < d16; k += PG_WAVE) {
             const float v = k < d ? x[k] : 0.f;
             nonint |= (v != rintf(v));
+            neg |= v < 0.f;
             mabs = fmaxf(mabs, fabsf(v));
             s = fmaf(v, v, s);
             if (mode == PG_FP16) xh[i * d16 + k] = (_Float16)v;
@@ -814,24 +828,28 @@ __global__ __launch_bounds__(256) void k_prep(const float *__restrict__ X, int64
         mnorm = fmaxf(mnorm, s);
     }
     const unsigned int ni = __ballot(nonint) != 0 ? 1u : 0u;
+    const unsigned int ng = __ballot(neg) != 0 ? 1u : 0u;
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, o, PG_WAVE));
     if (lane == 0) {
         red[wv][0] = ni;
         red[wv][1] = __float_as_uint(mabs);
         red[wv][2] = __float_as_uint(mnorm);
+        red[wv][3] = ng;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned int a = 0, b = 0, c = 0;
+        unsigned int a = 0, b = 0, c = 0, e = 0;
         for (int w = 0; w < 4; ++w) {
             a |= red[w][0];
             b = max(b, red[w][1]);
             c = max(c, red[w][2]);
+            e |= red[w][3];
         }
         if (a) atomicOr(&ex[EX_NONINT], 1u);
         atomicMax(&ex[EX_MAXABS], b);
         atomicMax(&ex[EX_MAXNORM], c);
+        if (e) atomicOr(&ex[EX_NEG], 1u);
     }
 }
 
@@ -1682,10 +1700,9 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         unsigned int he[4];
         PG_HIP(hipMemcpyAsync(he, exf, sizeof(he), hipMemcpyDeviceToHost, st));
         PG_HIP(hipStreamSynchronize(st));
-        float maxabs, maxnorm;
+        float maxabs;
         memcpy(&maxabs, &he[EX_MAXABS], 4);
-        memcpy(&maxnorm, &he[EX_MAXNORM], 4);
-        const bool ints = he[EX_NONINT] == 0 && maxnorm <= 8388608.0f;
+        const bool ints = exact_integer_rows(he);
         if (p->precision == PG_FP32 && ints) path = PG_JOIN_MFMA_FP32;
         MixedParams none{};
         mx = none;
