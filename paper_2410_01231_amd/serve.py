@@ -10,7 +10,13 @@ and the graphs kept resident; builds start in arrival order, and a query
 whose collection is built may start ahead of builds still waiting for
 memory.  A request larger than the whole budget is rejected.  A build keeps
 its collection's rows and graph resident (counted in the ledger) until
-release().  Results do not depend on what else runs: every kernel of the
+release().  Queries of one collection share its library context, so they
+run one at a time: a query is not admitted while another query of the same
+collection runs, and holds no slot or memory while it waits.  A query for a
+collection whose build failed, that was released or that was never
+submitted fails at once; queries still queued when their build fails or
+their collection is released fail then, and close() fails whatever can no
+longer run.  Results do not depend on what else runs: every kernel of the
 library is deterministic, so a collection's graph and a query's results are
 the same alone and in the mix.
 """
@@ -66,6 +72,11 @@ class AdmissionError(RuntimeError):
     pass
 
 
+class CollectionError(RuntimeError):
+    """A query names a collection with no graph to answer it: its build
+    failed, it was released, or it was never submitted."""
+
+
 @dataclass
 class _Request:
     kind: str                # "build" or "query"
@@ -98,7 +109,10 @@ class Server:
         self._running = 0
         self._resident: dict[str, int] = {}
         self._graphs: dict[str, object] = {}
-        self._job_locks: dict[str, threading.Lock] = {}
+        # collection state: "building" (build submitted, no graph yet), "ready",
+        # "failed" or "released"; absent = never submitted
+        self._state: dict[str, str] = {}
+        self._querying: set[str] = set()   # collections with a query running
         self.peak_in_use = 0
         self.admission_log: list[str] = []
         self._closed = False
@@ -115,13 +129,19 @@ class Server:
         return self._enqueue("query", batch, fp, 0)
 
     def release(self, job_id: str) -> None:
-        """Drop a collection's resident graph and give its bytes back."""
+        """Drop a collection's resident graph and give its bytes back; its
+        queued queries fail.  A collection still building is dropped when its
+        build ends."""
         with self._cv:
             self._graphs.pop(job_id, None)
             self._in_use -= self._resident.pop(job_id, 0)
+            if job_id in self._state:
+                self._state[job_id] = "released"
+            self._fail_queued(job_id, f"collection {job_id!r} was released")
             self._cv.notify_all()
 
     def close(self) -> None:
+        """Stop taking requests, run what can still run, fail the rest."""
         with self._cv:
             self._closed = True
             self._cv.notify_all()
@@ -138,14 +158,49 @@ class Server:
                 f"{kind} request needs {req.footprint} bytes, more than the budget of {self.budget}"))
             return fut
         with self._cv:
+            if self._closed:
+                fut.set_exception(AdmissionError("the server is closed"))
+                return fut
+            job_id = payload.job_id
+            if kind == "build":
+                if self._state.get(job_id) in ("building", "ready"):
+                    fut.set_exception(AdmissionError(f"collection {job_id!r} is already built or building"))
+                    return fut
+                self._state[job_id] = "building"
+            else:
+                st = self._state.get(job_id)
+                if st not in ("building", "ready"):
+                    why = "was never submitted" if st is None else ("failed to build" if st == "failed"
+                                                                    else "was released")
+                    fut.set_exception(CollectionError(f"collection {job_id!r} {why}"))
+                    return fut
             self._queue.append(req)
             self._cv.notify_all()
         return fut
+
+    def _fail_queued(self, job_id, why) -> None:
+        """Fail the queued queries of a collection (caller holds the lock)."""
+        keep = collections.deque()
+        for r in self._queue:
+            if r.kind == "query" and r.payload.job_id == job_id:
+                r.timing.finished = time.perf_counter()
+                r.future.set_exception(CollectionError(why))
+            else:
+                keep.append(r)
+        self._queue = keep
+
+    def _runnable(self, r: _Request) -> bool:
+        """A queued request can still start some day."""
+        return r.kind == "build" or self._state.get(r.payload.job_id) in ("building", "ready")
 
     def _dispatch(self) -> None:
         while True:
             with self._cv:
                 while True:
+                    if self._closed:
+                        dead = [r for r in self._queue if not self._runnable(r)]
+                        for r in dead:
+                            self._fail_queued(r.payload.job_id, f"collection {r.payload.job_id!r} has no graph")
                     if self._closed and not self._queue and self._running == 0:
                         return
                     i = self._pick() if self._running < self._slots else None
@@ -156,6 +211,8 @@ class Server:
                     self._cv.wait(timeout=0.05)
                 self._in_use += head.footprint
                 self._running += 1
+                if head.kind == "query":
+                    self._querying.add(head.payload.job_id)
                 self.peak_in_use = max(self.peak_in_use, self._in_use)
                 name = head.payload.job_id
                 self.admission_log.append(f"{head.kind}:{name}")
@@ -164,7 +221,8 @@ class Server:
     def _pick(self):
         """Index of the next request to start: builds in arrival order (a build
         that does not fit holds back the later ones), queries as soon as their
-        collection is built and they fit, ahead of waiting builds."""
+        collection is built, no other query of it runs and they fit, ahead of
+        waiting builds."""
         build_blocked = False
         for i, r in enumerate(self._queue):
             fits = self._in_use + r.footprint <= self.budget
@@ -179,8 +237,10 @@ class Server:
         return None
 
     def _ready(self, req: _Request) -> bool:
-        # a query waits for its collection's graph
-        return req.kind != "query" or req.payload.job_id in self._graphs
+        # a query waits for its collection's graph and for the collection's
+        # running query (they share one library context)
+        return req.kind != "query" or (req.payload.job_id in self._graphs and
+                                       req.payload.job_id not in self._querying)
 
     def _execute(self, req: _Request) -> None:
         req.timing.started = time.perf_counter()
@@ -188,26 +248,35 @@ class Server:
             if req.kind == "build":
                 graph = self._runner("build", req.payload, None)
                 with self._cv:
-                    self._graphs[req.payload.job_id] = graph
-                    self._job_locks.setdefault(req.payload.job_id, threading.Lock())
-                    self._resident[req.payload.job_id] = req.resident
-                    self._in_use += req.resident
+                    # a collection released while it was building keeps nothing
+                    if self._state.get(req.payload.job_id) != "released":
+                        self._graphs[req.payload.job_id] = graph
+                        self._state[req.payload.job_id] = "ready"
+                        self._resident[req.payload.job_id] = req.resident
+                        self._in_use += req.resident
                 result = graph
             else:
                 with self._cv:
-                    graph = self._graphs[req.payload.job_id]
-                    lock = self._job_locks[req.payload.job_id]
-                with lock:  # one query at a time per collection context
-                    result = self._runner("query", req.payload, graph)
+                    graph = self._graphs.get(req.payload.job_id)
+                if graph is None:
+                    raise CollectionError(f"collection {req.payload.job_id!r} was released")
+                result = self._runner("query", req.payload, graph)
             req.timing.finished = time.perf_counter()
             req.future.set_result((result, req.timing))
         except BaseException as e:  # the request fails, the server goes on
             req.timing.finished = time.perf_counter()
+            if req.kind == "build":
+                with self._cv:
+                    self._state[req.payload.job_id] = "failed"
+                    self._fail_queued(req.payload.job_id,
+                                      f"collection {req.payload.job_id!r} failed to build: {e}")
             req.future.set_exception(e)
         finally:
             with self._cv:
                 self._in_use -= req.footprint
                 self._running -= 1
+                if req.kind == "query":
+                    self._querying.discard(req.payload.job_id)
                 self._cv.notify_all()
 
     # --------------------------------------------------------------- GPU side

@@ -8,7 +8,7 @@ import time
 import numpy as np
 import pytest
 
-from paper_2410_01231_amd.serve import AdmissionError, BuildJob, QueryBatch, Server
+from paper_2410_01231_amd.serve import AdmissionError, BuildJob, CollectionError, QueryBatch, Server
 
 
 class Fake:
@@ -97,4 +97,86 @@ def test_failing_request_does_not_stop_the_server():
     f.gates["A"].set()
     (g, timing) = srv.submit_build(job("A")).result(timeout=5)
     assert g == {"graph_of": "A"} and timing.latency >= timing.service >= 0
+    srv.close()
+
+
+def test_query_after_failed_build_fails():
+    f = Fake({"bad": (10, 0)})
+    srv = Server(100, workers=2, runner=f.runner, footprint=f.footprint)
+    fbad = srv.submit_build(job("bad"))
+    fq = srv.submit_query(QueryBatch("bad", np.zeros((2, 4), np.float32)))   # queued before the failure
+    with pytest.raises(ValueError):
+        fbad.result(timeout=5)
+    with pytest.raises(CollectionError):
+        fq.result(timeout=5)
+    with pytest.raises(CollectionError):                                      # submitted after it
+        srv.submit_query(QueryBatch("bad", np.zeros((2, 4), np.float32))).result(timeout=5)
+    srv.close()
+
+
+def test_query_for_unknown_or_released_collection_fails():
+    f = Fake({"A": (10, 5)})
+    srv = Server(100, workers=2, runner=f.runner, footprint=f.footprint)
+    with pytest.raises(CollectionError, match="never submitted"):
+        srv.submit_query(QueryBatch("nope", np.zeros((1, 4), np.float32))).result(timeout=5)
+    fa = srv.submit_build(job("A"))
+    fq = srv.submit_query(QueryBatch("A", np.zeros((1, 4), np.float32)))
+    srv.release("A")                                                          # before the graph exists
+    with pytest.raises(CollectionError, match="released"):
+        fq.result(timeout=5)
+    f.gates["A"].set()
+    fa.result(timeout=5)
+    srv.release("A")
+    with pytest.raises(CollectionError, match="released"):
+        srv.submit_query(QueryBatch("A", np.zeros((1, 4), np.float32))).result(timeout=5)
+    srv.close()
+    assert srv._in_use == 0
+
+
+def test_close_with_pending_queries_returns():
+    f = Fake({"A": (10, 0), "B": (10, 0)})
+    srv = Server(100, workers=2, runner=f.runner, footprint=f.footprint)
+    fa = srv.submit_build(job("A"))
+    qs = [srv.submit_query(QueryBatch("A", np.zeros((1, 4), np.float32))) for _ in range(3)]
+    closer = threading.Thread(target=srv.close)
+    closer.start()
+    time.sleep(0.1)
+    f.gates["A"].set()                         # the build and its queries can still run
+    closer.join(timeout=5)
+    assert not closer.is_alive()
+    fa.result(timeout=1)
+    for q in qs:
+        assert q.result(timeout=1)[0] == ("answer", "A", "A")
+    with pytest.raises(AdmissionError):
+        srv.submit_build(job("B")).result(timeout=1)
+
+
+def test_queries_of_one_collection_wait_outside_admission():
+    # a second query of a collection whose query runs takes no slot: a query
+    # of another collection starts beside it
+    started = threading.Event()
+    release_q = threading.Event()
+    order = []
+
+    def runner(kind, payload, graph):
+        if kind == "build":
+            return {"graph_of": payload.job_id}
+        order.append(payload.job_id)
+        if payload.job_id == "A" and not started.is_set():
+            started.set()
+            assert release_q.wait(5)
+        return payload.job_id
+
+    srv = Server(100, workers=2, runner=runner, footprint=lambda k, p: (1, 0))
+    srv.submit_build(job("A")).result(timeout=5)
+    srv.submit_build(job("B")).result(timeout=5)
+    q1 = srv.submit_query(QueryBatch("A", np.zeros((1, 4), np.float32)))
+    assert started.wait(5)
+    q2 = srv.submit_query(QueryBatch("A", np.zeros((1, 4), np.float32)))
+    q3 = srv.submit_query(QueryBatch("B", np.zeros((1, 4), np.float32)))
+    assert q3.result(timeout=5)[0] == "B"      # B ran while A's second query waited
+    assert not q2.done()
+    release_q.set()
+    assert q1.result(timeout=5)[0] == "A" and q2.result(timeout=5)[0] == "A"
+    assert order == ["A", "B", "A"]
     srv.close()
