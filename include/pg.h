@@ -170,6 +170,23 @@ pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_
                        const pg_knn_params *p, void *ws, size_t ws_bytes,
                        int32_t *knn_ids, float *knn_d2, pg_knn_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pg_knn_build
+ * with its workspace taken from a static device array of PG_NOALLOC_WS_BYTES
+ * that the library holds on each device it runs on, until the process ends.
+ * Results are those of pg_knn_build with the same arguments.  Builds whose
+ * workspace (pg_knn_build_workspace) exceeds PG_NOALLOC_WS_BYTES fail with
+ * PG_ENOMEM before any work is enqueued: at K = 32, S = 16 that is up to
+ * n = 39,488 rows with PG_FP32 (fewer with PG_FP16 / PG_BF16, which also keep
+ * a 16-bit copy of X there: 36,710 rows at d = 128, 27,160 at d = 768).  The call allocates nothing (no hipMalloc / hipFree).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (several host threads, or several streams in flight) race and
+ * corrupt each other's results, so the caller must serialise them. */
+#define PG_NOALLOC_WS_BYTES ((size_t)128 << 20)
+pg_status pg_knn_build_noalloc(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                               const pg_knn_params *p, int32_t *knn_ids, float *knn_d2,
+                               pg_knn_stats *stats);
+
 /* Brute-force k nearest neighbours of each query row among the rows of X
  * (k-ANN problem statement of Section 2, solved exactly).  Q is nq x d with
  * leading dimension ldq.  exclude (optional, nq ints) names a row of X to skip

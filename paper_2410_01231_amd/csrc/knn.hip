@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "pg_common.h"
@@ -1640,26 +1641,29 @@ static pg_status knn_exact_lists(pg_ctx *ctx, const float *X, int64_t n, int32_t
     return PG_OK;
 }
 
-extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
-                                  const pg_knn_params *p, void *ws, size_t ws_bytes,
-                                  int32_t *knn_ids, float *knn_d2, pg_knn_stats *stats) {
+static pg_status check_build_args(const char *who, pg_ctx *ctx, const float *X, int64_t n, int32_t d,
+                                  int64_t ldx, const pg_knn_params *p, int32_t *knn_ids, float *knn_d2) {
     if (!ctx || !X || !knn_ids || !knn_d2) {
-        set_error("pg_knn_build: NULL argument");
+        set_error("%s: NULL argument", who);
         return PG_EINVAL;
     }
     PG_TRY(check_knn(p, n, d));
     if (ldx < d || ldx % 4 || ((uintptr_t)X & 15)) {
-        set_error("pg_knn_build: ldx must be >= d and a multiple of 4, X 16-byte aligned");
+        set_error("%s: ldx must be >= d and a multiple of 4, X 16-byte aligned", who);
         return PG_EUNSUPPORTED;
     }
+    return PG_OK;
+}
+
+// The build itself, arguments already checked.  ws holds at least
+// knn_layout(p, n, d).total bytes of any content: everything that must start
+// at zero is cleared on the stream here.  Nothing is allocated.
+static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                               const pg_knn_params *p, void *ws, int32_t *knn_ids, float *knn_d2,
+                               pg_knn_stats *stats) {
     if (stats) memset(stats, 0, sizeof(*stats));
     if (p->exact) return knn_exact_lists(ctx, X, n, d, ldx, p->K, knn_ids, knn_d2);
     const KnnLayout L = knn_layout(p, n, d);
-    if (!ws || ws_bytes < L.total) {
-        set_error("pg_knn_build: workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
-                  L.total);
-        return PG_ENOMEM;
-    }
     char *w = (char *)ws;
     uint64_t *keys = (uint64_t *)(w + L.keys), *newm = (uint64_t *)(w + L.newm),
              *insm = (uint64_t *)(w + L.insm);
@@ -1805,7 +1809,10 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         // so later (larger) passes emit fewer proposals; c grows with the
         // proposals of the previous iteration.  The passes never change the
         // result.
-        std::vector<int> rbnd{0};
+        // at most 8 boundaries: r, r, 2r, 4r, ... covering 64 residues
+        int rbnd[2 + PG_PASS_PERIOD];
+        int nb = 0;
+        rbnd[nb++] = 0;
         {
             int64_t c0;
             if (prev_props < 0)
@@ -1818,12 +1825,12 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
             bool first = true;
             while (at < PG_PASS_PERIOD) {
                 at = std::min(PG_PASS_PERIOD, at + sz);
-                rbnd.push_back(at);
+                rbnd[nb++] = at;
                 if (!first) sz *= 2;
                 first = false;
             }
         }
-        for (size_t ci = 0; ci + 1 < rbnd.size(); ++ci) {
+        for (int ci = 0; ci + 1 < nb; ++ci) {
             PassRange pr;
             pr.lo = rbnd[ci];
             pr.w = rbnd[ci + 1] - rbnd[ci];
@@ -1938,4 +1945,76 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
     PG_HIP(hipGetLastError());
     PG_HIP(hipStreamSynchronize(st));
     return PG_OK;
+}
+
+extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                  const pg_knn_params *p, void *ws, size_t ws_bytes,
+                                  int32_t *knn_ids, float *knn_d2, pg_knn_stats *stats) {
+    PG_TRY(check_build_args("pg_knn_build", ctx, X, n, d, ldx, p, knn_ids, knn_d2));
+    if (!p->exact) {
+        const size_t need = knn_layout(p, n, d).total;
+        if (!ws || ws_bytes < need) {
+            set_error("pg_knn_build: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+            return PG_ENOMEM;
+        }
+    }
+    return knn_build_run(ctx, X, n, d, ldx, p, ws, knn_ids, knn_d2, stats);
+}
+
+// ---------------------------------------------------------------------------
+// pg_knn_build_noalloc: the same build with its workspace in a file-scope
+// device array, for callers that cannot allocate device memory.  Each device
+// the library runs on holds its own copy of the array until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and only that address is ever handed to kernels or copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PG_NOALLOC_WS_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static pg_status scratch_of(int device, void **out) {
+    if (device < 0 || device >= MAX_DEVICES) {
+        set_error("pg_knn_build_noalloc: device %d beyond the %d this library tracks", device, MAX_DEVICES);
+        return PG_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        PG_HIP(hipGetDevice(&cur));
+        if (cur != device) PG_HIP(hipSetDevice(device));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) PG_HIP(hipSetDevice(cur));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) {
+            set_error("pg_knn_build_noalloc: hipGetSymbolAddress returned no address");
+            return PG_EDEVICE;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return PG_OK;
+}
+
+extern "C" pg_status pg_knn_build_noalloc(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                          const pg_knn_params *p, int32_t *knn_ids, float *knn_d2,
+                                          pg_knn_stats *stats) {
+    PG_TRY(check_build_args("pg_knn_build_noalloc", ctx, X, n, d, ldx, p, knn_ids, knn_d2));
+    void *ws = nullptr;
+    if (!p->exact) {
+        const size_t need = knn_layout(p, n, d).total;
+        if (need > (size_t)PG_NOALLOC_WS_BYTES) {
+            set_error("pg_knn_build_noalloc: n=%lld, d=%d, K=%d needs %zu workspace bytes, more than the "
+                      "%zu of the static scratch; use pg_knn_build with a caller workspace",
+                      (long long)n, d, p->K, need, (size_t)PG_NOALLOC_WS_BYTES);
+            return PG_ENOMEM;
+        }
+        PG_TRY(scratch_of(ctx->device, &ws));
+    }
+    return knn_build_run(ctx, X, n, d, ldx, p, ws, knn_ids, knn_d2, stats);
 }

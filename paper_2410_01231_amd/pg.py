@@ -57,7 +57,7 @@ class SearchParams(ctypes.Structure):
 EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
            "pg_ctx_kernel_time", "pg_ctx_reset_timing", "pg_knn_build_workspace", "pg_knn_build",
            "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search", "pg_hnsw_levels",
-           "pg_half_rows"]
+           "pg_half_rows", "pg_knn_build_noalloc"]
 
 _lib = None
 
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     lib.pg_knn_build_workspace.argtypes = [POINTER(KnnParams), c_int64, c_int32, POINTER(c_size_t)]
     lib.pg_knn_build.argtypes = [P, P, c_int64, c_int32, c_int64, POINTER(KnnParams), P, c_size_t,
                                  P, P, POINTER(KnnStats)]
+    lib.pg_knn_build_noalloc.argtypes = [P, P, c_int64, c_int32, c_int64, POINTER(KnnParams), P, P,
+                                         POINTER(KnnStats)]
     lib.pg_exact_knn.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int64, c_int64, P, c_int32,
                                  P, P]
     lib.pg_prune_workspace.argtypes = [POINTER(PruneParams), c_int64, c_int32, c_int32,
@@ -219,6 +221,44 @@ def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001
              "members": list(st.members[:it]),
              "retries": st.retries,
              "spilled": st.spilled, "join_path": JOIN_PATHS.get(st.join_path, st.join_path)}
+    return ids, d2, stats
+
+
+NOALLOC_WS_BYTES = 128 << 20  # PG_NOALLOC_WS_BYTES of include/pg.h
+
+
+def knn_build_noalloc(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001,
+                      bucket_cap=0, chunks=0, precision=FP32, margin_rel=0.0, out=None, ctx=None):
+    """knn_build through pg_knn_build_noalloc: the library's static device
+    scratch serves as the workspace (no workspace tensor is made).  out
+    (optional pair of n x K int32 / float32 device tensors) receives the lists;
+    returns (ids, d2, stats dict)."""
+    lib = load_library()
+    X = _dev_f32(X, "X")
+    n, d = X.shape
+    S = (K + 1) // 2 if S is None else S
+    if stop_updates is None:
+        stop_updates = int(delta * n * K)
+    p = KnnParams(K=K, S=S, max_iters=max_iters, exact=0, stop_updates=stop_updates,
+                  seed=seed & (2**64 - 1), precision=precision, margin_rel=float(margin_rel),
+                  bucket_cap=bucket_cap, chunks=chunks)
+    if out is None:
+        ids = torch.empty((n, K), dtype=torch.int32, device=X.device)
+        d2 = torch.empty((n, K), dtype=torch.float32, device=X.device)
+    else:
+        ids, d2 = out
+        if ids.dtype != torch.int32 or d2.dtype != torch.float32 or tuple(ids.shape) != (n, K) \
+                or tuple(d2.shape) != (n, K) or not ids.is_contiguous() or not d2.is_contiguous():
+            raise ValueError("out must be contiguous n x K int32 and float32 tensors")
+    st = KnnStats()
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_knn_build_noalloc(ctx.handle, _ptr(X), n, d, X.stride(0), ctypes.byref(p), _ptr(ids),
+                                    _ptr(d2), ctypes.byref(st)), "pg_knn_build_noalloc")
+    it = st.iters_run
+    stats = {"iters": it, "updates": list(st.updates[:it]), "pairs": list(st.pairs[:it]),
+             "proposals": list(st.proposals[:it]), "rechecked": list(st.rechecked[:it]),
+             "members": list(st.members[:it]), "retries": st.retries, "spilled": st.spilled,
+             "join_path": JOIN_PATHS.get(st.join_path, st.join_path)}
     return ids, d2, stats
 
 
