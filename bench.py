@@ -3,15 +3,28 @@
 One step = one pass of the whole hot path over the resident input: the
 NN-Descent kNN lists, prune, reverse re-prune, entry point and connect (the
 graph build), then beam search of the query batch.  Inputs are in HBM before
-the timed region starts.  The beam width L is the smallest one on a fixed
-ladder whose search recall@10 reaches 0.95 (measured once, before timing,
-against GPU brute-force ground truth).
+the timed region starts.
 
-Prints ONE JSON line.  `value` is build throughput in points/s over the timed
-steps (search time included in the step).  `roofline` reports the join
-kernel (the dominant one) from HIP events on the library's stream.
-`cpu_baseline` times the FP64 oracle on a bounded sample of the same
-workload on the host cores.
+The default run is the suite: the GIST-shaped 1M x 960 set is the headline
+(plain FP32 against FP16-MFMA tiles with FP32 recheck, timed over --steps),
+then the Deep-shaped 10M x 96 set (FP32 against BF16), the SIFT-shaped
+1M x 128 set (FP32 against FP16) and the tiny 10k x 128 set as legs timed
+over min(--steps, --leg-steps).  --workload NAME runs one set alone.
+
+Search entering points: Alg. 1 enters at the single point ep.  The recall
+ladder is reported for {ep} alone, for ep plus a seeded uniform sample of E
+ids (E = 256, 1024, 4096; the same ids for every path), and for ep plus
+every connect root.  Each ladder stops at the smallest L whose recall@10
+reaches 0.95 (measured once, before timing, against GPU brute force); the
+timed search takes, among the sets that reached it, the one that evaluates
+the fewest distances per query (entries + L R at most).
+
+Prints ONE JSON line.  `value` is the headline set's build throughput in
+points/s over the timed steps (search included in the step) on its fastest
+path that reaches the recall target.  `roofline` reports the join kernel (the
+dominant one) from HIP events on the library's stream.  `cpu_baseline` times
+the FP64 oracle on a bounded sample of the headline set on the host cores,
+with a one-core run of the whole tiny set beside it.
 """
 from __future__ import annotations
 
@@ -27,37 +40,44 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+SUITE = ["gist1m", "deep10m", "sift1m", "tiny"]  # headline first
+ENTRY_SAMPLES = [256, 1024, 4096]
 WORKLOADS = {
     # SIFT-shaped: 1M x 128, 100 Gaussian clusters (sigma 20) rounded to [0,255]
-    "sift1m": dict(n=1_000_000, nq=10_000, d=128, K=64, R=32, S=32, iters=12, seed=2,
+    "sift1m": dict(n=1_000_000, nq=10_000, d=128, K=64, R=32, S=32, iters=12, seed=2, paths="fp32,fp16",
+                   cpu_sample=100_000,
                    gen="sift_like", desc="sift-like 1Mx128 mixture-of-100, K=64 R=32 FP32"),
     # GIST-shaped precision mode: 1M x 960 float data (Gamma(2, 0.05) + 50 offsets);
     # the FP16 path is the mixed one (16-bit tiles prefilter, FP32 recheck)
-    "gist1m": dict(n=1_000_000, nq=1_000, d=960, K=64, R=32, S=32, iters=12, seed=3,
+    "gist1m": dict(n=1_000_000, nq=1_000, d=960, K=64, R=32, S=32, iters=12, seed=3, paths="fp32,fp16",
+                   cpu_sample=10_000,
                    gen="gist_like", desc="gist-like 1Mx960 Gamma(2,0.05)+50 offsets, K=64 R=32 FP32 storage"),
     # Deep-shaped: 10M x 96 unit vectors, 1000 Gaussian clusters; BF16 tiles with
     # FP32 recheck against plain FP32
-    "deep10m": dict(n=10_000_000, nq=10_000, d=96, K=64, R=32, S=32, iters=12, seed=4,
+    "deep10m": dict(n=10_000_000, nq=10_000, d=96, K=64, R=32, S=32, iters=12, seed=4, paths="fp32,bf16",
+                    cpu_sample=50_000,
                     gen="unit_mixture", desc="deep-like 10Mx96 unit mixture-of-1000, K=64 R=32 FP32 storage"),
     # tiny: 10k x 128 integers
-    "tiny": dict(n=10_000, nq=100, d=128, K=32, R=32, S=16, iters=12, seed=0,
+    "tiny": dict(n=10_000, nq=100, d=128, K=32, R=32, S=16, iters=12, seed=0, paths="fp32",
+                 cpu_sample=10_000,
                  gen="uniform_int", desc="uniform-int 10kx128, K=32 R=32 FP32"),
 }
 L_LADDER = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector and FP32 MFMA (dense)
+PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 MFMA
 PEAK_HBM_GBS = 8000.0
 # HBM traffic of the join measured with rocprofv3 counters; only valid while
 # the join source is the one the counters were taken on (sha256 recorded)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_join_sift1m.md")
 JOIN_SOURCE = os.path.join(ROOT, "paper_2410_01231_amd", "csrc", "knn.hip")
 
 
-def measured_traffic(path_name):
-    """HBM bytes per join launch for this path from the counter summary, or None."""
+def measured_traffic(path_name, workload):
+    """HBM bytes per join launch for this path from the counter summary of the
+    workload (profiles/traffic_join_<workload>.md), or None."""
     import hashlib
     import re
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(ROOT, "profiles", f"traffic_join_{workload}.md")).read()
         sha = hashlib.sha256(open(JOIN_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -81,11 +101,24 @@ def roofline(join_path, work, launches, total_ms, name, workload):
     achieved = per_launch / (avg_ms / 1000.0) / scale if launches else 0.0
     return {"kernel": "join", "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak,
-            # counters were taken on the sift-like workload only
-            "traffic": measured_traffic(name) if workload == "sift1m" else None,
+            "traffic": measured_traffic(name, workload),
             "work_per_launch": per_launch,
             "work_unit": "flops" if scale == 1e12 else "bytes",
             "avg_launch_ms": avg_ms, "launches": launches}
+
+
+def mfma_utilisation(join_path, pairs, d, join_ms):
+    """Dense MFMA rate of the join's Gram tiles (2 d16 flops per pair for the
+    16-bit tiles, 2 d for the FP32 ones) against the chip's peak for that type."""
+    if not join_path.endswith(("mfma", "mixed")) or join_ms <= 0:
+        return None
+    d16 = (d + 15) // 16 * 16
+    sixteen = not join_path.startswith("fp32")
+    flops = 2.0 * pairs * (d16 if sixteen else d)
+    peak = PEAK_16BIT_TFLOPS if sixteen else PEAK_FP32_TFLOPS
+    rate = flops / (join_ms / 1000.0) / 1e12
+    return {"tflops": rate, "peak_tflops": peak, "frac": rate / peak,
+            "dtype": "f32" if not sixteen else join_path.split("-")[0]}
 
 
 def gen_data(w):
@@ -114,19 +147,55 @@ def recall(found, gt):
     return hits / gt.size
 
 
-def cpu_baseline(w, X, budget_n):
-    """The oracle (as it stands) on the first budget_n points of the workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_build_time(w, X, budget_n):
+    """The oracle (as it stands): NN-Descent + refine of the first budget_n points."""
     from oracle import oracle as O
     Xs = np.ascontiguousarray(X[:budget_n])
     stop = int(0.001 * budget_n * w["K"])
     t0 = time.perf_counter()
     ids, _, _, st = O.nndescent(Xs, w["K"], w["S"], w["iters"], 1, stop_updates=stop)
     O.refine(Xs, ids, w["R"])
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, st["iters"]
+
+
+def cpu_baseline(name, w, X, budget_n):
+    """The oracle on a bounded sample of the workload on every host core, and
+    on one core over the whole tiny set (a child process with one OpenMP thread)."""
+    dt, iters = oracle_build_time(w, X, budget_n)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": budget_n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {budget_n} points of the workload: NN-Descent ({st['iters']} iters) + "
-                      f"refine (prune, reverse, entry point, connect), {dt:.1f} s"}
+    out = {"value": budget_n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"first {budget_n} points of the {name} set: NN-Descent ({iters} iters) + "
+                     f"refine (prune, reverse, entry point, connect), {dt:.1f} s"}
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-core"], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode == 0 and r.stdout.strip():
+        out["one_core_tiny"] = json.loads(r.stdout.strip().splitlines()[-1])
+    else:
+        out["one_core_tiny"] = {"error": r.stderr[-400:]}
+    return out
+
+
+def oracle_one_core():
+    """Child process of cpu_baseline: the whole tiny set through the oracle."""
+    w = WORKLOADS["tiny"]
+    X, _ = gen_data(w)
+    dt, iters = oracle_build_time(w, X, w["n"])
+    print(json.dumps({"value": w["n"] / dt, "unit": "points/s", "cores": 1, "seconds": dt,
+                      "sample": f"the whole tiny set ({w['n']} points): NN-Descent ({iters} iters) + refine"}),
+          flush=True)
 
 
 def main():
@@ -134,9 +203,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sift1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--workload", default="suite", choices=["suite"] + sorted(WORKLOADS))
+    ap.add_argument("--leg-steps", type=int, default=2,
+                    help="timed steps of the suite's legs (at most --steps)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="points of the oracle's bounded sample (0: the workload's default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-one-core", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--iternsg", type=int, default=0, metavar="I",
                     help="also build the IterNSG graph (Alg. 6) with I OptKCNA rounds on the "
                          "fastest path and report its build time and search recall")
@@ -149,12 +222,16 @@ def main():
                          "d in {96, 128, 384, 768}, unit vectors in 20 clusters, K = R = 32) with 4 "
                          "query batches each, first saturated, then Poisson arrivals at 0.5 and 0.9 times that rate")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
-    ap.add_argument("--paths", default="fp32,fp16",
-                    help="comma-separated join paths to measure: fp32, fp16, bf16, fp32-valu")
+    ap.add_argument("--paths", default="",
+                    help="comma-separated join paths of a single --workload run: fp32, fp16, bf16, "
+                         "fp32-valu, fp16-stated (default: the workload's own)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "HBM byte counters against a copy of known size) and exit")
     args = ap.parse_args()
+    if args.oracle_one_core:
+        oracle_one_core()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -173,15 +250,74 @@ def main():
                           "expected_write_bytes_per_copy": nbytes}), flush=True)
         return
     from paper_2410_01231_amd import pg
+    torch.cuda.set_device(0)
+    ctx = pg.context(0)
 
-    w = WORKLOADS[args.workload]
+    names = SUITE if args.workload == "suite" else [args.workload]
+    legs = {}
+    head_name = names[0]
+    head_X = None
+    for i, name in enumerate(names):
+        steps = args.steps if i == 0 else max(1, min(args.steps, args.leg_steps))
+        warmup = args.warmup if i == 0 else 1
+        paths = args.paths if (args.paths and args.workload != "suite") else WORKLOADS[name]["paths"]
+        res, X = run_workload(args, name, paths, steps, warmup, pg, torch, ctx, keep_x=(i == 0))
+        legs[name] = res
+        if i == 0:
+            head_X = X
+        torch.cuda.empty_cache()
+    head = legs[head_name]
+    r = head["paths"][head["best"]]
+    w = WORKLOADS[head_name]
+    out = {
+        "metric": "build points/s at search recall@10>=0.95, FP32 vs FP16-MFMA; query p50/p99",
+        "value": r["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1, "steps": head["steps"], "warmup": head["warmup"],
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": PATHS[head["best"]]["dtype"], "data": "synthetic",
+        "config": {"workload": w["desc"], "n": w["n"], "d": w["d"], "K": w["K"], "R": w["R"], "S": w["S"],
+                   "max_iters": w["iters"], "delta": 0.001, "nq": w["nq"], "k": 10,
+                   "L": r["L"], "entries": r["entries"], "path": head["best"]},
+        "recall@10": r["recall@10"], "recall@10_ep_only": r["recall_ep_only"],
+        "knn_recall_sample": r["knn_recall_sample"],
+        "qps_batch": r["qps_batch"], "query_latency_ms_batch1": r["query_latency_ms_batch1"],
+        "roofline": r["roofline"],
+        "mfma_utilisation": r["mfma_utilisation"],
+        "fp32_vs_mixed": {p: {"points_per_s": v["points_per_s"], "ms_per_step": v["ms_per_step"],
+                              "recall@10": v["recall@10"], "join_path": v["join_path"]}
+                          for p, v in head["paths"].items()},
+        "host_upload": head["host_upload"],
+        "workloads": legs,
+    }
+    if args.iternsg or args.hnsw or args.serve:
+        Xd = torch.from_numpy(head_X).cuda()
+        X, Q = gen_data(w)
+        Qd = torch.from_numpy(Q).cuda()
+        gt, _ = pg.exact_knn(Xd, Qd, 10, ctx=ctx)
+        gt = gt.cpu().numpy()
+        if args.iternsg:
+            out["iter_nsg"] = run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[head["best"]])
+        if args.hnsw:
+            out["fast_hnsw"] = run_hnsw(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[head["best"]])
+        if args.serve:
+            out["serving"] = run_serve(args)
+    if not args.no_cpu_baseline:
+        budget = args.cpu_sample or w["cpu_sample"]
+        log(f"[bench] cpu baseline on {budget} points of {head_name}")
+        out["cpu_baseline"] = cpu_baseline(head_name, w, head_X, budget)
+    print(json.dumps(out), flush=True)
+
+
+def run_workload(args, name, paths, steps, warmup, pg, torch, ctx, keep_x=False):
+    """One workload: every path timed over `steps` steps after `warmup` builds."""
+    w = WORKLOADS[name]
     log(f"[bench] generating {w['desc']}")
     X, Q = gen_data(w)
-    torch.cuda.set_device(0)
     Xd = torch.from_numpy(X).cuda()
     Qd = torch.from_numpy(Q).cuda()
-    n, d, K, R, S = w["n"], w["d"], w["K"], w["R"], w["S"]
-    ctx = pg.context(0)
+    n, K = w["n"], w["K"]
     gt, _ = pg.exact_knn(Xd, Qd, 10, ctx=ctx)
     gt = gt.cpu().numpy()
     samp = np.random.default_rng(9).choice(n, size=min(n, 2000), replace=False).astype(np.int32)
@@ -208,8 +344,8 @@ def main():
         f"pinned {1000 * up_pinned:.1f} ms")
 
     results = {}
-    for path in args.paths.split(","):
-        results[path] = run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, PATHS[path])
+    for path in paths.split(","):
+        results[path] = run_path(steps, warmup, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, PATHS[path], name)
     # kNN-list entries and graph edges that differ from the FP32 build
     ref = next((results[p] for p in ("fp32", "fp32-valu") if p in results), None)
     for p in results:
@@ -219,75 +355,49 @@ def main():
     for p in results:
         results[p].pop("_ids")
         results[p].pop("_graph")
-    # headline: the fastest path whose graph reached the recall target
     ok = [p for p in results if results[p]["recall@10"] >= 0.95] or list(results)
     best = max(ok, key=lambda p: results[p]["points_per_s"])
-    r = results[best]
-    out = {
-        "metric": "build points/s at search recall@10>=0.95, FP32 vs FP16-MFMA; query p50/p99",
-        "value": r["points_per_s"],
-        "unit": "points/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": PATHS[best]["dtype"], "data": "synthetic",
-        "config": {"workload": w["desc"], "n": n, "d": d, "K": K, "R": R, "S": S,
-                   "max_iters": w["iters"], "delta": 0.001, "nq": int(Q.shape[0]), "k": 10,
-                   "L": r["L"], "path": best},
-        "recall@10": r["recall@10"], "knn_recall_sample": r["knn_recall_sample"],
-        "qps_batch": r["qps_batch"], "query_latency_ms_batch1": r["query_latency_ms_batch1"],
-        "roofline": r["roofline"],
-        "host_upload": {"bytes": int(X.nbytes), "pageable_ms": 1000.0 * up_pageable, "pinned_ms": 1000.0 * up_pinned,
-                        "points_per_s_with_pinned_upload": n / (r["ms_per_step"] / 1000.0 + up_pinned)},
-        "paths": {p: {k: v for k, v in results[p].items() if k != "roofline"} | {"roofline": results[p]["roofline"]}
-                  for p in results},
-    }
-    if args.iternsg:
-        out["iter_nsg"] = run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[best])
-    if args.hnsw:
-        out["fast_hnsw"] = run_hnsw(args, w, pg, torch, ctx, Xd, Qd, gt, PATHS[best])
-    if args.serve:
-        out["serving"] = run_serve(args)
-    if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline on {args.cpu_sample} points")
-        out["cpu_baseline"] = cpu_baseline(w, X, args.cpu_sample)
-    print(json.dumps(out), flush=True)
+    up = {"bytes": int(X.nbytes), "pageable_ms": 1000.0 * up_pageable, "pinned_ms": 1000.0 * up_pinned,
+          "points_per_s_with_pinned_upload": n / (results[best]["ms_per_step"] / 1000.0 + up_pinned)}
+    del Xd, Qd
+    return ({"workload": w["desc"], "steps": steps, "warmup": warmup, "best": best, "paths": results,
+             "host_upload": up}, X if keep_x else None)
 
 
 def run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, path):
     """IterNSG (Alg. 6) with args.iternsg OptKCNA rounds (alpha 65 degrees, k = K,
-    L = 2K): build time without P2K (the reported one) and with it (Section
-    5.4; the graphs must be identical), each after an untimed warm-up, then
-    the search ladder."""
+    L = 2K): build time without P2K and K2P (the reported one), with P2K and
+    with K2P (Section 5.4; the graphs must be identical), each after an
+    untimed warm-up, then the search ladders."""
     K, R, S = w["K"], w["R"], w["S"]
 
-    def build(p2k, counts=None):
+    def build(opt, counts=None):
         return pg.iter_nsg(Xd, K, R, K, 2 * K, 65.0, args.iternsg, S=S, max_iters=w["iters"], seed=1,
-                           delta=0.001, precision=path["precision"], p2k=p2k, counts=counts, ctx=ctx)
+                           delta=0.001, precision=path["precision"], p2k=opt == "p2k",
+                           counts=counts if opt != "k2p" else None,
+                           k2p=opt == "k2p", k2p_counts=counts if opt == "k2p" else None, ctx=ctx)
     times, graphs, counts = {}, {}, {}
-    for p2k in (False, True):
-        build(p2k)
+    for opt in ("none", "p2k", "k2p"):
+        build(opt)
         torch.cuda.synchronize()
         cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
         t0 = time.perf_counter()
-        graphs[p2k] = build(p2k, cnt)
+        graphs[opt] = build(opt, cnt)
         torch.cuda.synchronize()
-        times[p2k] = time.perf_counter() - t0
-        counts[p2k] = [int(x) for x in cnt.cpu().tolist()]
-        log(f"[bench] iternsg p2k={p2k} build {times[p2k]:.3f} s, distances computed/reused {counts[p2k]}")
-    same = all(torch.equal(graphs[False][k], graphs[True][k]) for k in ("ids", "deg", "cand"))
-    g = graphs[False]
-    build_s = times[False]
-    entries = torch.cat([g["ep"], g["roots"]]).contiguous()
-    ladder, chosen = [], None
-    for L in L_LADDER:
-        f, _ = pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, L, ctx=ctx)
-        r = recall(f.cpu().numpy(), gt)
-        ladder.append((L, r))
-        log(f"[bench] iternsg L={L} recall@10={r:.4f}")
-        if r >= 0.95:
-            chosen = L
-            break
+        times[opt] = time.perf_counter() - t0
+        counts[opt] = [int(x) for x in cnt.cpu().tolist()]
+        log(f"[bench] iternsg {opt} build {times[opt]:.3f} s, counts {counts[opt]}")
+    same = {o: all(torch.equal(graphs["none"][k], graphs[o][k]) for k in ("ids", "deg", "cand"))
+            for o in ("p2k", "k2p")}
+    g = graphs["none"]
+    build_s = times["none"]
+    ladders, sizes, sets = {}, {}, {}
+    for sname, ent in entry_sets(g, w["n"], torch):
+        lad = ladder(pg, torch, ctx, Xd, g, Qd, gt, ent, None)
+        ladders[sname], sizes[sname], sets[sname] = lad, int(ent.numel()), ent
+        log(f"[bench] iternsg entries {sname}: {lad}")
+    ename, chosen, _ = pick_entries(ladders, sizes, R)
+    entries = sets[ename]
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
     s0.record()
@@ -296,11 +406,13 @@ def run_iternsg(args, w, pg, torch, ctx, Xd, Qd, gt, path):
     s1.synchronize()
     return {"rounds": args.iternsg, "alpha_deg": 65.0, "k": K, "L_search": 2 * K,
             "build_ms": 1000.0 * build_s, "points_per_s": w["n"] / build_s,
-            "build_ms_with_p2k": 1000.0 * times[True],
-            "self_search_distances": {"without_p2k": counts[False][0],
-                                      "with_p2k_computed": counts[True][0],
-                                      "with_p2k_reused": counts[True][1]},
-            "p2k_graph_identical": bool(same), "L": chosen, "search_ladder": ladder,
+            "build_ms_with_p2k": 1000.0 * times["p2k"], "build_ms_with_k2p": 1000.0 * times["k2p"],
+            "self_search_distances": {"without_p2k": counts["none"][0],
+                                      "with_p2k_computed": counts["p2k"][0],
+                                      "with_p2k_reused": counts["p2k"][1]},
+            "k2p_pairs": {"skipped": counts["k2p"][0], "tested": counts["k2p"][1]},
+            "p2k_graph_identical": bool(same["p2k"]), "k2p_graph_identical": bool(same["k2p"]),
+            "L": chosen, "entries": ename, "search_ladders": ladders,
             "qps_batch": Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)}
 
 
@@ -425,10 +537,44 @@ PATHS = {
 }
 
 
-def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
+def ladder(pg, torch, ctx, Xd, g, Qd, gt, entries, x16, stop=0.95):
+    """Recall@10 over L_LADDER until it reaches `stop`: [(L, recall)]."""
+    out = []
+    for L in L_LADDER:
+        f, _ = pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, L, x16=x16, ctx=ctx)
+        r = recall(f.cpu().numpy(), gt)
+        out.append((L, r))
+        if r >= stop:
+            break
+    return out
+
+
+def entry_sets(g, n, torch):
+    """The entering-point sets in the order the search tries them: {ep}, ep
+    plus seeded uniform samples of E ids, ep plus every connect root."""
+    from paper_2410_01231_amd import datagen
+    sets = [("ep", g["ep"])]
+    for E in ENTRY_SAMPLES:
+        if E < n:
+            ids = torch.from_numpy(datagen.entry_sample(n, E)).to(g["ep"].device)
+            sets.append((f"ep+{E} seeded", torch.cat([g["ep"], ids]).contiguous()))
+    sets.append(("ep+roots", torch.cat([g["ep"], g["roots"]]).contiguous()))
+    return sets
+
+
+def pick_entries(ladders, sizes, R):
+    """Among the entering-point sets whose ladder reached recall@10 >= 0.95,
+    the one whose search evaluates the fewest distances per query (entries
+    plus L R neighbours at most); if none reached it, the last set at its
+    widest beam.  Returns (set name, L, recall)."""
+    ok = [(sizes[s] + lad[-1][0] * R, s) for s, lad in ladders.items() if lad[-1][1] >= 0.95]
+    s = min(ok)[1] if ok else list(ladders)[-1]
+    return s, ladders[s][-1][0], ladders[s][-1][1]
+
+
+def run_path(steps, warmup, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path, name):
     n, K, R, S = w["n"], w["K"], w["R"], w["S"]
     prec = path["precision"]
-
     last = {}
 
     def build():
@@ -439,90 +585,99 @@ def run_path(args, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path):
         return ids, st, g
 
     # ---- warm-up and recall calibration (untimed)
-    for i in range(max(args.warmup, 1)):
+    for i in range(max(warmup, 1)):
         t0 = time.perf_counter()
         ids, st, g = build()
         torch.cuda.synchronize()
-        log(f"[bench] {path['dtype']} warmup {i}: {time.perf_counter() - t0:.3f} s, iters {st['iters']}, "
+        log(f"[bench] {name} {path['name']} warmup {i}: {time.perf_counter() - t0:.3f} s, iters {st['iters']}, "
             f"join {st['join_path']}, roots {len(g['roots'])}, retries {st['retries']}, "
             f"spilled {st['spilled']}")
         log(f"[bench]   updates {st['updates']}\n[bench]   pairs {st['pairs']}\n"
             f"[bench]   proposals {st['proposals']}\n[bench]   rechecked {st['rechecked']}")
-    entries = torch.cat([g["ep"], g["roots"]]).contiguous()
     # rows for the search: an FP16 copy when it holds X exactly (same results)
     h16, exact16 = pg.half_rows(Xd, ctx=ctx)
     x16 = h16 if exact16 else None
-    chosen, rec = None, 0.0
-    ladder = []
-    for L in L_LADDER:
-        f, _ = pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, L, x16=x16, ctx=ctx)
-        r = recall(f.cpu().numpy(), gt)
-        ladder.append((L, r))
-        log(f"[bench] L={L} recall@10={r:.4f}")
-        if r >= 0.95:
-            chosen, rec = L, r
-            break
-    if chosen is None:
-        chosen, rec = L_LADDER[-1], ladder[-1][1]
+    ladders, sizes = {}, {}
+    for sname, ent in entry_sets(g, n, torch):
+        lad = ladder(pg, torch, ctx, Xd, g, Qd, gt, ent, x16)
+        ladders[sname], sizes[sname] = lad, int(ent.numel())
+        log(f"[bench] {name} {path['name']} entries {sname} ({ent.numel()}): {lad}")
+    ename, L_ch, rec = pick_entries(ladders, sizes, R)
+    n_entry_seeded = int(ename.split("+")[1].split()[0]) if "seeded" in ename else 0
+
+    def entries_of(g):
+        from paper_2410_01231_amd import datagen
+        if ename == "ep":
+            return g["ep"]
+        if n_entry_seeded:
+            return torch.cat([g["ep"], torch.from_numpy(datagen.entry_sample(n, n_entry_seeded)).cuda()])
+        return torch.cat([g["ep"], g["roots"]]).contiguous()
+    entries = entries_of(g)
     kl = ids.cpu().numpy()[samp]
     knn_recall = float(np.mean([len(set(a) & set(b)) / K for a, b in zip(kl, kt)]))
     # distance error of the stored list distances against FP64 (first 200 sampled nodes)
-    sub = samp[:200]
-    xs = Xd[torch.from_numpy(sub).cuda().long()].double()
-    kl_d2 = last["d2"].double()[torch.from_numpy(sub).cuda().long()]
-    nb = Xd[ids[torch.from_numpy(sub).cuda().long()].long()].double()
+    sub = torch.from_numpy(samp[:200]).cuda().long()
+    xs = Xd[sub].double()
+    kl_d2 = last["d2"].double()[sub]
+    nb = Xd[ids[sub].long()].double()
     exact = ((xs[:, None, :] - nb) ** 2).sum(-1)
-    d2_err = float(((kl_d2 - exact).abs() / exact.clamp_min(1e-300)).max())
+    rel = ((kl_d2 - exact).abs() / exact.clamp_min(1e-300)).flatten()
+    d2_err = {"max": float(rel.max()), "median": float(rel.median())}
 
     # ---- timed steps
     ctx.set_timing(True)
     ctx.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         ids, st, g = build()
-        entries = torch.cat([g["ep"], g["roots"]]).contiguous()
         h16, exact16 = pg.half_rows(Xd, ctx=ctx)
-        pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, chosen, x16=h16 if exact16 else None, ctx=ctx)
+        pg.search(Xd, g["ids"], g["deg"], Qd, entries_of(g), 10, L_ch, x16=h16 if exact16 else None, ctx=ctx)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kt_ = {name: ctx.kernel_time(name) for name in
+    kt_ = {kn: ctx.kernel_time(kn) for kn in
            ("join", "merge", "init", "sample", "prune", "connect", "search", "exact_knn")}
     ctx.set_timing(False)
     join_ms, join_n, join_work = kt_["join"]
 
-    # search latency: batches of one query, then the whole batch
+    # search latency: batches of one query (entering points included), then the whole batch
     lat = []
     for i in range(200):
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record()
-        pg.search(Xd, g["ids"], g["deg"], Qd[i:i + 1], entries, 10, chosen, x16=x16, ctx=ctx)
+        pg.search(Xd, g["ids"], g["deg"], Qd[i % Qd.shape[0]:i % Qd.shape[0] + 1], entries, 10, L_ch, x16=x16,
+                  ctx=ctx)
         s1.record()
         s1.synchronize()
         lat.append(s0.elapsed_time(s1))
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
     s0.record()
-    pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, chosen, x16=x16, ctx=ctx)
+    pg.search(Xd, g["ids"], g["deg"], Qd, entries, 10, L_ch, x16=x16, ctx=ctx)
     s1.record()
     s1.synchronize()
     qps = Qd.shape[0] / (s0.elapsed_time(s1) / 1000.0)
+    ep_lad = ladders["ep"]
 
     return {
         "_ids": ids, "_graph": g["ids"],
-        "points_per_s": n * args.steps / elapsed,
-        "ms_per_step": 1000.0 * elapsed / args.steps,
-        "join_path": st["join_path"], "L": chosen,
-        "recall@10": rec, "knn_recall_sample": knn_recall, "search_ladder": ladder,
-        "knn_d2_max_rel_error_vs_fp64": d2_err,
+        "points_per_s": n * steps / elapsed,
+        "ms_per_step": 1000.0 * elapsed / steps,
+        "join_path": st["join_path"], "L": L_ch, "entries": ename,
+        "recall@10": rec,
+        "recall_ep_only": {"L": ep_lad[-1][0], "recall@10": ep_lad[-1][1]},
+        "search_ladders": ladders,
+        "knn_recall_sample": knn_recall,
+        "knn_d2_rel_error_vs_fp64": d2_err,
         "nndescent_iters": st["iters"], "connect_roots": int(len(g["roots"])),
         "rechecked_fraction": sum(st["rechecked"]) / max(1, sum(st["pairs"])),
         "qps_batch": qps, "search_rows": "fp16 (exact copy)" if exact16 else "fp32",
         "query_latency_ms_batch1": {"p50": float(np.percentile(lat, 50)),
                                     "p99": float(np.percentile(lat, 99))},
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt_.items()},
-        "roofline": roofline(st["join_path"], join_work, join_n, join_ms, path["name"], args.workload),
+        "kernel_ms_per_step": {k: v[0] / steps for k, v in kt_.items()},
+        "roofline": roofline(st["join_path"], join_work, join_n, join_ms, path["name"], name),
+        "mfma_utilisation": mfma_utilisation(st["join_path"], sum(st["pairs"]) * steps, w["d"], join_ms),
     }
 
 

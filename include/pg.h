@@ -195,6 +195,23 @@ pg_status pg_exact_knn(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_
                        const float *Q, int64_t nq, int64_t ldq, const int32_t *exclude,
                        int32_t k, int32_t *out_ids, float *out_d2);
 
+/* Quality examination of Section 5.2 (the sample-size theorem; the quality
+ * test that ends IterNSG's rounds, Alg. 6): for each sampled node u =
+ * sample[i] the exact k nearest other points N*_k(u) (brute force over the
+ * rows of X, u itself skipped) go to exact_ids / exact_d2 (ns x k, ordered by
+ * (d2, id)), hits[i] (ns int32) receives |C(u)[:k] & N*_k(u)| with C(u) the
+ * first k entries of row u of cand_ids (n x C, -1 pads count as misses), and
+ * *estimate (device, one double) the estimated k-CNA recall
+ * sum(hits) / (k ns).  The caller draws the sample (ns = (8 + 2 eps) l ln n /
+ * eps^2 nodes estimate the mean within eps / 2 with probability 1 - n^-l).
+ * Requires 1 <= k <= min(64, C), k < n, 1 <= ns <= n.  Only enqueues work:
+ * on a stream of its own it overlaps other work (the next OptKCNA round).  A
+ * sample id outside [0, n) gives hits -1 for it and a NaN estimate. */
+pg_status pg_quality_examination(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                 const int32_t *cand_ids, int32_t C, int32_t k,
+                                 const int32_t *sample, int64_t ns, int32_t *exact_ids,
+                                 float *exact_d2, int32_t *hits, double *estimate);
+
 /* ------------------------------------------------------------------ */
 /* Refinement: Prune (Alg. 3), reverse re-prune and connect (Alg. 2)   */
 /* ------------------------------------------------------------------ */
@@ -208,6 +225,29 @@ typedef struct {
     const float *pair_d2; /* optional test hook, PRUNE stage alone: n tables of
                              (C+1) x (C+1) floats, positions 0 = u and 1..C =
                              cand_ids[u][0..C-1]; all distances are read from it */
+    int32_t precision;    /* PG_FP32 (0): pairwise distances from FP16 MFMA Gram
+                             tiles where they are exact (integer data, see
+                             below), else from tiles on the mean-centred FP16
+                             copy that only decide what their rigorous error
+                             bound allows, the rest (and, with the alpha test,
+                             every pair that may occlude) taking the FP32
+                             chain; PG_FP32_VALU: every pairwise distance is
+                             the FP32 chain.  Both give the same graph. */
+    /* K2P (Section 5.4; the index is unchanged, Exp. 6).  k2p_prev_ids (n x
+       k2p_prev_R, -1 pads, lengths k2p_prev_deg) holds the PRUNE-stage lists
+       of the previous round over the same X with the same alpha_deg and
+       strict_ties (prune_ids_out of that call).  Two candidates of u that
+       both stayed in u's previous list are not tested against each other:
+       the earlier did not occlude the later then, and cannot now.  Applies to
+       the PRUNE stage of the MFMA kernels (given cand_d2, precision PG_FP32).
+       k2p_counts (optional, device, 2 values) is added the pairs skipped and
+       the pairs tested. */
+    const int32_t *k2p_prev_ids;
+    const int32_t *k2p_prev_deg;
+    int32_t k2p_prev_R;
+    unsigned long long *k2p_counts;
+    int32_t *prune_ids_out;  /* optional, n x R: this call's PRUNE-stage lists */
+    int32_t *prune_deg_out;  /* optional, n: their lengths (with prune_ids_out) */
 } pg_prune_params;
 
 /* Workspace bytes needed by pg_prune for n points of dimension d and C

@@ -361,6 +361,13 @@ __global__ __launch_bounds__(256) void k_build_join(
 // local join tile
 // ---------------------------------------------------------------------------
 // Is `key` one of the K sorted keys of a list?  (binary search)
+// whether the list (K keys) holds id, whatever its distance
+__device__ __forceinline__ bool list_has_id(const uint64_t *__restrict__ row, int K, int32_t id) {
+    bool f = false;
+    for (int j = 0; j < K; ++j) f |= key_id(row[j]) == id;
+    return f;
+}
+
 __device__ __forceinline__ bool list_has(const uint64_t *__restrict__ row, int K, uint64_t key) {
     int lo = 0, hi = K;
     while (lo < hi) {
@@ -1008,15 +1015,15 @@ __device__ __forceinline__ mf_f32x16 gram_tile(const float *__restrict__ X, int6
 }
 
 constexpr int MW = 4;  // sources (waves) per workgroup in the MFMA join
-// mixed path: recheck list (a 32 x 32 tile has at most 1024 pairs) and the
-// rechecked distances (16 registers x 64 lanes)
+// mixed path: recheck list (a 32 x 32 tile has at most 1024 pairs), the
+// rechecked distances (16 registers x 64 lanes) and the ends they go to
 constexpr int JR_LIST = 1024;
 
 // LDS bytes of one join wave: per member kth, sbase, ids, cnt, base, mk, nrm,
-// thr; the mixed path adds the recheck list and distances
+// thr; the mixed path adds the recheck list, distances and end flags
 __host__ __device__ inline size_t join_mfma_wave_bytes(int mps, bool mix) {
     return (size_t)mps * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4) +
-           (mix ? (size_t)JR_LIST * sizeof(uint16_t) + (size_t)16 * PG_WAVE * sizeof(float) : 0);
+           (mix ? (size_t)JR_LIST * sizeof(uint16_t) + (size_t)16 * PG_WAVE * (sizeof(float) + 1) : 0);
 }
 
 // MFMA local join for data on which the norm expansion is exact (see k_prep):
@@ -1057,6 +1064,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     // mixed: the tile's pairs to recheck (q << 6 | lane) and their direct-form distances
     uint16_t *rlist = reinterpret_cast<uint16_t *>(thr + MPS);
     float *rdx = reinterpret_cast<float *>(rlist + JR_LIST);
+    uint8_t *rfl = reinterpret_cast<uint8_t *>(rdx + 16 * PG_WAVE);
 
     const int nn = jn_c[u], no = jo_c[u];
     const int m = nn + no;
@@ -1094,19 +1102,31 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
             const float thc = thr[cm < mp ? cm : 0];
             float dx[MIX ? 16 : 1];  // mixed: direct-form distances of the rechecked pairs
             uint32_t rmask = 0;      // mixed: registers whose pair is rechecked
+            uint32_t emask = 0;      // mixed: bits 2q / 2q + 1, the row / column end takes it
+            uint32_t bmask = 0;      // mixed: the same bits, ends whose bound the estimate meets
             if constexpr (MIX) {
                 // Pairs whose 16-bit estimate lies within the rigorous bound of
-                // an end's cut are rechecked in the FP32 direct form.  They are
-                // gathered from the whole wave and spread one per lane, so the
-                // long chains run in parallel rather than one register at a time.
+                // an end's cut are candidates.  They are gathered from the whole
+                // wave and spread one per lane.  An end that lists the other
+                // member already needs no proposal (the merge would drop it), so
+                // only pairs that some end does not list yet are rechecked in
+                // the FP32 direct form, the long chains running in parallel.
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
                     dx[q] = __int_as_float(0x7f800000);
                     if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
                     const float d2e = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
-                    const float cut = fmaxf(mk[r] ? key_d2(kth[r]) : -1.0f, mk[cm] ? key_d2(kth[cm]) : -1.0f);
+                    const float cr = mk[r] ? key_d2(kth[r]) : -1.0f, cc = mk[cm] ? key_d2(kth[cm]) : -1.0f;
+                    const float cut = fmaxf(cr, cc);
                     if (cut < 0.0f || !(d2e <= mixed_bound(mx, cut, nrm[r], nc, g[q]))) continue;
+                    // the bound grows with the cut: the end with the larger cut
+                    // is in band, the other one is when its own bound holds
+                    const float lo = fminf(cr, cc);
+                    const bool other = lo >= 0.0f && d2e <= mixed_bound(mx, lo, nrm[r], nc, g[q]);
+                    const bool er = cr >= 0.0f && (cr >= cc || other);
+                    const bool ec = cc >= 0.0f && (cc > cr || other);
+                    bmask |= (er ? 1u : 0u) << (2 * q) | (ec ? 2u : 0u) << (2 * q);
                     rmask |= 1u << q;
                 }
                 const int nr = __popc(rmask);
@@ -1125,22 +1145,36 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
                         while (mm) {
                             const int q = __builtin_ctz(mm);
                             mm &= mm - 1;
-                            rlist[e++] = (uint16_t)((q << 6) | lane);
+                            rlist[e++] = (uint16_t)((((bmask >> (2 * q)) & 3u) << 10) | (q << 6) | lane);
                         }
                     }
                     __builtin_amdgcn_wave_barrier();
+                    int done = 0;
                     for (int e = lane; e < rtot; e += PG_WAVE) {
-                        const int ent = rlist[e], q = ent >> 6, src = ent & 63;
+                        const int ent = rlist[e], q = (ent >> 6) & 15, src = ent & 63;
                         const int rr = 32 * rb + 8 * (q / 4) + 4 * (src >> 5) + (q % 4);
                         const int cc = 32 * cb + (src & 31);
-                        rdx[src * 16 + q] = dist_chain(X + (int64_t)ids[rr] * ldx, X + (int64_t)ids[cc] * ldx, d);
+                        const int32_t ir = ids[rr], ic = ids[cc];
+                        int fl = (ent >> 10) & 3;
+                        if ((fl & 1) && list_has_id(keys + (int64_t)ir * K, K, ic)) fl &= ~1;
+                        if ((fl & 2) && list_has_id(keys + (int64_t)ic * K, K, ir)) fl &= ~2;
+                        float v = __int_as_float(0x7f800000);
+                        if (fl) {
+                            v = dist_chain(X + (int64_t)ir * ldx, X + (int64_t)ic * ldx, d);
+                            ++done;
+                        }
+                        rdx[src * 16 + q] = v;
+                        rfl[src * 16 + q] = (uint8_t)fl;
                     }
                     __builtin_amdgcn_wave_barrier();
 #pragma unroll
                     for (int q = 0; q < 16; ++q)
-                        if ((rmask >> q) & 1u) dx[q] = rdx[lane * 16 + q];
+                        if ((rmask >> q) & 1u) {
+                            dx[q] = rdx[lane * 16 + q];
+                            emask |= (uint32_t)rfl[lane * 16 + q] << (2 * q);
+                        }
                     __builtin_amdgcn_wave_barrier();
-                    local_rechk += (unsigned long long)nr;
+                    local_rechk += (unsigned long long)done;
                 }
             }
 #pragma unroll
@@ -1151,14 +1185,19 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
                 if (!MIX && !(d2 <= thr[r]) && !(d2 <= thc)) continue;
                 if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
                 if (MIX) {
-                    if (!((rmask >> q) & 1u)) continue;  // not rechecked: outside the bound
+                    // outside the bound, or every end in band lists the other
+                    if (!((emask >> (2 * q)) & 3u)) continue;
                     d2 = dx[MIX ? q : 0];
                 }
                 const uint64_t kw = pack_key(d2, ids[cm]), kv = pack_key(d2, ids[r]);
-                if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
-                    to_row |= 1u << q;
-                if (mk[cm] && kv < kth[cm] && !(mark && list_has(keys + (int64_t)ids[cm] * K, K, kv)))
-                    to_col |= 1u << q;
+                // mixed: an end takes the pair only if it is in band and does
+                // not list the other member (checked above, repeat passes too)
+                const bool row_ok = MIX ? ((emask >> (2 * q)) & 1u) != 0
+                                        : !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw));
+                const bool col_ok = MIX ? ((emask >> (2 * q)) & 2u) != 0
+                                        : !(mark && list_has(keys + (int64_t)ids[cm] * K, K, kv));
+                if (mk[r] && kw < kth[r] && row_ok) to_row |= 1u << q;
+                if (mk[cm] && kv < kth[cm] && col_ok) to_col |= 1u << q;
             }
             // Offsets within this tile's contribution to each target.  Each
             // (register, half) is a distinct row, so a row's count is one
@@ -1358,6 +1397,7 @@ constexpr int EQ = 64, EP = 64, EDC = 32, ESTR = EDC + 4;
 __global__ __launch_bounds__(256) void k_exact_knn(const float *__restrict__ X, int64_t n, int d,
                                                    int64_t ldx, const float *__restrict__ Q,
                                                    int64_t nq, int64_t ldq,
+                                                   const int32_t *__restrict__ qrow, int64_t qrow_n,
                                                    const int32_t *__restrict__ exclude,
                                                    int self_excl, int k,
                                                    int32_t *__restrict__ out_ids,
@@ -1371,8 +1411,19 @@ __global__ __launch_bounds__(256) void k_exact_knn(const float *__restrict__ X, 
     const int ty = tid >> 4, tx = tid & 15;
     const int64_t q0 = (int64_t)blockIdx.x * EQ;
     for (int i = tid; i < EQ * PG_WAVE; i += 256) topk[i] = KEY_INF;
-    for (int i = tid; i < EQ; i += 256)
+    // query q reads row qrow[q] of Q when qrow is given (a row outside
+    // [0, qrow_n) reads as zeros; the caller reports it), else row q
+    __shared__ int64_t qoff[EQ];
+    for (int i = tid; i < EQ; i += 256) {
         excl[i] = q0 + i >= nq ? -1 : (self_excl ? (int32_t)(q0 + i) : (exclude ? exclude[q0 + i] : -1));
+        int64_t r = q0 + i;
+        if (qrow && q0 + i < nq) {
+            const int32_t qi = qrow[q0 + i];
+            r = (qi >= 0 && qi < qrow_n) ? (int64_t)qi : -1;
+        }
+        qoff[i] = q0 + i < nq && r >= 0 ? r * ldq : -1;
+    }
+    __syncthreads();
     for (int64_t p0 = 0; p0 < n; p0 += EP) {
         float acc[4][4];
 #pragma unroll
@@ -1385,8 +1436,8 @@ __global__ __launch_bounds__(256) void k_exact_knn(const float *__restrict__ X, 
                 const int r = e / (EDC / 4), q = e % (EDC / 4);
                 float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (r < EQ) {
-                    if (q0 + r < nq && c0 + 4 * q < d)
-                        val = *reinterpret_cast<const float4 *>(Q + (q0 + r) * ldq + c0 + 4 * q);
+                    if (qoff[r] >= 0 && c0 + 4 * q < d)
+                        val = *reinterpret_cast<const float4 *>(Q + qoff[r] + c0 + 4 * q);
                     *reinterpret_cast<float4 *>(qt + r * ESTR + 4 * q) = val;
                 } else {
                     const int rr = r - EQ;
@@ -1603,12 +1654,13 @@ extern "C" pg_status pg_knn_build_workspace(const pg_knn_params *p, int64_t n, i
 
 static pg_status launch_exact(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
                               const float *Q, int64_t nq, int64_t ldq, const int32_t *exclude,
-                              int self_excl, int32_t k, int32_t *out_ids, float *out_d2) {
+                              int self_excl, int32_t k, int32_t *out_ids, float *out_d2,
+                              const int32_t *qrow = nullptr, int64_t qrow_n = 0) {
     if (nq == 0) return PG_OK;
     const int64_t blocks = (nq + EQ - 1) / EQ;
     TimedLaunch tl(ctx, K_EXACT, 3.0 * (double)n * (double)nq * d);
     hipLaunchKernelGGL(k_exact_knn, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, X, n, d, ldx, Q,
-                       nq, ldq, exclude, self_excl, k, out_ids, out_d2);
+                       nq, ldq, qrow, qrow_n, exclude, self_excl, k, out_ids, out_d2);
     PG_HIP(hipGetLastError());
     return PG_OK;
 }
@@ -1959,6 +2011,83 @@ extern "C" pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_
         }
     }
     return knn_build_run(ctx, X, n, d, ldx, p, ws, knn_ids, knn_d2, stats);
+}
+
+// ---------------------------------------------------------------------------
+// Quality examination (Section 5.2): hits[i] = |C(u)[:k] & N*_k(u)| for the
+// sampled u = sample[i], N*_k(u) being the exact list the brute-force kernel
+// wrote for it, and the estimate sum(hits) / (k ns).  One workgroup; integer
+// sums, so the estimate does not depend on the order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cna_hits(const int32_t *__restrict__ cand, int C, int k,
+                                                  const int32_t *__restrict__ sample, int64_t ns, int64_t n,
+                                                  const int32_t *__restrict__ exact_ids,
+                                                  int32_t *__restrict__ hits, double *__restrict__ estimate) {
+    __shared__ long long part[256];
+    __shared__ int bad[256];
+    long long acc = 0;
+    int nbad = 0;
+    for (int64_t i = threadIdx.x; i < ns; i += 256) {
+        const int32_t u = sample[i];
+        int h = -1;
+        if (u >= 0 && u < n) {
+            h = 0;
+            const int32_t *c = cand + (int64_t)u * C;
+            const int32_t *t = exact_ids + i * k;
+            // the exact ids are distinct, so counting those that C(u)[:k]
+            // holds counts the intersection of the two sets
+            for (int a = 0; a < k; ++a) {
+                const int32_t v = t[a];
+                if (v < 0) continue;
+                bool in = false;
+                for (int b = 0; b < k; ++b) in |= c[b] == v;
+                h += in ? 1 : 0;
+            }
+            acc += h;
+        } else {
+            ++nbad;
+        }
+        hits[i] = h;
+    }
+    part[threadIdx.x] = acc;
+    bad[threadIdx.x] = nbad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            part[threadIdx.x] += part[threadIdx.x + o];
+            bad[threadIdx.x] += bad[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *estimate = bad[0] ? __longlong_as_double(0x7ff8000000000000ll)
+                           : (double)part[0] / ((double)k * (double)ns);
+}
+
+extern "C" pg_status pg_quality_examination(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                            const int32_t *cand_ids, int32_t C, int32_t k,
+                                            const int32_t *sample, int64_t ns, int32_t *exact_ids,
+                                            float *exact_d2, int32_t *hits, double *estimate) {
+    if (!ctx || !X || !cand_ids || !sample || !exact_ids || !exact_d2 || !hits || !estimate) {
+        set_error("pg_quality_examination: NULL argument");
+        return PG_EINVAL;
+    }
+    if (n < 2 || n >= (int64_t)1 << 31 || d <= 0 || ldx < d || k < 1 || k > 64 || k >= n || C < k ||
+        ns < 1 || ns > n) {
+        set_error("pg_quality_examination: bad sizes n=%lld d=%d k=%d C=%d ns=%lld (need 1 <= k <= min(64, C), "
+                  "k < n, 1 <= ns <= n)", (long long)n, d, k, C, (long long)ns);
+        return PG_EINVAL;
+    }
+    if (d % 4 || ldx % 4 || ((uintptr_t)X & 15)) {
+        set_error("pg_quality_examination: d and ldx must be multiples of 4 and X 16-byte aligned");
+        return PG_EUNSUPPORTED;
+    }
+    // the sampled rows are their own queries, each skipping itself
+    PG_TRY(launch_exact(ctx, X, n, d, ldx, X, ns, ldx, sample, 0, k, exact_ids, exact_d2, sample, n));
+    hipLaunchKernelGGL(k_cna_hits, dim3(1), dim3(256), 0, ctx->stream, cand_ids, C, k, sample, ns, n, exact_ids,
+                       hits, estimate);
+    PG_HIP(hipGetLastError());
+    return PG_OK;
 }
 
 // ---------------------------------------------------------------------------

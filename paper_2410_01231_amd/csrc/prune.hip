@@ -300,6 +300,73 @@ __global__ __launch_bounds__(256) void k_prune_prep(const float *__restrict__ X,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed 16-bit path for float data.  The Gram tiles run on the centred FP16
+// copy x^ = fp16(fl32(x - mu)) with FP32 norms n^ of the rounded rows, and
+// give an estimate b^ = n^_v + n^_w - 2 v^.w^ of the canonical chain b of
+// the FP32 rows.  With e = un (|x^| + |y^|)(1 + 2 un) + 2 sqrt(d) ea bounding
+// the rounding of the difference, and the FP32 accumulation of the estimate
+// within ga (n^_v + n^_w + 2 |v^.w^|) and of the chain within gd b (the same
+// error model as the mixed join):
+//   b <= t  implies  b^ <= hi(t) = t' + 2 e sqrt(t') + e^2 + acc,  t' = t (1 + gd)
+//   b >= t  implies  b^ >= lo(t) = t" - 2 e sqrt(t") - e^2 - acc, t" = t (1 - gd)
+// (the second as long as sqrt(t") >= e; below that lo is negative and never
+// decides).  So b^ > hi(c) decides b > c (no occlusion) and, without the
+// angle test, b^ < lo(c) decides b < c; every other pair, and with the angle
+// test every pair that may occlude, gets its canonical chain from the FP32
+// rows.  The decisions are therefore those of the VALU kernel.
+// ---------------------------------------------------------------------------
+struct PruneMix {
+    int on;
+    float un, ea, gd, ga, sqd;
+};
+
+__device__ __forceinline__ float pmix_e(const PruneMix &m, float nx, float ny) {
+    return m.un * (sqrtf(nx) + sqrtf(ny)) * (1.0f + 2.0f * m.un) + 2.0f * m.sqd * m.ea;
+}
+__device__ __forceinline__ float pmix_hi(const PruneMix &m, float t, float e, float acc) {
+    const float tg = t * (1.0f + m.gd);
+    const float v = tg + 2.0f * e * sqrtf(tg) + e * e + acc;
+    return v + v * 1e-5f + 1e-30f;  // slack for evaluating the bound in FP32
+}
+__device__ __forceinline__ float pmix_lo(const PruneMix &m, float t, float e, float acc) {
+    const float tl = t * (1.0f - m.gd);
+    const float r = 2.0f * e * sqrtf(tl) + e * e + acc;
+    return (tl - r) - (tl + r) * 1e-5f - 1e-30f;
+}
+
+// one wave per row (grid-stride): x16 = fp16(fl32(x - mu)) with mu the FP32
+// rounding of the centroid, norms = FP32 sum of the rounded squares;
+// PX_MAXABS gets max |x - mu|
+__global__ __launch_bounds__(256) void k_prune_prep_mixed(const float *__restrict__ X, int64_t ldx, int d, int d16,
+                                                          int64_t n, const double *__restrict__ cen,
+                                                          _Float16 *__restrict__ x16, float *__restrict__ norms,
+                                                          unsigned int *__restrict__ ex) {
+    __shared__ unsigned int red[4];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    float mabs = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < n; i += (int64_t)gridDim.x * 4) {
+        const float *x = X + i * ldx;
+        float s = 0.f;
+        for (int k = lane; k < d16; k += PG_WAVE) {
+            const float c = k < d ? x[k] - (float)cen[k] : 0.f;
+            mabs = fmaxf(mabs, fabsf(c));
+            const _Float16 hv = (_Float16)c;
+            x16[i * d16 + k] = hv;
+            const float r = (float)hv;
+            s = fmaf(r, r, s);
+        }
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) s += __shfl_xor(s, o, PG_WAVE);
+        if (lane == 0) norms[i] = s;
+    }
+#pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, o, PG_WAVE));
+    if (lane == 0) red[wv] = __float_as_uint(mabs);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&ex[PX_MAXABS], max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
 constexpr int PM_DC = 32;            // dimensions per staged chunk
 constexpr int PM_RS = PM_DC + 8;     // LDS row stride in halves (16-byte pad)
 constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept nodes
@@ -310,22 +377,49 @@ constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept 
 // Occlusion among this round's candidates is kept per occluding row (lane i
 // holds the set of later candidates that i occludes); the greedy scan of
 // Alg. 3 ORs in the set of every candidate it keeps.
+//
+// MIX (float data): the tiles give estimates on the centred copy; pairs they
+// cannot decide go to a list of the tile and get their canonical chains from
+// the FP32 rows, one pair per lane, and their occlusion bits through LDS.
+//
+// K2P (Section 5.4): prev_ids holds u's list after the PRUNE stage of the
+// previous round (same alpha and tie rule).  Two candidates that both stayed
+// in it were both visited then, in the same (d2, id) order, and the earlier
+// did not occlude the later (else the later would have been dropped); the
+// test involves only the three points, so it is skipped now.  k2p counts the
+// pairs skipped and the pairs tested.
+template <bool MIX>
 __global__ __launch_bounds__(64, 4) void k_prune_mfma(
     const _Float16 *__restrict__ X16, int d16, const float *__restrict__ norms, int64_t n,
     const int32_t *__restrict__ src1, const float *__restrict__ src1_d2, int C1,
     const int32_t *__restrict__ src1_deg, const int64_t *__restrict__ src2_off,
     const int32_t *__restrict__ src2, const float *__restrict__ src2_d2, int R, AngleTest at,
-    int strict, int32_t *__restrict__ out_ids, float *__restrict__ out_d2, int32_t *__restrict__ out_deg) {
+    int strict, int32_t *__restrict__ out_ids, float *__restrict__ out_d2, int32_t *__restrict__ out_deg,
+    const float *__restrict__ X, int64_t ldx, int d, PruneMix pmx, const int32_t *__restrict__ prev_ids,
+    const int32_t *__restrict__ prev_deg, int prevR, unsigned long long *__restrict__ k2p) {
     __shared__ __align__(16) _Float16 rows[PM_ROWS * PM_RS];
     __shared__ uint64_t kept_key[PG_WAVE];
     __shared__ uint64_t chunk_key[PG_WAVE];
     __shared__ float cn[PG_WAVE], kn[PG_WAVE];
+    // mixed: pairs of the current tile left to the chains (row << 6 | column),
+    // and the occlusion bits they produce
+    __shared__ uint16_t rl[MIX ? 1024 : 1];
+    __shared__ unsigned long long kill_lds[MIX ? PG_WAVE : 1];
+    __shared__ unsigned long long occk_lds;
+    __shared__ int32_t prev_lds[PG_WAVE];
     const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
     const int64_t u = blockIdx.x;
     const int c1 = src1_deg ? min(src1_deg[u], C1) : C1;
     const int64_t off2 = src2_off ? src2_off[u] : 0;
     const int c2 = src2_off ? (int)(src2_off[u + 1] - off2) : 0;
     const int m = c1 + c2;
+    const int np = prev_ids ? min(prev_deg[u], prevR) : 0;
+    if (prev_ids) {
+        prev_lds[lane] = lane < np ? prev_ids[u * prevR + lane] : -1;
+        __builtin_amdgcn_wave_barrier();
+    }
+    unsigned long long n_skip = 0, n_test = 0;
+    uint64_t kpk = 0;  // kept nodes that were in the previous round's list
 
     int nk = 0;
     bool first = true;
@@ -374,6 +468,14 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
         const int cm = __popcll(__ballot(top != KEY_INF));
         if (cm == 0) break;
         chunk_key[lane] = top;
+        // K2P: this round's candidates that were in the previous round's list
+        uint64_t pk = 0;
+        if (np > 0) {
+            const int32_t cid = top != KEY_INF ? key_id(top) : -1;
+            bool in = false;
+            for (int t = 0; t < np; ++t) in |= cid >= 0 && prev_lds[t] == cid;
+            pk = __ballot(in);
+        }
         {
             const int32_t cid = top != KEY_INF ? key_id(top) : -1;
             cn[lane] = cid >= 0 ? norms[cid] : 0.f;
@@ -381,6 +483,56 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             kn[lane] = kid >= 0 ? norms[kid] : 0.f;
         }
         const bool two = cm > 32;
+        if (MIX) {
+            kill_lds[lane] = 0;
+            if (lane == 0) occk_lds = 0;
+            __builtin_amdgcn_wave_barrier();
+        }
+        // mixed: the undecided pairs of a tile (bit g of umask: register g,
+        // row rowof(g), column `col`) are listed and decided on the chains;
+        // kept: the rows are kept nodes (occk_lds), else candidates (kill_lds)
+        auto settle = [&](uint32_t umask, auto rowof, int col, bool kept) {
+            const int nu = __popc(umask);
+            int ro = nu;
+#pragma unroll
+            for (int o = 1; o < PG_WAVE; o <<= 1) {
+                const int t = __shfl_up(ro, o, PG_WAVE);
+                if (lane >= o) ro += t;
+            }
+            const int rtot = __shfl(ro, PG_WAVE - 1, PG_WAVE);
+            ro -= nu;
+            if (rtot == 0) return;
+            uint32_t mm = umask;
+            while (mm) {
+                const int g = __builtin_ctz(mm);
+                mm &= mm - 1;
+                rl[ro++] = (uint16_t)((rowof(g) << 6) | col);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < rtot; e += PG_WAVE) {
+                const int ent = rl[e], i = ent >> 6, j = ent & 63;
+                const uint64_t ki = kept ? kept_key[i] : chunk_key[i], kj = chunk_key[j];
+                const float b = dist_chain(X + (int64_t)key_id(ki) * ldx, X + (int64_t)key_id(kj) * ldx, d);
+                if (occludes(key_d2(ki), b, key_d2(kj), strict, at)) {
+                    if (kept)
+                        atomicOr(&occk_lds, 1ull << j);
+                    else
+                        atomicOr(&kill_lds[i], 1ull << j);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+        // mixed: decide a pair from its estimate when the bound allows;
+        // returns 1 (occludes), 0 (does not) or 2 (undecided)
+        auto decide = [&](float a, float c, float ni, float nj, float gv) -> int {
+            if (strict && !(a < c)) return 0;
+            const float bh = fmaxf(fmaf(-2.0f, gv, ni + nj), 0.0f);
+            const float e = pmix_e(pmx, ni, nj);
+            const float acc = pmx.ga * (ni + nj + 2.0f * fabsf(gv));
+            if (bh > pmix_hi(pmx, c, e, acc)) return 0;
+            if (!at.on && bh < pmix_lo(pmx, c, e, acc)) return 1;
+            return 2;
+        };
         // stage rows [0, nrows) of this round (candidates, then kept nodes at
         // 64..) for dimensions [c0, c0 + dc)
         auto stage = [&](int c0, int dc, int nrows) {
@@ -424,25 +576,37 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             auto cand_tile = [&](const pm_f32x16 &t, int rb, int cb) {
                 const int j = 32 * cb + l32;
                 const float cj = key_d2(chunk_key[j]), nj = cn[j];
+                uint32_t umask = 0;
 #pragma unroll
                 for (int g = 0; g < 16; ++g) {
                     const int i = 32 * rb + 8 * (g / 4) + 4 * h + (g % 4);
                     bool cnd = false;
-                    if (i < cm && j < cm && i < j) {
-                        const float b = fmaxf(fmaf(-2.0f, t[g], cn[i] + nj), 0.0f);
-                        cnd = occludes(key_d2(chunk_key[i]), b, cj, strict, at);
+                    if (i < cm && j < cm && i < j && ((pk >> i) & (pk >> j) & 1ull)) {
+                        ++n_skip;
+                    } else if (i < cm && j < cm && i < j) {
+                        ++n_test;
+                        if (MIX) {
+                            const int dv = decide(key_d2(chunk_key[i]), cj, cn[i], nj, t[g]);
+                            cnd = dv == 1;
+                            umask |= (dv == 2 ? 1u : 0u) << g;
+                        } else {
+                            const float b = fmaxf(fmaf(-2.0f, t[g], cn[i] + nj), 0.0f);
+                            cnd = occludes(key_d2(chunk_key[i]), b, cj, strict, at);
+                        }
                     }
                     const uint64_t bm = __ballot(cnd);
                     const int i0 = 32 * rb + 8 * (g / 4) + (g % 4);
                     if (lane == i0) killv |= (bm & 0xFFFFFFFFull) << (32 * cb);
                     if (lane == i0 + 4) killv |= (bm >> 32) << (32 * cb);
                 }
+                if (MIX) settle(umask, [&](int g) { return 32 * rb + 8 * (g / 4) + 4 * h + (g % 4); }, j, false);
             };
             cand_tile(t00, 0, 0);
             if (two) {
                 cand_tile(t01, 0, 1);
                 cand_tile(t11, 1, 1);
             }
+            if (MIX) killv |= kill_lds[lane];
         }
         // ---- occlusion by the nodes kept in earlier rounds (second pass)
         if (nk > 0) {
@@ -465,26 +629,39 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             auto kept_tile = [&](const pm_f32x16 &t, int cb) {
                 const int j = 32 * cb + l32;
                 const float cj = key_d2(chunk_key[j]), nj = cn[j];
+                uint32_t umask = 0;
 #pragma unroll
                 for (int g = 0; g < 16; ++g) {
                     const int k = 8 * (g / 4) + 4 * h + (g % 4);
                     bool cnd = false;
-                    if (k < nk && j < cm) {
-                        const float b = fmaxf(fmaf(-2.0f, t[g], kn[k] + nj), 0.0f);
-                        cnd = occludes(key_d2(kept_key[k]), b, cj, strict, at);
+                    if (k < nk && j < cm && ((kpk >> k) & (pk >> j) & 1ull)) {
+                        ++n_skip;
+                    } else if (k < nk && j < cm) {
+                        ++n_test;
+                        if (MIX) {
+                            const int dv = decide(key_d2(kept_key[k]), cj, kn[k], nj, t[g]);
+                            cnd = dv == 1;
+                            umask |= (dv == 2 ? 1u : 0u) << g;
+                        } else {
+                            const float b = fmaxf(fmaf(-2.0f, t[g], kn[k] + nj), 0.0f);
+                            cnd = occludes(key_d2(kept_key[k]), b, cj, strict, at);
+                        }
                     }
                     const uint64_t bm = __ballot(cnd);
                     occk |= ((bm & 0xFFFFFFFFull) | (bm >> 32)) << (32 * cb);
                 }
+                if (MIX) settle(umask, [&](int g) { return 8 * (g / 4) + 4 * h + (g % 4); }, j, true);
             };
             kept_tile(k0, 0);
             if (two) kept_tile(k1, 1);
+            if (MIX) occk |= occk_lds;
         }
         // ---- greedy scan of Alg. 3 over this round's candidates
         uint64_t dead = occk;
         for (int j = 0; j < cm; ++j) {
             if ((dead >> j) & 1ull) continue;
             dead |= readlane64(killv, j);
+            kpk |= ((pk >> j) & 1ull) << nk;
             if (lane == 0) kept_key[nk] = chunk_key[j];
             __builtin_amdgcn_wave_barrier();
             ++nk;
@@ -502,6 +679,17 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
         out_d2[u * R + lane] = have ? key_d2(k) : __int_as_float(0x7f800000);
     }
     if (lane == 0) out_deg[u] = nk;
+    if (k2p) {
+#pragma unroll
+        for (int o = 1; o < PG_WAVE; o <<= 1) {
+            n_skip += (unsigned long long)__shfl_xor((long long)n_skip, o, PG_WAVE);
+            n_test += (unsigned long long)__shfl_xor((long long)n_test, o, PG_WAVE);
+        }
+        if (lane == 0) {
+            atomicAdd(&k2p[0], n_skip);
+            atomicAdd(&k2p[1], n_test);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1302,6 +1490,18 @@ static pg_status check_prune(const pg_prune_params *p, int64_t n, int32_t C) {
         set_error("pg_prune: the pair_d2 table only serves the PRUNE stage alone");
         return PG_EINVAL;
     }
+    if (p->k2p_prev_ids && (!p->k2p_prev_deg || p->k2p_prev_R < 1 || p->k2p_prev_R > 64)) {
+        set_error("pg_prune: k2p_prev_ids needs k2p_prev_deg and 1 <= k2p_prev_R <= 64");
+        return PG_EINVAL;
+    }
+    if ((p->prune_ids_out != nullptr) != (p->prune_deg_out != nullptr)) {
+        set_error("pg_prune: prune_ids_out and prune_deg_out go together");
+        return PG_EINVAL;
+    }
+    if (p->precision != PG_FP32 && p->precision != PG_FP32_VALU) {
+        set_error("pg_prune: precision=%d must be PG_FP32 or PG_FP32_VALU", p->precision);
+        return PG_EINVAL;
+    }
     if (!(p->alpha_deg >= 0.0f && p->alpha_deg <= 180.0f)) {
         set_error("pg_prune: alpha_deg=%g must be in [0, 180]", (double)p->alpha_deg);
         return PG_EINVAL;
@@ -1558,21 +1758,55 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         exact16 = he[PX_NONINT] == 0 && maxabs <= 2048.0f &&
                   (maxnorm <= 4194304.0f || (he[PX_NEG] == 0 && maxnorm <= 8388608.0f));
     }
+    // float data: centred FP16 copy for the mixed tiles (the centroid is the
+    // entry point's too)
+    bool centroid_done = false, mix = false;
+    PruneMix pmx{};
+    if (!p->pair_d2 && !exact16 && p->precision != PG_FP32_VALU) {
+        hipLaunchKernelGGL(k_centroid_partial, dim3((unsigned)L.ncb), dim3(256), 0, st, X, n, d, ldx, cpart);
+        hipLaunchKernelGGL(k_centroid_final, dim3(1), dim3(256), 0, st, cpart, L.ncb, d, n, cen);
+        centroid_done = true;
+        unsigned int *exf = (unsigned int *)(w + L.exflags);
+        PG_HIP(hipMemsetAsync(exf, 0, sizeof(unsigned int) * 4, st));
+        hipLaunchKernelGGL(k_prune_prep_mixed, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 4096)), dim3(256), 0,
+                           st, X, ldx, d, L.d16, n, cen, x16, nrm, exf);
+        PG_HIP(hipGetLastError());
+        unsigned int he[4];
+        PG_HIP(hipMemcpyAsync(he, exf, sizeof(he), hipMemcpyDeviceToHost, st));
+        PG_HIP(hipStreamSynchronize(st));
+        float cmax;
+        memcpy(&cmax, &he[PX_MAXABS], 4);
+        if (cmax <= 32768.0f) {
+            mix = true;
+            const double u32 = 1.0 / 16777216.0;
+            pmx.on = 1;
+            pmx.un = (float)(1.0 / 2048.0 + 4.0 * u32);
+            pmx.ea = 2.98023224e-08f;  // half the FP16 subnormal spacing
+            pmx.gd = (float)((d + 4) * u32 * 1.01);
+            pmx.ga = (float)((2.0 * L.d16 + 16) * u32 * 1.01);
+            pmx.sqd = sqrtf((float)d);
+        }
+    }
     int32_t *s_ids = rev_stage ? p_ids : g_ids, *s_deg = rev_stage ? p_deg : g_deg;
     float *s_d2 = rev_stage ? p_d2 : g_d2;
     {
         TimedLaunch tl(ctx, K_PRUNE, (double)n * C * C / 2.0 * 3.0 * d);
-        if (exact16 && cand_d2)
-            hipLaunchKernelGGL(k_prune_mfma, dim3((unsigned)n), dim3(64), 0, st, x16, L.d16, nrm, n, cand_ids,
-                               cand_d2, C, (const int32_t *)nullptr, (const int64_t *)nullptr,
-                               (const int32_t *)nullptr, (const float *)nullptr, R, at,
-                               p->strict_ties, s_ids, s_d2, s_deg);
+        if ((exact16 || mix) && cand_d2)
+            hipLaunchKernelGGL(exact16 ? k_prune_mfma<false> : k_prune_mfma<true>, dim3((unsigned)n), dim3(64), 0,
+                               st, x16, L.d16, nrm, n, cand_ids, cand_d2, C, (const int32_t *)nullptr,
+                               (const int64_t *)nullptr, (const int32_t *)nullptr, (const float *)nullptr, R, at,
+                               p->strict_ties, s_ids, s_d2, s_deg, X, ldx, d, pmx, p->k2p_prev_ids,
+                               p->k2p_prev_deg, p->k2p_prev_R, p->k2p_counts);
         else
             hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, cand_ids, cand_d2, C,
                                (const int32_t *)nullptr, (const int64_t *)nullptr, (const int32_t *)nullptr,
                                (const float *)nullptr, R, at, p->strict_ties, p->pair_d2,
                                s_ids, s_d2, s_deg);
         PG_HIP(hipGetLastError());
+    }
+    if (p->prune_ids_out) {
+        PG_HIP(hipMemcpyAsync(p->prune_ids_out, s_ids, sizeof(int32_t) * n * R, hipMemcpyDeviceToDevice, st));
+        PG_HIP(hipMemcpyAsync(p->prune_deg_out, s_deg, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     }
     if (rev_stage) {
         const int64_t tot = n * R;
@@ -1586,10 +1820,11 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
                            p_deg, n, R, off, cnt, rev, rev_d2);
         PG_HIP(hipGetLastError());
         TimedLaunch tl(ctx, K_PRUNE, -1.0);
-        if (exact16)
-            hipLaunchKernelGGL(k_prune_mfma, dim3((unsigned)n), dim3(64), 0, st, x16, L.d16, nrm, n, p_ids, p_d2, R,
-                               p_deg, off, rev, rev_d2, R, at, p->strict_ties, g_ids, g_d2,
-                               g_deg);
+        if (exact16 || mix)
+            hipLaunchKernelGGL(exact16 ? k_prune_mfma<false> : k_prune_mfma<true>, dim3((unsigned)n), dim3(64), 0,
+                               st, x16, L.d16, nrm, n, p_ids, p_d2, R, p_deg, off, rev, rev_d2, R, at,
+                               p->strict_ties, g_ids, g_d2, g_deg, X, ldx, d, pmx, (const int32_t *)nullptr,
+                               (const int32_t *)nullptr, 0, (unsigned long long *)nullptr);
         else
             hipLaunchKernelGGL(k_prune, dim3((unsigned)n), dim3(64), 0, st, X, ldx, d, n, p_ids, p_d2, R, p_deg,
                                off, rev, rev_d2, R, at, p->strict_ties, (const float *)nullptr,
@@ -1597,8 +1832,10 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         PG_HIP(hipGetLastError());
     }
     // entry point
-    hipLaunchKernelGGL(k_centroid_partial, dim3((unsigned)L.ncb), dim3(256), 0, st, X, n, d, ldx, cpart);
-    hipLaunchKernelGGL(k_centroid_final, dim3(1), dim3(256), 0, st, cpart, L.ncb, d, n, cen);
+    if (!centroid_done) {
+        hipLaunchKernelGGL(k_centroid_partial, dim3((unsigned)L.ncb), dim3(256), 0, st, X, n, d, ldx, cpart);
+        hipLaunchKernelGGL(k_centroid_final, dim3(1), dim3(256), 0, st, cpart, L.ncb, d, n, cen);
+    }
     hipLaunchKernelGGL(k_argmin_center, dim3((unsigned)L.nab), dim3(256), 0, st, X, n, d, ldx, cen, apd,
                        api);
     hipLaunchKernelGGL(k_argmin_final, dim3(1), dim3(256), 0, st, apd, api, L.nab, ep);

@@ -104,6 +104,12 @@ def sample_ids(n: int, count: int, seed: int, sub: int = 9) -> np.ndarray:
     return np.sort(_rng(seed, sub).choice(n, size=count, replace=False)).astype(np.int32)
 
 
+def entry_sample(n: int, count: int, seed: int = 21) -> np.ndarray:
+    """count distinct ids in [0, n), sorted: the seeded entering points that a
+    search takes beside the graph's entry point (the same set on every side)."""
+    return sample_ids(n, count, seed, sub=15)
+
+
 def random_candidates(n: int, C: int, seed: int, sub: int = 11) -> np.ndarray:
     """n x C candidate ids drawn uniformly from [0, n) (repeats and self allowed)."""
     return _rng(seed, sub).integers(0, n, size=(n, C)).astype(np.int32)

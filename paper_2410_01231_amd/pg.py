@@ -44,7 +44,9 @@ class KnnStats(ctypes.Structure):
 
 class PruneParams(ctypes.Structure):
     _fields_ = [("R", c_int32), ("alpha_deg", c_float), ("stages", c_uint32),
-                ("strict_ties", c_int32), ("pair_d2", c_void_p)]
+                ("strict_ties", c_int32), ("pair_d2", c_void_p), ("precision", c_int32),
+                ("k2p_prev_ids", c_void_p), ("k2p_prev_deg", c_void_p), ("k2p_prev_R", c_int32),
+                ("k2p_counts", c_void_p), ("prune_ids_out", c_void_p), ("prune_deg_out", c_void_p)]
 
 
 class SearchParams(ctypes.Structure):
@@ -57,7 +59,7 @@ class SearchParams(ctypes.Structure):
 EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
            "pg_ctx_kernel_time", "pg_ctx_reset_timing", "pg_knn_build_workspace", "pg_knn_build",
            "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search", "pg_hnsw_levels",
-           "pg_half_rows", "pg_knn_build_noalloc"]
+           "pg_half_rows", "pg_knn_build_noalloc", "pg_quality_examination"]
 
 _lib = None
 
@@ -84,6 +86,8 @@ def load_library(path: str = LIB_PATH):
                                  P, P, POINTER(KnnStats)]
     lib.pg_knn_build_noalloc.argtypes = [P, P, c_int64, c_int32, c_int64, POINTER(KnnParams), P, P,
                                          POINTER(KnnStats)]
+    lib.pg_quality_examination.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, c_int32, P, c_int64,
+                                           P, P, P, P]
     lib.pg_exact_knn.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int64, c_int64, P, c_int32,
                                  P, P]
     lib.pg_prune_workspace.argtypes = [POINTER(PruneParams), c_int64, c_int32, c_int32,
@@ -278,11 +282,16 @@ def exact_knn(X, Q, k, exclude=None, ctx=None):
 
 
 def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair_d2=None,
-          cand_d2=None, ctx=None):
+          cand_d2=None, precision=FP32, k2p_prev=None, k2p_counts=None, prune_out=False, ctx=None):
     """Refinement of Alg. 2: returns dict(ids, d2, deg, ep, roots).
 
     cand_d2 (optional, same shape as cand): the canonical squared distances of
-    the candidates, e.g. the d2 output of knn_build."""
+    the candidates, e.g. the d2 output of knn_build.  k2p_prev (optional pair
+    (ids, deg)): the PRUNE-stage lists of the previous round with the same
+    alpha (K2P, Section 5.4; the graph is unchanged); k2p_counts (optional
+    int64 device tensor of 2) is added the pairs skipped and tested.  With
+    prune_out the dict also holds this call's PRUNE-stage lists
+    ("prune_ids", "prune_deg"), the next round's k2p_prev."""
     lib = load_library()
     X = _dev_f32(X, "X")
     cand = _dev_i32(cand, "cand")
@@ -297,8 +306,26 @@ def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair
         tab = pair_d2.contiguous()
         if tab.dtype != torch.float32 or tuple(tab.shape) != (n, C + 1, C + 1):
             raise ValueError("pair_d2 must be float32 of shape (n, C+1, C+1)")
+    pi = pd = None
+    if prune_out:
+        pi = torch.empty((n, R), dtype=torch.int32, device=X.device)
+        pd = torch.empty(n, dtype=torch.int32, device=X.device)
+    kp_ids = kp_deg = None
+    if k2p_prev is not None:
+        kp_ids, kp_deg = _dev_i32(k2p_prev[0], "k2p ids"), _dev_i32(k2p_prev[1], "k2p deg")
+        if kp_ids.dim() != 2 or kp_ids.shape[0] != n or kp_deg.numel() != n:
+            raise ValueError("k2p_prev must be an n x r id tensor and n lengths")
+    if k2p_counts is not None and (k2p_counts.dtype != torch.int64 or k2p_counts.numel() < 2
+                                   or not k2p_counts.is_cuda):
+        raise ValueError("k2p_counts must be a CUDA int64 tensor of 2")
     p = PruneParams(R=R, alpha_deg=float(alpha_deg), stages=stages, strict_ties=int(bool(strict_ties)),
-                    pair_d2=tab.data_ptr() if tab is not None else None)
+                    pair_d2=tab.data_ptr() if tab is not None else None, precision=precision,
+                    k2p_prev_ids=kp_ids.data_ptr() if kp_ids is not None else None,
+                    k2p_prev_deg=kp_deg.data_ptr() if kp_deg is not None else None,
+                    k2p_prev_R=kp_ids.shape[1] if kp_ids is not None else 0,
+                    k2p_counts=k2p_counts.data_ptr() if k2p_counts is not None else None,
+                    prune_ids_out=pi.data_ptr() if pi is not None else None,
+                    prune_deg_out=pd.data_ptr() if pd is not None else None)
     ws_bytes = c_size_t()
     _check(lib.pg_prune_workspace(ctypes.byref(p), n, d, C, ctypes.byref(ws_bytes)), "workspace")
     ws = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=X.device)
@@ -313,7 +340,10 @@ def prune(X, cand, R, alpha_deg=60.0, stages=STAGES_ALL, strict_ties=False, pair
                         _ptr(cand_d2) if cand_d2 is not None else None, C, ctypes.byref(p),
                         _ptr(ws), ws_bytes.value, _ptr(g_ids), _ptr(g_d2), _ptr(g_deg), _ptr(ep),
                         _ptr(roots), ctypes.byref(nroots)), "pg_prune")
-    return {"ids": g_ids, "d2": g_d2, "deg": g_deg, "ep": ep, "roots": roots[:nroots.value]}
+    out = {"ids": g_ids, "d2": g_d2, "deg": g_deg, "ep": ep, "roots": roots[:nroots.value]}
+    if prune_out:
+        out["prune_ids"], out["prune_deg"] = pi, pd
+    return out
 
 
 def half_rows(X, ctx=None):
@@ -406,15 +436,21 @@ def search_self(X, g_ids, g_deg, k, L, record=None, pool_out=False, counts=None,
 
 
 def opt_kcna(X, cand, k, L, M, alpha_deg, cand_d2=None, record=None, return_pool=False, counts=None,
-             x16=None, ctx=None):
+             x16=None, k2p_prev=None, k2p_counts=None, return_prune=False, ctx=None):
     """OptKCNA (Alg. 5): the alpha-PG of the candidate lists (prune with M and
     alpha, reverse re-prune, connect), then a search from every point on it.
     Returns the new candidate lists (ids, d2), n x k, and with return_pool the
-    search pools too (the P2K record of the next round)."""
-    g = prune(X, cand, M, alpha_deg=alpha_deg, cand_d2=cand_d2, ctx=ctx)
+    search pools too (the P2K record of the next round).  k2p_prev: the
+    previous round's PRUNE-stage lists (K2P, Section 5.4); with return_prune
+    this round's are appended to the result (the next round's k2p_prev)."""
+    g = prune(X, cand, M, alpha_deg=alpha_deg, cand_d2=cand_d2, k2p_prev=k2p_prev, k2p_counts=k2p_counts,
+              prune_out=return_prune, ctx=ctx)
     r = search_self(X, g["ids"], g["deg"], k, L, record=record, pool_out=return_pool, counts=counts,
                     x16=x16, ctx=ctx)
-    return r if return_pool else (r[0], r[1])
+    r = r if return_pool else (r[0], r[1])
+    if return_prune:
+        r = tuple(r) + ((g["prune_ids"], g["prune_deg"]),)
+    return r
 
 
 def quality_sample_size(n, eps, l=1):
@@ -425,31 +461,65 @@ def quality_sample_size(n, eps, l=1):
     return int(math.ceil((8.0 + 2.0 * eps) * l * math.log(n) / (eps * eps)))
 
 
-def quality_examination(X, cand, k, sample, ctx=None):
-    """Estimated k-CNA quality of the candidate lists (Section 5.2): the mean
-    over the sampled nodes u of |C(u)[:k] & N*_k(u)| / k, the exact k nearest
-    other points N*_k coming from the brute-force kernel."""
+def quality_examination_async(X, cand, k, sample, ctx=None):
+    """Enqueue the quality examination of Section 5.2 on the context's stream
+    (pg_quality_examination): returns (estimate, hits) device tensors, the
+    estimate being one float64 (the mean over the sampled nodes u of
+    |C(u)[:k] & N*_k(u)| / k) and hits the per-node counts.  Read them after
+    the context's stream has finished the call."""
+    lib = load_library()
     X = _dev_f32(X, "X")
     cand = _dev_i32(cand, "cand")
-    sample = _dev_i32(torch.as_tensor(sample).reshape(1, -1).to(X.device), "sample").reshape(-1)
-    rows = sample.long()
-    gt, _ = exact_knn(X, X[rows].contiguous(), k, exclude=sample, ctx=ctx)
-    c = cand[rows, :k]
-    hit = ((c.unsqueeze(2) == gt.unsqueeze(1)).any(2) & (c >= 0)).sum()
-    return float(hit.item()) / (k * sample.numel())
+    n, d = X.shape
+    sample = _dev_i32(torch.as_tensor(sample).reshape(-1).to(X.device), "sample")
+    ns = sample.numel()
+    exact_ids = torch.empty((ns, k), dtype=torch.int32, device=X.device)
+    exact_d2 = torch.empty((ns, k), dtype=torch.float32, device=X.device)
+    hits = torch.empty(ns, dtype=torch.int32, device=X.device)
+    est = torch.empty(1, dtype=torch.float64, device=X.device)
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_quality_examination(ctx.handle, _ptr(X), n, d, X.stride(0), _ptr(cand), cand.shape[1], k,
+                                      _ptr(sample), ns, _ptr(exact_ids), _ptr(exact_d2), _ptr(hits),
+                                      _ptr(est)), "pg_quality_examination")
+    return est, hits
+
+
+def quality_examination(X, cand, k, sample, ctx=None):
+    """Estimated k-CNA quality of the candidate lists (Section 5.2), computed
+    by pg_quality_examination; waits for the result."""
+    ctx = ctx or context(X.device.index)
+    est, _ = quality_examination_async(X, cand, k, sample, ctx=ctx)
+    ctx.stream.synchronize()
+    return float(est.item())
+
+
+_side_contexts = {}
+
+
+def _side_context(device):
+    """A context on a second stream of the device (default priority), for work
+    that overlaps the main stream's (the quality examination)."""
+    if device not in _side_contexts:
+        _side_contexts[device] = Context(device, torch.cuda.Stream(device=device))
+    return _side_contexts[device]
 
 
 def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0, delta=0.001,
-             target=None, sample=None, p2k=False, counts=None, half=True, ctx=None, **knn_kw):
+             target=None, sample=None, p2k=False, counts=None, half=True, k2p=False, k2p_counts=None,
+             ctx=None, **knn_kw):
     """IterNSG (Alg. 6): NN-Descent lists, rounds of OptKCNA with angle
     alpha_deg, then the refinement of Alg. 2 with RNG pruning.  Without
     `target` it runs `iterations` rounds; with `target` the quality
     examination on the nodes `sample` runs before each round and the rounds
-    stop once the estimate reaches it (or after `iterations`).  Returns the
+    stop once the estimate reaches it (or after `iterations`).  The
+    examination runs on a second stream, overlapping the round that follows
+    it; that round is dropped when the estimate reaches the target.  Returns the
     graph dict of prune() plus the final candidate lists ("cand", "cand_d2"),
     the rounds run, the estimates and the kNN statistics.  With p2k, every
     round's self-search reuses the distances recorded in the previous round's
-    pools (Section 5.4, P2K); the graph is the same.  counts (optional int64
+    pools (Section 5.4, P2K); the graph is the same.  With k2p, every round's
+    prune skips the pairs the previous round's prune settled (Section 5.4,
+    K2P; k2p_counts as in prune()); the graph is the same.  counts (optional int64
     device tensor of 2) is added the distances the searches computed and
     reused.  With half (the default), the searches gather rows from an FP16
     copy of X whenever that copy is exact (same results)."""
@@ -459,17 +529,39 @@ def iter_nsg(X, K, R, k, L, alpha_deg, iterations, S=None, max_iters=12, seed=0,
     if half and iterations > 0:
         h, exact = half_rows(X, ctx=ctx)
         x16 = h if exact else None
+    ctx = ctx or context(X.device.index)
+    side, prev_prune = None, None
     while rounds < iterations:
+        pending = None
         if target is not None:
-            quality.append(quality_examination(X, cand, k, sample, ctx=ctx))
+            # the examination of the current lists runs on a stream of its own
+            # while the next round runs speculatively on the context's stream;
+            # the round is dropped when the estimate reaches the target, so the
+            # rounds and lists are those of examining first
+            if side is None:
+                side = _side_context(X.device.index)
+            ev = torch.cuda.Event()
+            ev.record(ctx.stream)
+            side.stream.wait_event(ev)
+            with torch.cuda.stream(side.stream):
+                est, _ = quality_examination_async(X, cand, k, sample, ctx=side)
+            pending = (est, cand)  # cand stays referenced until the estimate is read
+        res = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, record=record if p2k else None,
+                       return_pool=p2k, counts=counts, x16=x16, k2p_prev=prev_prune if k2p else None,
+                       k2p_counts=k2p_counts, return_prune=k2p, ctx=ctx)
+        nc, nd = res[0], res[1]
+        if p2k:
+            pi, pd = res[2], res[3]
+        if pending is not None:
+            side.stream.synchronize()
+            quality.append(float(pending[0].item()))
             if quality[-1] >= target:
                 break
+        cand, cd2 = nc, nd
         if p2k:
-            cand, cd2, pi, pd = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, record=record,
-                                         return_pool=True, counts=counts, x16=x16, ctx=ctx)
             record = (pi, pd)
-        else:
-            cand, cd2 = opt_kcna(X, cand, k, L, R, alpha_deg, cand_d2=cd2, counts=counts, x16=x16, ctx=ctx)
+        if k2p:
+            prev_prune = res[-1]
         rounds += 1
     g = prune(X, cand, R, cand_d2=cd2, ctx=ctx)
     g["cand"], g["cand_d2"], g["knn_stats"] = cand, cd2, st

@@ -25,6 +25,7 @@ pytestmark = pytest.mark.gpu
 
 N, NQ, D, K, S, R, T = 1_000_000, 10_000, 128, 64, 32, 32, 12
 L_BENCH = 192
+E_BENCH = 1024
 SAMPLE = 200
 
 
@@ -135,7 +136,9 @@ def test_entry_point_and_connect(built, oracle):
 
 def test_sampled_search_and_batch_recall(built, oracle):
     pg, X, Q, g = built["pg"], built["X"], built["Q"], built["g"]
-    entries = np.concatenate([g["ep"], g["roots"]]).astype(np.int32)
+    # the benchmark's entering points on this set: ep and 1,024 seeded ids
+    from paper_2410_01231_amd import datagen
+    entries = np.concatenate([g["ep"], datagen.entry_sample(N, E_BENCH)]).astype(np.int32)
     ids, d2 = pg.search(built["Xd"], built["gd"]["ids"], built["gd"]["deg"], built["Qd"],
                         dev(entries), 10, L_BENCH)
     ids = host(ids)

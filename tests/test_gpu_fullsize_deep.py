@@ -11,7 +11,8 @@ oracle computes one by one:
 * sampled PRUNE rows equal the oracle's Alg. 3 on the same candidates (float
   data: a row may differ only through a near-tie, at most 1 in 100);
 * sampled searches on the GPU graph equal the oracle's on the same graph
-  (same allowance); batch recall at L = 1024 is reported (0.949 measured).
+  (differences only through near-ties); batch recall reaches 0.95 at the
+  benchmark's beam from ep and the connect roots.
 """
 import numpy as np
 import pytest
@@ -22,7 +23,7 @@ import neartie
 pytestmark = pytest.mark.gpu
 
 N, NQ, D, K, R, S, T = 10_000_000, 10_000, 96, 64, 32, 32, 12
-L_BENCH = 1024
+L_BENCH = 1536
 SAMPLE = 60
 
 
@@ -95,17 +96,30 @@ def test_sampled_prune_rows(built, oracle):
 
 def test_sampled_search_and_batch_recall(built, oracle):
     pg, X, Q, g = built["pg"], built["X"], built["Q"], built["g"]
+    # the benchmark's entering points on this set: ep and every connect root
+    # (one per component of the pruned graph; no bounded seeded set reaches
+    # the recall target on 1,000 separated clusters)
     entries = np.concatenate([g["ep"], g["roots"]]).astype(np.int32)
     ids, _ = pg.search(built["Xd"], built["gd"]["ids"], built["gd"]["deg"], built["Qd"], dev(entries), 10,
                        L_BENCH)
     ids = host(ids)
     qs = np.random.default_rng(24).choice(NQ, size=30, replace=False)
     rid, _, _ = oracle.search(X, g["ids"], g["deg"], Q[qs], entries, 10, L_BENCH)
-    same = sum(list(a) == list(b) for a, b in zip(ids[qs], rid))
+    same, unexplained = 0, []
+    for q, a, b in zip(qs.tolist(), ids[qs], rid):
+        if list(a) == list(b):
+            same += 1
+            continue
+        # a differing search must come from a comparison within the FP32 band
+        rep, gap = neartie.search_replay(X, g["ids"], g["deg"], Q[q], entries, 10, L_BENCH)
+        assert rep == list(b), q  # the FP64 replay is the oracle's Alg. 1
+        print(f"[fullsize-deep] search {q} differs; smallest decision gap {gap:.3e}", flush=True)
+        if gap > neartie.chain_band(X.shape[1]):
+            unexplained.append(q)
     print(f"[fullsize-deep] sampled searches identical {same}/30", flush=True)
-    assert same >= 29
+    assert not unexplained
     gt, _ = pg.exact_knn(built["Xd"], built["Qd"], 10)
     gt = host(gt)
     rec = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids.tolist(), gt.tolist())])
     print(f"[fullsize-deep] recall@10 at L={L_BENCH}: {rec:.4f}", flush=True)
-    assert rec >= 0.94
+    assert rec >= 0.95

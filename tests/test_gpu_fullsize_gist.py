@@ -101,15 +101,27 @@ def test_sampled_prune_rows(built, oracle):
 
 def test_sampled_search_and_batch_recall(built, oracle):
     pg, X, Q, g = built["pg"], built["X"], built["Q"], built["g"]
-    entries = np.concatenate([g["ep"], g["roots"]]).astype(np.int32)
+    # the benchmark's entering points on this set: ep and 256 seeded ids
+    from paper_2410_01231_amd import datagen
+    entries = np.concatenate([g["ep"], datagen.entry_sample(N, 256)]).astype(np.int32)
     ids, _ = pg.search(built["Xd"], built["gd"]["ids"], built["gd"]["deg"], built["Qd"], dev(entries), 10,
                        L_BENCH)
     ids = host(ids)
     qs = np.random.default_rng(24).choice(NQ, size=30, replace=False)
     rid, _, _ = oracle.search(X, g["ids"], g["deg"], Q[qs], entries, 10, L_BENCH)
-    same = sum(list(a) == list(b) for a, b in zip(ids[qs], rid))
+    same, unexplained = 0, []
+    for q, a, b in zip(qs.tolist(), ids[qs], rid):
+        if list(a) == list(b):
+            same += 1
+            continue
+        # a differing search must come from a comparison within the FP32 band
+        rep, gap = neartie.search_replay(X, g["ids"], g["deg"], Q[q], entries, 10, L_BENCH)
+        assert rep == list(b), q  # the FP64 replay is the oracle's Alg. 1
+        print(f"[fullsize-gist] search {q} differs; smallest decision gap {gap:.3e}", flush=True)
+        if gap > neartie.chain_band(X.shape[1]):
+            unexplained.append(q)
     print(f"[fullsize-gist] sampled searches identical {same}/30", flush=True)
-    assert same >= 29
+    assert not unexplained
     gt, _ = pg.exact_knn(built["Xd"], built["Qd"], 10)
     gt = host(gt)
     rec = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids.tolist(), gt.tolist())])

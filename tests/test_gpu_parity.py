@@ -334,6 +334,35 @@ def test_prune_given_distances_match_computed_on_float_data(pg, datagen):
         assert torch.equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("law,alpha,strict", [("gist", 60.0, False), ("gist", 65.0, False),
+                                               ("deep", 60.0, True), ("deep", 89.0, False),
+                                               ("sift", 60.0, False), ("sift", 120.0, False)])
+def test_prune_mixed_tiles_equal_chains_on_float_data(pg, datagen, law, alpha, strict):
+    # float data: the MFMA prune on the centred FP16 copy decides only what
+    # its error bound allows and takes the FP32 chain for the rest, so its
+    # graph equals the all-chain prune, for every stage (the reverse unions
+    # run on both kernels too); duplicated rows give zero distances and ties
+    log("mixed prune", law, alpha, strict)
+    if law == "gist":
+        X, _ = datagen.gist_like(3000, 0, d=240, n_clusters=10, seed=5)
+    elif law == "deep":
+        X, _ = datagen.unit_mixture(4000, 0, d=96, n_clusters=20, seed=6)
+    else:
+        X, _ = datagen.sift_like(3000, 0, d=128, n_clusters=20, seed=7)
+        X = X * np.float32(0.37) + np.float32(0.011)
+    X = np.ascontiguousarray(X)
+    X[200:260] = X[0:60]
+    Xd = dev(X)
+    ids, d2, _ = pg.knn_build(Xd, 48, S=24, max_iters=6, seed=2)
+    # the prune stages (connect may overflow at wide angles on clustered data)
+    st = pg.STAGE_PRUNE | pg.STAGE_REVERSE
+    a = pg.prune(Xd, ids, 24, alpha_deg=alpha, strict_ties=strict, cand_d2=d2, stages=st)
+    b = pg.prune(Xd, ids, 24, alpha_deg=alpha, strict_ties=strict, cand_d2=d2, precision=pg.FP32_VALU,
+                 stages=st)
+    for k in ("ids", "d2", "deg", "ep"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_prune_table_hook_float_bit_exact(pg, oracle, datagen):
     # identical candidate lists and identical float32 distances -> identical edges
     X, _ = datagen.unit_mixture(400, 0, d=16, n_clusters=5, seed=6)
@@ -666,12 +695,40 @@ def test_iter_nsg_bit_exact(pg, oracle, datagen, nn, d, nc, sig, K, S, k, L, R, 
         assert torch.equal(g[key], gp[key]), key  # P2K leaves the graph unchanged
     log("P2K computed / reused", host(cnt))
     assert host(cnt)[1] > 0
+    kc = torch.zeros(2, dtype=torch.int64, device="cuda")
+    gk = pg.iter_nsg(dev(X), K, R, k, L, alpha, 2, S=S, max_iters=8, seed=3, stop_updates=stop, k2p=True,
+                     k2p_counts=kc)
+    for key in ("ids", "d2", "deg", "ep", "roots", "cand", "cand_d2"):
+        assert torch.equal(g[key], gk[key]), key  # K2P leaves the graph unchanged
+    log("K2P pairs skipped / tested", host(kc))
+    assert host(kc)[0] > 0
     r = oracle.iter_nsg(X, K, S, 8, 3, stop, k, L, R, alpha, 2)
     assert np.array_equal(host(g["cand"]), r["cand"])
     assert np.array_equal(host(g["ids"]), r["ids"])
     assert np.array_equal(host(g["deg"]), r["deg"])
     assert np.array_equal(host(g["roots"]), r["roots"])
     assert int(host(g["ep"])[0]) == r["ep"]
+
+
+@pytest.mark.parametrize("law", ["gist", "deep"])
+def test_k2p_on_float_data_leaves_the_graph_unchanged(pg, datagen, law):
+    # K2P in the mixed-precision prune (Section 5.4, Exp. 6): skipping the
+    # pairs of candidates that both stayed in the previous round's list gives
+    # the same graph, three OptKCNA rounds on float data
+    if law == "gist":
+        X, _ = datagen.gist_like(3000, 0, d=240, n_clusters=10, seed=12)
+    else:
+        X, _ = datagen.unit_mixture(4000, 0, d=96, n_clusters=20, seed=13)
+    Xd = dev(X)
+    stop = int(0.001 * len(X) * 24)
+    g = pg.iter_nsg(Xd, 24, 32, 24, 48, 65.0, 3, S=12, max_iters=6, seed=2, stop_updates=stop)
+    kc = torch.zeros(2, dtype=torch.int64, device="cuda")
+    gk = pg.iter_nsg(Xd, 24, 32, 24, 48, 65.0, 3, S=12, max_iters=6, seed=2, stop_updates=stop, k2p=True,
+                     k2p_counts=kc)
+    for key in ("ids", "d2", "deg", "ep", "roots", "cand", "cand_d2"):
+        assert torch.equal(g[key], gk[key]), key
+    log(law, "K2P pairs skipped / tested", host(kc))
+    assert host(kc)[0] > 0
 
 
 def test_quality_examination_and_stopping_rule(pg, oracle, datagen):
@@ -683,6 +740,17 @@ def test_quality_examination_and_stopping_rule(pg, oracle, datagen):
     cand, _, _, _ = oracle.nndescent(X, K, S, 2, 3)
     assert pg.quality_examination(dev(X), dev(cand), k, sample) == \
         oracle.quality_examination(X, cand, k, sample)
+    # per-node counts through the C call, against the oracle's brute force
+    est, hits = pg.quality_examination_async(dev(X), dev(cand), 10, sample)
+    gt, _ = oracle.exact_knn(X, X[sample], 10, exclude=sample)
+    want = [len(set(cand[u, :10].tolist()) & set(t)) for u, t in zip(sample.tolist(), gt.tolist())]
+    assert host(hits).tolist() == want
+    assert float(est.item()) == sum(want) / (10 * len(sample))
+    # a sample id outside [0, n) is reported, not read
+    bad = sample.copy()
+    bad[7] = n + 5
+    est, hits = pg.quality_examination_async(dev(X), dev(cand), 10, bad)
+    assert np.isnan(float(est.item())) and int(host(hits)[7]) == -1
     stop = int(0.001 * n * K)
     r = oracle.iter_nsg(X, K, S, 3, 3, stop, k, L, R, 65.0, 3, target=0.995, sample=sample)
     g = pg.iter_nsg(dev(X), K, R, k, L, 65.0, 3, S=S, max_iters=3, seed=3, stop_updates=stop,
