@@ -50,7 +50,7 @@ WORKLOADS = {
     # GIST-shaped precision mode: 1M x 960 float data (Gamma(2, 0.05) + 50 offsets);
     # the FP16 path is the mixed one (16-bit tiles prefilter, FP32 recheck)
     "gist1m": dict(n=1_000_000, nq=1_000, d=960, K=64, R=32, S=32, iters=12, seed=3, paths="fp32,fp16",
-                   cpu_sample=10_000,
+                   cpu_sample=30_000,
                    gen="gist_like", desc="gist-like 1Mx960 Gamma(2,0.05)+50 offsets, K=64 R=32 FP32 storage"),
     # Deep-shaped: 10M x 96 unit vectors, 1000 Gaussian clusters; BF16 tiles with
     # FP32 recheck against plain FP32

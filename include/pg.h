@@ -170,6 +170,24 @@ pg_status pg_knn_build(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_
                        const pg_knn_params *p, void *ws, size_t ws_bytes,
                        int32_t *knn_ids, float *knn_d2, pg_knn_stats *stats);
 
+/* Batched builds (several collections in one build; the batching pattern of
+ * serving many uneven collections).  Collection c is rows
+ * [offsets[c], offsets[c + 1]) of X (host offsets, offsets[0] = 0,
+ * offsets[ncoll] = n, every collection more than K rows, same d).  Every
+ * kernel of an iteration runs once over all collections; each collection
+ * draws with its own local ids and stops on its own rule (an iteration that
+ * changes at most stop_updates[c] of its entries, host array), so its lists
+ * (knn_ids in ids local to the collection, knn_d2) equal those of
+ * pg_knn_build on its rows alone with stop_updates[c].  iters (host, ncoll,
+ * optional) receives each collection's iterations.  p->stop_updates and
+ * p->exact are not used (exact != 0 is an error). */
+pg_status pg_knn_build_batch_workspace(const pg_knn_params *p, int64_t n, int32_t d, int32_t ncoll,
+                                       size_t *bytes);
+pg_status pg_knn_build_batch(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                             const int64_t *offsets, int32_t ncoll, const int64_t *stop_updates,
+                             const pg_knn_params *p, void *ws, size_t ws_bytes, int32_t *knn_ids,
+                             float *knn_d2, int32_t *iters);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): pg_knn_build
  * with its workspace taken from a static device array of PG_NOALLOC_WS_BYTES

@@ -10,11 +10,15 @@
 //   k_rev_scatter wave per node: CSR reverse lists
 //   k_build_join  wave per node: keep the S smallest-hash reverse entries,
 //                 form new(u) and old(u) (the join set of u)
-//   k_join        workgroup per source u: the join set's vectors are staged
-//                 through LDS in 32-dim chunks; every new-new and new-old pair
-//                 gets its squared distance in registers (4x4 micro-tiles);
+//   k_join        wave per source u: the join set's vectors are staged
+//                 through LDS in 16-dim chunks; every new-new and new-old pair
+//                 gets its squared distance in registers (micro-tiles);
 //                 a pair is proposed to each end whose K-th key it beats and
-//                 appended to that end's proposal bucket
+//                 appended to that end's proposal bucket.  k_join_mfma runs
+//                 the same join as MFMA Gram tiles on data where the norm
+//                 expansion is exact; k_join_hybrid, on float data, takes
+//                 16-bit MFMA estimates and the exact chains of the pairs
+//                 the estimates cannot settle
 //   k_merge       wave per node: each list becomes the K smallest distinct
 //                 keys of (list U bucket) by wave64 bitonic sort and merge
 // Sources are joined in several passes (chunks) per iteration; each pass is
@@ -90,6 +94,24 @@ __global__ __launch_bounds__(NSTRIPE) void k_counters_clear(unsigned long long *
 }
 
 // ---------------------------------------------------------------------------
+// Collections.  A build may hold several collections, each a contiguous range
+// of rows of X; every random draw then uses ids local to the node's
+// collection, so each collection's lists are those of a build of its rows
+// alone (ids, ties and hashes all shift by the same base).  of == nullptr
+// means one collection of all n rows.  A frozen collection (its stop rule
+// met) takes no samples, so its lists no longer change.
+// ---------------------------------------------------------------------------
+struct Segs {
+    const int32_t *of;      // n: collection of each node
+    const int64_t *off;     // ncoll + 1: first row of each collection
+    const uint8_t *frozen;  // ncoll
+};
+
+__device__ __forceinline__ int64_t seg_base(const Segs &sg, int64_t u) {
+    return sg.of ? sg.off[sg.of[u]] : 0;
+}
+
+// ---------------------------------------------------------------------------
 // init: K distinct random neighbours, hash4(seed, 0, u, attempt) mod (n-1)
 // ---------------------------------------------------------------------------
 // Rows come from X, or, when X16 is given (an exact FP16 copy, rows of d16
@@ -100,7 +122,7 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
                                               int64_t n, int K, uint64_t seed,
                                               uint64_t *__restrict__ keys,
                                               uint64_t *__restrict__ newm,
-                                              uint64_t *__restrict__ insm) {
+                                              uint64_t *__restrict__ insm, Segs sg) {
     constexpr int IDC = 32, IST = IDC + 4;  // dims per LDS chunk, row stride (floats)
     __shared__ int32_t acc_s[4][PG_WAVE];
     __shared__ __align__(16) float rows_s[4][(PG_WAVE + 1) * IST];
@@ -111,10 +133,12 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
     int32_t *acc = acc_s[w];
     int na = 0;
     uint64_t j0 = 0;
-    const uint64_t nm1 = (uint64_t)(n - 1);
+    const int64_t base = seg_base(sg, u);
+    const uint64_t ul = (uint64_t)(u - base);
+    const uint64_t nm1 = (uint64_t)((sg.of ? sg.off[sg.of[u] + 1] - base : n) - 1);
     while (na < K) {
-        const uint64_t r = hash4(seed, 0, (uint64_t)u, j0 + (uint64_t)lane) % nm1;
-        const int32_t c = (int32_t)(r >= (uint64_t)u ? r + 1 : r);
+        const uint64_t r = hash4(seed, 0, ul, j0 + (uint64_t)lane) % nm1;
+        const int32_t c = (int32_t)(base + (int64_t)(r >= ul ? r + 1 : r));
         bool dup = false;
         for (int i = 0; i < na; ++i) dup |= (acc[i] == c);
         for (int i = 0; i < PG_WAVE - 1; ++i) {
@@ -193,16 +217,24 @@ __global__ __launch_bounds__(256) void k_sample(const uint64_t *__restrict__ key
                                                 int32_t *__restrict__ rn_cnt,
                                                 int32_t *__restrict__ ro_cnt,
                                                 int32_t *__restrict__ nf_slot,
-                                                int32_t *__restrict__ of_slot) {
+                                                int32_t *__restrict__ of_slot, Segs sg) {
     const int lane = lane_id();
     const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (u >= n) return;
+    if (sg.of && sg.frozen[sg.of[u]]) {
+        if (lane == 0) {
+            nf_c[u] = 0;
+            of_c[u] = 0;
+        }
+        return;
+    }
+    const int64_t base = seg_base(sg, u);
     const uint64_t nm = newm[u];
     const uint64_t key = lane < K ? keys[u * K + lane] : KEY_INF;
     const int32_t id = key_id(key);
     const bool isnew = lane < K && ((nm >> lane) & 1ull);
     const bool isold = lane < K && !isnew;
-    uint64_t sk = isnew ? sample_key(hash4(seed, stream, (uint64_t)u, (uint64_t)id), id) : KEY_INF;
+    uint64_t sk = isnew ? sample_key(hash4(seed, stream, (uint64_t)(u - base), (uint64_t)(id - base)), id) : KEY_INF;
     int pos = lane;
     wave_sort(sk, pos);
     const bool sel = lane < S && sk != KEY_INF;
@@ -259,7 +291,7 @@ __global__ __launch_bounds__(256) void k_rev_scatter(int64_t n, const int32_t *_
 // a list of at most S entries is selected whole (ids only, in list order).
 __device__ __forceinline__ uint64_t select_reverse(int64_t v, const int64_t *__restrict__ off,
                                                    const int32_t *__restrict__ list,
-                                                   uint64_t seed, uint64_t stream, int S) {
+                                                   uint64_t seed, uint64_t stream, int S, int64_t base) {
     const int lane = lane_id();
     const int64_t beg = off[v], cnt = off[v + 1] - beg;
     if (cnt <= S)  // every entry is selected; callers use the ids only
@@ -270,7 +302,7 @@ __device__ __forceinline__ uint64_t select_reverse(int64_t v, const int64_t *__r
         uint64_t sk = KEY_INF;
         if (b + lane < cnt) {
             const int32_t x = list[beg + b + lane];
-            sk = sample_key(hash4(seed, stream, (uint64_t)v, (uint64_t)x), x);
+            sk = sample_key(hash4(seed, stream, (uint64_t)(v - base), (uint64_t)(x - base)), x);
         }
         int p = 0;
         wave_sort(sk, p);
@@ -295,15 +327,16 @@ __global__ __launch_bounds__(256) void k_build_join(
     const int64_t *__restrict__ rn_off, const int32_t *__restrict__ rn_list,
     const int64_t *__restrict__ ro_off, const int32_t *__restrict__ ro_list,
     int32_t *__restrict__ jn, int32_t *__restrict__ jn_c, int JN, int32_t *__restrict__ jo,
-    int32_t *__restrict__ jo_c, int JO, unsigned long long *__restrict__ counters) {
+    int32_t *__restrict__ jo_c, int JO, unsigned long long *__restrict__ counters, Segs sg) {
     __shared__ unsigned long long pairs_s[4], memb_s[4];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     unsigned long long pairs = 0, memb = 0;
     // grid-stride over nodes, one wave each; one counter atomic per block
     for (int64_t v = (int64_t)blockIdx.x * 4 + w; v < n; v += (int64_t)gridDim.x * 4) {
-        const uint64_t rsel = select_reverse(v, rn_off, rn_list, seed, stream_rn, S);
-        const uint64_t osel = select_reverse(v, ro_off, ro_list, seed, stream_ro, S);
+        const int64_t base = seg_base(sg, v);
+        const uint64_t rsel = select_reverse(v, rn_off, rn_list, seed, stream_rn, S, base);
+        const uint64_t osel = select_reverse(v, ro_off, ro_list, seed, stream_ro, S, base);
         // new set (|new_f| <= S and |Rnew| <= S, S <= 32: one id per lane)
         const int nfc = nf_c[v];
         const uint64_t rsel_id = (lane < S && rsel != KEY_INF) ? (uint64_t)(uint32_t)key_id(rsel) : KEY_INF;
@@ -361,13 +394,6 @@ __global__ __launch_bounds__(256) void k_build_join(
 // local join tile
 // ---------------------------------------------------------------------------
 // Is `key` one of the K sorted keys of a list?  (binary search)
-// whether the list (K keys) holds id, whatever its distance
-__device__ __forceinline__ bool list_has_id(const uint64_t *__restrict__ row, int K, int32_t id) {
-    bool f = false;
-    for (int j = 0; j < K; ++j) f |= key_id(row[j]) == id;
-    return f;
-}
-
 __device__ __forceinline__ bool list_has(const uint64_t *__restrict__ row, int K, uint64_t key) {
     int lo = 0, hi = K;
     while (lo < hi) {
@@ -1015,15 +1041,10 @@ __device__ __forceinline__ mf_f32x16 gram_tile(const float *__restrict__ X, int6
 }
 
 constexpr int MW = 4;  // sources (waves) per workgroup in the MFMA join
-// mixed path: recheck list (a 32 x 32 tile has at most 1024 pairs), the
-// rechecked distances (16 registers x 64 lanes) and the ends they go to
-constexpr int JR_LIST = 1024;
 
-// LDS bytes of one join wave: per member kth, sbase, ids, cnt, base, mk, nrm,
-// thr; the mixed path adds the recheck list, distances and end flags
-__host__ __device__ inline size_t join_mfma_wave_bytes(int mps, bool mix) {
-    return (size_t)mps * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4) +
-           (mix ? (size_t)JR_LIST * sizeof(uint16_t) + (size_t)16 * PG_WAVE * (sizeof(float) + 1) : 0);
+// LDS bytes of one join wave: per member kth, sbase, ids, cnt, base, mk, nrm, thr
+__host__ __device__ inline size_t join_mfma_wave_bytes(int mps) {
+    return (size_t)mps * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4);
 }
 
 // MFMA local join for data on which the norm expansion is exact (see k_prep):
@@ -1032,8 +1053,8 @@ __host__ __device__ inline size_t join_mfma_wave_bytes(int mps, bool mix) {
 // FP32 join.  Offsets of the proposals to a tile's row member come from
 // ballots (the 32 lanes of a half share the row), so only one LDS atomic per
 // (row, tile half) and one per (lane, column) are needed.
-template <int P, bool MIX>
-__global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
+template <int P>
+__global__ __launch_bounds__(MW * PG_WAVE, 4) void k_join_mfma(
     const float *__restrict__ X, int64_t ldx, const void *__restrict__ X16, int d, int d16,
     const float *__restrict__ norms, int K, const int32_t *__restrict__ jn,
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
@@ -1041,7 +1062,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
     int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t seg,
     uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, const int32_t *__restrict__ order,
-    int64_t n, PassRange pr, int maxm, MixedParams mx, unsigned long long *__restrict__ counters) {
+    int64_t n, PassRange pr, int maxm, unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int MPS = (maxm + 31) / 32 * 32;
     const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
@@ -1052,7 +1073,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     if (u < 0) return;
     unsigned long long *cslot = stripe_of(counters);
     const int64_t seg_begin = (int64_t)(blockIdx.x % NSTRIPE) * seg, seg_end = seg_begin + seg;
-    unsigned char *region = smem + (size_t)wv * join_mfma_wave_bytes(MPS, MIX);
+    unsigned char *region = smem + (size_t)wv * join_mfma_wave_bytes(MPS);
     uint64_t *kth = reinterpret_cast<uint64_t *>(region);
     int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
     int32_t *ids = reinterpret_cast<int32_t *>(sbase + MPS);
@@ -1061,10 +1082,6 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     int32_t *mk = base + MPS;
     float *nrm = reinterpret_cast<float *>(mk + MPS);
     float *thr = nrm + MPS;  // d2 of the member's cut when it takes proposals, else -1
-    // mixed: the tile's pairs to recheck (q << 6 | lane) and their direct-form distances
-    uint16_t *rlist = reinterpret_cast<uint16_t *>(thr + MPS);
-    float *rdx = reinterpret_cast<float *>(rlist + JR_LIST);
-    uint8_t *rfl = reinterpret_cast<uint8_t *>(rdx + 16 * PG_WAVE);
 
     const int nn = jn_c[u], no = jo_c[u];
     const int m = nn + no;
@@ -1087,7 +1104,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
     __builtin_amdgcn_wave_barrier();
     const int RB = (nn + 31) / 32, CB = mp / 32;
     const int32_t id0 = ids[0];
-    unsigned long long local_props = 0, local_rechk = 0;
+    unsigned long long local_props = 0;
     for (int rb = 0; rb < RB; ++rb) {
         for (int cb = rb; cb < CB; ++cb) {
             // member of this lane's column and of the tile rows it loads
@@ -1100,102 +1117,16 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
             uint32_t to_row = 0, to_col = 0;
             const float nc = nrm[cm < mp ? cm : 0];
             const float thc = thr[cm < mp ? cm : 0];
-            float dx[MIX ? 16 : 1];  // mixed: direct-form distances of the rechecked pairs
-            uint32_t rmask = 0;      // mixed: registers whose pair is rechecked
-            uint32_t emask = 0;      // mixed: bits 2q / 2q + 1, the row / column end takes it
-            uint32_t bmask = 0;      // mixed: the same bits, ends whose bound the estimate meets
-            if constexpr (MIX) {
-                // Pairs whose 16-bit estimate lies within the rigorous bound of
-                // an end's cut are candidates.  They are gathered from the whole
-                // wave and spread one per lane.  An end that lists the other
-                // member already needs no proposal (the merge would drop it), so
-                // only pairs that some end does not list yet are rechecked in
-                // the FP32 direct form, the long chains running in parallel.
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
-                    dx[q] = __int_as_float(0x7f800000);
-                    if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
-                    const float d2e = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
-                    const float cr = mk[r] ? key_d2(kth[r]) : -1.0f, cc = mk[cm] ? key_d2(kth[cm]) : -1.0f;
-                    const float cut = fmaxf(cr, cc);
-                    if (cut < 0.0f || !(d2e <= mixed_bound(mx, cut, nrm[r], nc, g[q]))) continue;
-                    // the bound grows with the cut: the end with the larger cut
-                    // is in band, the other one is when its own bound holds
-                    const float lo = fminf(cr, cc);
-                    const bool other = lo >= 0.0f && d2e <= mixed_bound(mx, lo, nrm[r], nc, g[q]);
-                    const bool er = cr >= 0.0f && (cr >= cc || other);
-                    const bool ec = cc >= 0.0f && (cc > cr || other);
-                    bmask |= (er ? 1u : 0u) << (2 * q) | (ec ? 2u : 0u) << (2 * q);
-                    rmask |= 1u << q;
-                }
-                const int nr = __popc(rmask);
-                int ro = nr;
-#pragma unroll
-                for (int o = 1; o < PG_WAVE; o <<= 1) {
-                    const int t = __shfl_up(ro, o, PG_WAVE);
-                    if (lane >= o) ro += t;
-                }
-                const int rtot = __shfl(ro, PG_WAVE - 1, PG_WAVE);
-                ro -= nr;
-                if (rtot > 0) {
-                    {
-                        uint32_t mm = rmask;
-                        int e = ro;
-                        while (mm) {
-                            const int q = __builtin_ctz(mm);
-                            mm &= mm - 1;
-                            rlist[e++] = (uint16_t)((((bmask >> (2 * q)) & 3u) << 10) | (q << 6) | lane);
-                        }
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    int done = 0;
-                    for (int e = lane; e < rtot; e += PG_WAVE) {
-                        const int ent = rlist[e], q = (ent >> 6) & 15, src = ent & 63;
-                        const int rr = 32 * rb + 8 * (q / 4) + 4 * (src >> 5) + (q % 4);
-                        const int cc = 32 * cb + (src & 31);
-                        const int32_t ir = ids[rr], ic = ids[cc];
-                        int fl = (ent >> 10) & 3;
-                        if ((fl & 1) && list_has_id(keys + (int64_t)ir * K, K, ic)) fl &= ~1;
-                        if ((fl & 2) && list_has_id(keys + (int64_t)ic * K, K, ir)) fl &= ~2;
-                        float v = __int_as_float(0x7f800000);
-                        if (fl) {
-                            v = dist_chain(X + (int64_t)ir * ldx, X + (int64_t)ic * ldx, d);
-                            ++done;
-                        }
-                        rdx[src * 16 + q] = v;
-                        rfl[src * 16 + q] = (uint8_t)fl;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                    for (int q = 0; q < 16; ++q)
-                        if ((rmask >> q) & 1u) {
-                            dx[q] = rdx[lane * 16 + q];
-                            emask |= (uint32_t)rfl[lane * 16 + q] << (2 * q);
-                        }
-                    __builtin_amdgcn_wave_barrier();
-                    local_rechk += (unsigned long long)done;
-                }
-            }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
-                float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                const float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
                 // a key below an end's cut has d2 <= the cut's d2: most pairs stop here
-                if (!MIX && !(d2 <= thr[r]) && !(d2 <= thc)) continue;
+                if (!(d2 <= thr[r]) && !(d2 <= thc)) continue;
                 if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
-                if (MIX) {
-                    // outside the bound, or every end in band lists the other
-                    if (!((emask >> (2 * q)) & 3u)) continue;
-                    d2 = dx[MIX ? q : 0];
-                }
                 const uint64_t kw = pack_key(d2, ids[cm]), kv = pack_key(d2, ids[r]);
-                // mixed: an end takes the pair only if it is in band and does
-                // not list the other member (checked above, repeat passes too)
-                const bool row_ok = MIX ? ((emask >> (2 * q)) & 1u) != 0
-                                        : !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw));
-                const bool col_ok = MIX ? ((emask >> (2 * q)) & 2u) != 0
-                                        : !(mark && list_has(keys + (int64_t)ids[cm] * K, K, kv));
+                const bool row_ok = !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw));
+                const bool col_ok = !(mark && list_has(keys + (int64_t)ids[cm] * K, K, kv));
                 if (mk[r] && kw < kth[r] && row_ok) to_row |= 1u << q;
                 if (mk[cm] && kv < kth[cm] && col_ok) to_col |= 1u << q;
             }
@@ -1235,7 +1166,7 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
                 const uint32_t bit = 1u << q;
                 if (!((to_row | to_col) & bit)) continue;
                 const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
-                const float d2 = MIX ? dx[MIX ? q : 0] : fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                const float d2 = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
                 if (to_row & bit) {
                     const int32_t v = ids[r];
                     const int slot = base[r] + off_row[q];
@@ -1261,17 +1192,291 @@ __global__ __launch_bounds__(MW * PG_WAVE, MIX ? 3 : 4) void k_join_mfma(
         }
     }
 #pragma unroll
+    for (int o = 1; o < PG_WAVE; o <<= 1)
+        local_props += (unsigned long long)__shfl_xor((long long)local_props, o, PG_WAVE);
+    if (lane == 0 && local_props) atomicAdd(&cslot[C_PROPOSALS], local_props);
+}
+
+static size_t join_mfma_lds_bytes(int maxm) {
+    const int mps = (maxm + 31) / 32 * 32;
+    return (size_t)MW * join_mfma_wave_bytes(mps);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision local join for float data (PG_FP16 / PG_BF16 on non-exact
+// rows).  One wave per source u.  The 16-bit Gram tiles of the centred copy
+// give every pair's estimate; a pair whose estimate lies within the rigorous
+// bound (mixed_bound) of an end's cut is a candidate for that end and goes to
+// the wave's pair list; every other pair cannot beat either cut.  The list is
+// then settled on the FP32 rows: the rows of the members it involves are
+// staged through LDS HCH dimensions at a time, each lane accumulates the
+// canonical chains of its entries (dims ascending, one fma per dim, the same
+// value as everywhere else), and the exact keys are decided and emitted as in
+// the FP32 join.  So every stored distance is the chain value and the lists
+// equal the FP32 build's; the FP32 rows are read once per source and only
+// for members that some candidate pair involves.
+// ---------------------------------------------------------------------------
+constexpr int HW = 3;        // sources (waves) per workgroup
+constexpr int HCAP = 1024;   // pair list entries per wave (a tile adds at most 1024)
+constexpr int HCH = 8;       // FP32 dims per staging chunk
+constexpr int HPL = HCAP / PG_WAVE;  // list entries per lane
+
+// LDS bytes of one hybrid-join wave: per member kth, sbase, ids, cnt, base,
+// mk, nrm, thr, staging slot and slot owner; the pair list; the staging tile
+__host__ __device__ inline size_t join_hybrid_wave_bytes(int mps) {
+    return (size_t)mps * (8 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4 + 4) + (size_t)HCAP * 4 +
+           (size_t)mps * HCH * sizeof(float);
+}
+
+static size_t join_hybrid_lds_bytes(int maxm) {
+    const int mps = (maxm + 31) / 32 * 32;
+    return (size_t)HW * join_hybrid_wave_bytes(mps);
+}
+
+template <int P>
+__global__ __launch_bounds__(HW * PG_WAVE, 2) void k_join_hybrid(
+    const float *__restrict__ X, int64_t ldx, const void *__restrict__ X16, int d, int d16,
+    const float *__restrict__ norms, int K, const int32_t *__restrict__ jn,
+    const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
+    const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
+    int32_t *__restrict__ pcnt, uint64_t *__restrict__ bucket, int B,
+    int32_t *__restrict__ spill_t, uint64_t *__restrict__ spill_k, int64_t seg,
+    uint8_t *__restrict__ ovf_next, const uint8_t *__restrict__ mark, const int32_t *__restrict__ order,
+    int64_t n, PassRange pr, int maxm, MixedParams mx, unsigned long long *__restrict__ counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int MPS = (maxm + 31) / 32 * 32;
+    const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
+    const int wv = threadIdx.x / PG_WAVE;
+    const int64_t nlog = (pr.items + HW - 1) / HW;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nlog);
+    const int64_t u = lb < nlog ? pass_source(order, n, pr, lb * HW + wv) : -1;
+    if (u < 0) return;
+    unsigned long long *cslot = stripe_of(counters);
+    const int64_t seg_begin = (int64_t)(blockIdx.x % NSTRIPE) * seg, seg_end = seg_begin + seg;
+    unsigned char *region = smem + (size_t)wv * join_hybrid_wave_bytes(MPS);
+    uint64_t *kth = reinterpret_cast<uint64_t *>(region);
+    int64_t *sbase = reinterpret_cast<int64_t *>(kth + MPS);
+    int32_t *ids = reinterpret_cast<int32_t *>(sbase + MPS);
+    int32_t *cnt = ids + MPS;
+    int32_t *base = cnt + MPS;
+    int32_t *mk = base + MPS;
+    float *nrm = reinterpret_cast<float *>(mk + MPS);
+    float *cut = nrm + MPS;     // d2 of the member's cut when it takes proposals, else -1
+    int32_t *slot = reinterpret_cast<int32_t *>(cut + MPS);  // staging row of a member, or -1
+    int32_t *owner = slot + MPS;                              // member of a staging row
+    uint32_t *plist = reinterpret_cast<uint32_t *>(owner + MPS);
+    float *stage = reinterpret_cast<float *>(plist + HCAP);  // [row][HCH]
+
+    const int nn = jn_c[u], no = jo_c[u];
+    const int m = nn + no;
+    if (nn == 0 || m < 2) return;
+    const int mp = (m + 31) / 32 * 32;
+    bool anymark = false;
+    for (int i = lane; i < mp; i += PG_WAVE) {
+        const int32_t id = i < nn ? jn[u * JN + i] : (i < m ? jo[u * JO + (i - nn)] : -1);
+        ids[i] = id;
+        const uint64_t kk = id >= 0 ? keys[(int64_t)id * K + (K - 1)] : 0ull;
+        kth[i] = kk;
+        nrm[i] = id >= 0 ? norms[id] : 0.f;
+        cnt[i] = 0;
+        slot[i] = -1;
+        const int mkv = (mark && id >= 0) ? (int)mark[id] : (mark ? 0 : 1);
+        mk[i] = mkv;
+        cut[i] = (id >= 0 && mkv) ? key_d2(kk) : -1.0f;
+        anymark |= (id >= 0 && mkv != 0);
+    }
+    if (__ballot(anymark) == 0) return;
+    __builtin_amdgcn_wave_barrier();
+    const int RB = (nn + 31) / 32, CB = mp / 32;
+    const int32_t id0 = ids[0];
+    unsigned long long local_props = 0, local_rechk = 0;
+    int nl = 0;  // entries in the pair list (wave-uniform)
+
+    // settle the listed pairs on the FP32 rows and emit their proposals
+    auto flush = [&]() {
+        if (nl == 0) return;
+        // staging rows: the members the list involves, in member order
+        for (int e = lane; e < nl; e += PG_WAVE) {
+            const uint32_t ent = plist[e];
+            slot[ent & 0xFF] = 0;
+            slot[(ent >> 8) & 0xFF] = 0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        int ns = 0;
+        for (int i0 = 0; i0 < mp; i0 += PG_WAVE) {
+            const int i = i0 + lane;
+            const bool inv = i < m && slot[i] == 0;
+            const uint64_t bm = __ballot(inv);
+            if (inv) {
+                const int s = ns + __popcll(bm & lanemask_lt());
+                slot[i] = s;
+                owner[s] = ids[i];
+            }
+            ns += __popcll(bm);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // per lane: entries e = lane + 64 j, their staging rows and chains
+        float acc[HPL];
+        int sr[HPL], sc[HPL];
+#pragma unroll
+        for (int j = 0; j < HPL; ++j) {
+            const int e = lane + PG_WAVE * j;
+            acc[j] = 0.0f;
+            sr[j] = sc[j] = 0;
+            if (e < nl) {
+                const uint32_t ent = plist[e];
+                sr[j] = slot[ent & 0xFF] * HCH;
+                sc[j] = slot[(ent >> 8) & 0xFF] * HCH;
+            }
+        }
+        const int jmax = (nl + PG_WAVE - 1) / PG_WAVE;
+        for (int c0 = 0; c0 < d; c0 += HCH) {
+            __builtin_amdgcn_wave_barrier();
+            for (int v = lane; v < ns * (HCH / 4); v += PG_WAVE) {
+                const int s = v / (HCH / 4), q = v - s * (HCH / 4);
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (c0 + 4 * q < d) x = *reinterpret_cast<const float4 *>(X + (int64_t)owner[s] * ldx + c0 + 4 * q);
+                *reinterpret_cast<float4 *>(stage + s * HCH + 4 * q) = x;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < HPL; ++j) {
+                if (j < jmax) {
+#pragma unroll
+                    for (int q = 0; q < HCH; q += 4) {
+                        const float4 a = *reinterpret_cast<const float4 *>(stage + sr[j] + q);
+                        const float4 b = *reinterpret_cast<const float4 *>(stage + sc[j] + q);
+                        float s = acc[j], t;
+                        t = a.x - b.x;
+                        s = fmaf(t, t, s);
+                        t = a.y - b.y;
+                        s = fmaf(t, t, s);
+                        t = a.z - b.z;
+                        s = fmaf(t, t, s);
+                        t = a.w - b.w;
+                        s = fmaf(t, t, s);
+                        acc[j] = s;
+                    }
+                }
+            }
+        }
+        // exact decisions; offsets per member from LDS atomics
+        uint32_t to_row = 0, to_col = 0;
+        int off_r[HPL], off_c[HPL];
+#pragma unroll
+        for (int j = 0; j < HPL; ++j) {
+            const int e = lane + PG_WAVE * j;
+            off_r[j] = off_c[j] = 0;
+            if (e < nl) {
+                const uint32_t ent = plist[e];
+                const int r = ent & 0xFF, c = (ent >> 8) & 0xFF;
+                const float d2 = acc[j];
+                const uint64_t kw = pack_key(d2, ids[c]), kv = pack_key(d2, ids[r]);
+                if (((ent >> 16) & 1u) && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw))) {
+                    to_row |= 1u << j;
+                    off_r[j] = atomicAdd(&cnt[r], 1);
+                }
+                if (((ent >> 17) & 1u) && kv < kth[c] && !(mark && list_has(keys + (int64_t)ids[c] * K, K, kv))) {
+                    to_col |= 1u << j;
+                    off_c[j] = atomicAdd(&cnt[c], 1);
+                }
+            }
+        }
+        local_rechk += (unsigned long long)(lane < nl ? (nl - lane + PG_WAVE - 1) / PG_WAVE : 0);
+        __builtin_amdgcn_wave_barrier();
+        local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < HPL; ++j) {
+            if (!(((to_row | to_col) >> j) & 1u)) continue;
+            const uint32_t ent = plist[lane + PG_WAVE * j];
+            const int r = ent & 0xFF, c = (ent >> 8) & 0xFF;
+            const float d2 = acc[j];
+            if ((to_row >> j) & 1u) {
+                const int32_t v = ids[r];
+                const int sl = base[r] + off_r[j];
+                const uint64_t kw = pack_key(d2, ids[c]);
+                if (sl < B)
+                    bucket[(int64_t)v * B + sl] = kw;
+                else
+                    spill_put(v, kw, sbase[r] + (sl - max(base[r], B)), spill_t, spill_k, seg_end, ovf_next, cslot);
+            }
+            if ((to_col >> j) & 1u) {
+                const int32_t w = ids[c];
+                const int sl = base[c] + off_c[j];
+                const uint64_t kv = pack_key(d2, ids[r]);
+                if (sl < B)
+                    bucket[(int64_t)w * B + sl] = kv;
+                else
+                    spill_put(w, kv, sbase[c] + (sl - max(base[c], B)), spill_t, spill_k, seg_end, ovf_next, cslot);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < mp; i += PG_WAVE) slot[i] = -1;
+        __builtin_amdgcn_wave_barrier();
+        nl = 0;
+    };
+
+    for (int rb = 0; rb < RB; ++rb) {
+        for (int cb = rb; cb < CB; ++cb) {
+            const int cm = 32 * cb + l32;
+            const int rm = 32 * rb + l32;
+            const int32_t cid = cm < m ? ids[cm] : id0;
+            const int32_t rid = rm < nn ? ids[rm] : id0;
+            const mf_f32x16 g = gram_tile<P>(X, ldx, X16, d, d16, rid, cid);
+            const float nc = nrm[cm < mp ? cm : 0];
+            const float cc = cut[cm < mp ? cm : 0];
+            // candidates: bits 2q (row end) and 2q + 1 (column end)
+            uint32_t emask = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
+                if (r >= nn || cm >= m || (cm < nn && cm <= r)) continue;
+                const float cr = cut[r];
+                const float hi = fmaxf(cr, cc);
+                if (hi < 0.0f) continue;
+                const float d2e = fmaxf(fmaf(-2.0f, g[q], nrm[r] + nc), 0.0f);
+                if (!(d2e <= mixed_bound(mx, hi, nrm[r], nc, g[q]))) continue;
+                // the bound grows with the cut: the end with the larger cut is
+                // a candidate, the other one when its own bound holds
+                const float lo = fminf(cr, cc);
+                const bool other = lo >= 0.0f && d2e <= mixed_bound(mx, lo, nrm[r], nc, g[q]);
+                const bool er = cr >= 0.0f && (cr >= cc || other);
+                const bool ec = cc >= 0.0f && (cc > cr || other);
+                emask |= ((er ? 1u : 0u) | (ec ? 2u : 0u)) << (2 * q);
+            }
+            // append this lane's candidates after the lanes below it
+            const uint32_t any = (emask | (emask >> 1)) & 0x55555555u;
+            const int mine = __popc(any);
+            int incl = mine;
+#pragma unroll
+            for (int o = 1; o < PG_WAVE; o <<= 1) {
+                const int t = __shfl_up(incl, o, PG_WAVE);
+                if (lane >= o) incl += t;
+            }
+            const int total = __shfl(incl, PG_WAVE - 1, PG_WAVE);
+            if (nl + total > HCAP) flush();
+            int at = nl + incl - mine;
+            uint32_t mm = any;
+            while (mm) {
+                const int b = __builtin_ctz(mm);
+                mm &= mm - 1;
+                const int q = b >> 1;
+                const int r = 32 * rb + 8 * (q / 4) + 4 * h + (q % 4);
+                plist[at++] = (uint32_t)r | ((uint32_t)cm << 8) | (((emask >> b) & 3u) << 16);
+            }
+            nl += total;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    flush();
+#pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) {
         local_props += (unsigned long long)__shfl_xor((long long)local_props, o, PG_WAVE);
         local_rechk += (unsigned long long)__shfl_xor((long long)local_rechk, o, PG_WAVE);
     }
     if (lane == 0 && local_props) atomicAdd(&cslot[C_PROPOSALS], local_props);
     if (lane == 0 && local_rechk) atomicAdd(&cslot[C_RECHECK], local_rechk);
-}
-
-static size_t join_mfma_lds_bytes(int maxm, bool mix) {
-    const int mps = (maxm + 31) / 32 * 32;
-    return (size_t)MW * join_mfma_wave_bytes(mps, mix);
 }
 
 // ---------------------------------------------------------------------------
@@ -1356,13 +1561,15 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t *__restrict__ keys,
 }
 
 __global__ __launch_bounds__(256) void k_count_updates(uint64_t *__restrict__ insm, int64_t n,
-                                                       unsigned long long *__restrict__ counters) {
+                                                       unsigned long long *__restrict__ counters, Segs sg,
+                                                       unsigned long long *__restrict__ seg_updates) {
     __shared__ unsigned long long s[256];
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long c = 0;
     if (v < n) {
         c = (unsigned long long)__popcll(insm[v]);
         insm[v] = 0;
+        if (sg.of && c) atomicAdd(&seg_updates[sg.of[v]], c);
     }
     s[threadIdx.x] = c;
     __syncthreads();
@@ -1374,11 +1581,12 @@ __global__ __launch_bounds__(256) void k_count_updates(uint64_t *__restrict__ in
 }
 
 __global__ void k_unpack(const uint64_t *__restrict__ keys, int64_t total,
-                         int32_t *__restrict__ ids, float *__restrict__ d2) {
+                         int32_t *__restrict__ ids, float *__restrict__ d2, Segs sg, int K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const uint64_t k = keys[i];
-    ids[i] = k == KEY_INF ? -1 : key_id(k);
+    // ids local to the node's collection
+    ids[i] = k == KEY_INF ? -1 : (int32_t)(key_id(k) - seg_base(sg, i / K));
     d2[i] = k == KEY_INF ? __int_as_float(0x7f800000) : key_d2(k);
 }
 
@@ -1526,13 +1734,28 @@ __global__ void k_order_scatter(const int32_t *__restrict__ piv, int64_t n, cons
     order[off[g] + atomicAdd(&cur[g], 1)] = (int32_t)i;
 }
 
+// collection of every node: the last c with off[c] <= u (binary search)
+__global__ void k_seg_fill(const int64_t *__restrict__ off, int ncoll, int64_t n, int32_t *__restrict__ seg_of) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int a = 0, b = ncoll - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (off[mid] <= u)
+            a = mid;
+        else
+            b = mid - 1;
+    }
+    seg_of[u] = a;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 struct KnnLayout {
     size_t keys, newm, insm, nf, nf_c, of, of_c, rn_cnt, ro_cnt, rn_off, ro_off, rn_list, ro_list,
         jn, jn_c, jo, jo_c, pcnt, bucket, mark, mark_next, counters, scan_tmp, spill_t, spill_k,
-        spill_s, x16, norms, exflags, order, mu, mu_part, total;
+        spill_s, x16, norms, exflags, order, mu, mu_part, seg_of, seg_off, seg_frozen, seg_updates, total;
     int64_t mu_nb;
     int B, JN, JO, d16;
     int64_t spill_cap;
@@ -1540,7 +1763,7 @@ struct KnnLayout {
 
 static int default_bucket(int K) { return 8 * K; }
 
-static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d) {
+static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d, int ncoll = 0) {
     KnnLayout L{};
     L.d16 = (d + 15) / 16 * 16;
     const int64_t K = p->K, S = p->S;
@@ -1588,6 +1811,11 @@ static KnnLayout knn_layout(const pg_knn_params *p, int64_t n, int d) {
     L.mu_nb = half ? (n + MU_ROWS - 1) / MU_ROWS : 0;
     L.mu = take(half ? sizeof(float) * d : 0);
     L.mu_part = take(sizeof(double) * L.mu_nb * d);
+    // collections of a batched build (none for a single build)
+    L.seg_of = take(ncoll ? sizeof(int32_t) * n : 0);
+    L.seg_off = take(ncoll ? sizeof(int64_t) * (ncoll + 1) : 0);
+    L.seg_frozen = take(ncoll ? (size_t)ncoll : 0);
+    L.seg_updates = take(ncoll ? sizeof(unsigned long long) * ncoll : 0);
     L.total = o;
     return L;
 }
@@ -1710,13 +1938,41 @@ static pg_status check_build_args(const char *who, pg_ctx *ctx, const float *X, 
 // The build itself, arguments already checked.  ws holds at least
 // knn_layout(p, n, d).total bytes of any content: everything that must start
 // at zero is cleared on the stream here.  Nothing is allocated.
+// A batch (ncoll > 0) holds collections [off[c], off[c + 1]) of the rows;
+// each stops on its own rule (stop[c]) and iters[c] receives its iterations.
+struct BatchSpec {
+    int ncoll;
+    const int64_t *off;   // host, ncoll + 1
+    const int64_t *stop;  // host, ncoll
+    int32_t *iters;       // host, ncoll (optional)
+};
+
 static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
                                const pg_knn_params *p, void *ws, int32_t *knn_ids, float *knn_d2,
-                               pg_knn_stats *stats) {
+                               pg_knn_stats *stats, const BatchSpec &bs = BatchSpec{0, nullptr, nullptr, nullptr}) {
     if (stats) memset(stats, 0, sizeof(*stats));
     if (p->exact) return knn_exact_lists(ctx, X, n, d, ldx, p->K, knn_ids, knn_d2);
-    const KnnLayout L = knn_layout(p, n, d);
+    const KnnLayout L = knn_layout(p, n, d, bs.ncoll);
     char *w = (char *)ws;
+    Segs sg{nullptr, nullptr, nullptr};
+    unsigned long long *seg_upd = nullptr;
+    std::vector<uint8_t> frozen_h;
+    if (bs.ncoll > 0) {
+        int32_t *seg_of = (int32_t *)(w + L.seg_of);
+        int64_t *seg_off = (int64_t *)(w + L.seg_off);
+        uint8_t *seg_fr = (uint8_t *)(w + L.seg_frozen);
+        seg_upd = (unsigned long long *)(w + L.seg_updates);
+        PG_HIP(hipMemcpyAsync(seg_off, bs.off, sizeof(int64_t) * (bs.ncoll + 1), hipMemcpyHostToDevice,
+                              ctx->stream));
+        PG_HIP(hipMemsetAsync(seg_fr, 0, (size_t)bs.ncoll, ctx->stream));
+        hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, seg_off,
+                           bs.ncoll, n, seg_of);
+        PG_HIP(hipGetLastError());
+        sg = Segs{seg_of, seg_off, seg_fr};
+        frozen_h.assign((size_t)bs.ncoll, 0);
+        if (bs.iters)
+            for (int c = 0; c < bs.ncoll; ++c) bs.iters[c] = 0;
+    }
     uint64_t *keys = (uint64_t *)(w + L.keys), *newm = (uint64_t *)(w + L.newm),
              *insm = (uint64_t *)(w + L.insm);
     int32_t *nf = (int32_t *)(w + L.nf), *nf_c = (int32_t *)(w + L.nf_c), *of = (int32_t *)(w + L.of),
@@ -1804,7 +2060,7 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         TimedLaunch tl(ctx, K_INIT, (double)n * K * (8.0 + 4.0 * d));
         const _Float16 *x16i = path == PG_JOIN_MFMA_FP16 ? xh : nullptr;
         hipLaunchKernelGGL(k_init, dim3(wave_blocks), dim3(256), 0, st, X, ldx, d, x16i, L.d16, n, K, p->seed,
-                           keys, newm, insm);
+                           keys, newm, insm, sg);
         PG_HIP(hipGetLastError());
     }
     if (stats) stats->join_path = path;
@@ -1830,9 +2086,9 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         PG_HIP(hipGetLastError());
     }
     const int maxm = 3 * S + K;
+    const bool mixed = path == PG_JOIN_MIXED_FP16 || path == PG_JOIN_MIXED_BF16;
     const size_t lds = path == PG_JOIN_VALU ? join_lds_bytes(maxm)
-                                            : join_mfma_lds_bytes(maxm, path == PG_JOIN_MIXED_FP16 ||
-                                                                            path == PG_JOIN_MIXED_BF16);
+                                            : (mixed ? join_hybrid_lds_bytes(maxm) : join_mfma_lds_bytes(maxm));
     int iters = 0;
     int64_t prev_props = -1;
     for (int t = 1; t <= p->max_iters; ++t) {
@@ -1843,7 +2099,7 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
             TimedLaunch tl(ctx, K_SAMPLE, (double)n * K * 8.0);
             // slots of the reverse entries live in jn / jo until the join sets are built
             hipLaunchKernelGGL(k_sample, dim3(wave_blocks), dim3(256), 0, st, keys, newm, n, K, S,
-                               p->seed, (uint64_t)(3 * t), nf, nf_c, of, of_c, rn_cnt, ro_cnt, jn, jo);
+                               p->seed, (uint64_t)(3 * t), nf, nf_c, of, of_c, rn_cnt, ro_cnt, jn, jo, sg);
             PG_HIP(hipGetLastError());
         }
         PG_TRY(scan_exclusive(ctx, rn_cnt, rn_off, n, scan_tmp));
@@ -1854,7 +2110,7 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         hipLaunchKernelGGL(k_build_join, dim3(std::min<unsigned>(wave_blocks, 8192)), dim3(256), 0, st, n, K, S,
                            p->seed,
                            (uint64_t)(3 * t + 1), (uint64_t)(3 * t + 2), nf, nf_c, of, of_c, rn_off,
-                           rn_list, ro_off, ro_list, jn, jn_c, L.JN, jo, jo_c, L.JO, counters);
+                           rn_list, ro_off, ro_list, jn, jn_c, L.JN, jo, jo_c, L.JO, counters, sg);
         PG_HIP(hipGetLastError());
         // Source passes: residue classes of the order positions mod 64, sized
         // r, r, 2r, 4r, ... (r = 64 / c).  Each merge tightens every K-th key,
@@ -1892,6 +2148,7 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
                 {
                     TimedLaunch tl(ctx, K_JOIN, -1.0);
                     const unsigned mg = xcd_grid((pr.items + MW - 1) / MW);
+                    const unsigned hg = xcd_grid((pr.items + HW - 1) / HW);
                     const void *x16 = (const void *)(w + L.x16);
                     if (path == PG_JOIN_VALU)
                         hipLaunchKernelGGL(k_join, dim3(xcd_grid((pr.items + JW - 1) / JW)), dim3(JT), lds, st,
@@ -1899,27 +2156,27 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
                                            L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, counters);
                     else if (path == PG_JOIN_MFMA_FP32)
-                        hipLaunchKernelGGL((k_join_mfma<PG_FP32, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
+                        hipLaunchKernelGGL((k_join_mfma<PG_FP32>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X, ldx,
                                            x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys,
                                            pcnt, bucket, L.B, spill_t, spill_k, seg, mark_next, mk,
-                                           order, n, pr, maxm, mx, counters);
+                                           order, n, pr, maxm, counters);
                     else if (path == PG_JOIN_MFMA_FP16)
-                        hipLaunchKernelGGL((k_join_mfma<PG_FP16, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                        hipLaunchKernelGGL((k_join_mfma<PG_FP16>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
                                            bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
-                                           maxm, mx, counters);
+                                           maxm, counters);
                     else if (path == PG_JOIN_MFMA_BF16)
-                        hipLaunchKernelGGL((k_join_mfma<PG_BF16, false>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                        hipLaunchKernelGGL((k_join_mfma<PG_BF16>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
                                            bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
-                                           maxm, mx, counters);
+                                           maxm, counters);
                     else if (path == PG_JOIN_MIXED_FP16)
-                        hipLaunchKernelGGL((k_join_mfma<PG_FP16, true>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                        hipLaunchKernelGGL((k_join_hybrid<PG_FP16>), dim3(hg), dim3(HW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
                                            bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, mx, counters);
                     else
-                        hipLaunchKernelGGL((k_join_mfma<PG_BF16, true>), dim3(mg), dim3(MW * PG_WAVE), lds, st, X,
+                        hipLaunchKernelGGL((k_join_hybrid<PG_BF16>), dim3(hg), dim3(HW * PG_WAVE), lds, st, X,
                                            ldx, x16, d, L.d16, norms, K, jn, jn_c, L.JN, jo, jo_c, L.JO, keys, pcnt,
                                            bucket, L.B, spill_t, spill_k, seg, mark_next, mk, order, n, pr,
                                            maxm, mx, counters);
@@ -1964,8 +2221,9 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
                 mk = mark;
             }
         }
+        if (bs.ncoll > 0) PG_HIP(hipMemsetAsync(seg_upd, 0, sizeof(unsigned long long) * bs.ncoll, st));
         hipLaunchKernelGGL(k_count_updates, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, insm,
-                           n, counters);
+                           n, counters, sg, seg_upd);
         PG_HIP(hipGetLastError());
         unsigned long long hc[C_NCOUNTERS];
         hipLaunchKernelGGL(k_counters_reduce, dim3(1), dim3(NSTRIPE), 0, st, counters, seg, csum);
@@ -1988,12 +2246,28 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
             ctx_add_work(ctx, K_JOIN, 2.0 * (double)hc[C_PAIRS] * d);
         else
             ctx_add_work(ctx, K_JOIN, 2.0 * (double)hc[C_MEMBERS] * L.d16);
-        if ((int64_t)hc[C_UPDATES] <= p->stop_updates) break;
+        if (bs.ncoll == 0) {
+            if ((int64_t)hc[C_UPDATES] <= p->stop_updates) break;
+            continue;
+        }
+        // batch: freeze every collection whose iteration met its stop rule
+        std::vector<unsigned long long> su((size_t)bs.ncoll);
+        PG_HIP(hipMemcpyAsync(su.data(), seg_upd, sizeof(unsigned long long) * bs.ncoll, hipMemcpyDeviceToHost, st));
+        PG_HIP(hipStreamSynchronize(st));
+        bool all = true;
+        for (int c = 0; c < bs.ncoll; ++c) {
+            if (frozen_h[c]) continue;
+            if (bs.iters) bs.iters[c] = t;
+            if ((int64_t)su[c] <= bs.stop[c]) frozen_h[c] = 1;
+            all = all && frozen_h[c];
+        }
+        if (all) break;
+        PG_HIP(hipMemcpyAsync((void *)sg.frozen, frozen_h.data(), (size_t)bs.ncoll, hipMemcpyHostToDevice, st));
     }
     if (stats) stats->iters_run = iters;
     const int64_t total = n * K;
     hipLaunchKernelGGL(k_unpack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, keys, total,
-                       knn_ids, knn_d2);
+                       knn_ids, knn_d2, sg, K);
     PG_HIP(hipGetLastError());
     PG_HIP(hipStreamSynchronize(st));
     return PG_OK;
@@ -2088,6 +2362,62 @@ extern "C" pg_status pg_quality_examination(pg_ctx *ctx, const float *X, int64_t
                        hits, estimate);
     PG_HIP(hipGetLastError());
     return PG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched builds: several collections of the same dimension in one launch of
+// every kernel of an iteration.
+// ---------------------------------------------------------------------------
+static pg_status check_batch(const char *who, const pg_knn_params *p, int64_t n, const int64_t *off, int ncoll) {
+    if (ncoll < 1 || !off) {
+        set_error("%s: ncoll=%d must be >= 1 with offsets", who, ncoll);
+        return PG_EINVAL;
+    }
+    if (p && p->exact) {
+        set_error("%s: exact lists are not batched (use pg_exact_knn per collection)", who);
+        return PG_EINVAL;
+    }
+    if (off[0] != 0 || off[ncoll] != n) {
+        set_error("%s: offsets must run from 0 to n=%lld", who, (long long)n);
+        return PG_EINVAL;
+    }
+    for (int c = 0; c < ncoll; ++c)
+        if (p && off[c + 1] - off[c] <= p->K) {
+            set_error("%s: collection %d has %lld rows, not more than K=%d", who, c,
+                      (long long)(off[c + 1] - off[c]), p->K);
+            return PG_EINVAL;
+        }
+    return PG_OK;
+}
+
+extern "C" pg_status pg_knn_build_batch_workspace(const pg_knn_params *p, int64_t n, int32_t d, int32_t ncoll,
+                                                  size_t *bytes) {
+    PG_TRY(check_knn(p, n, d));
+    if (!bytes || ncoll < 1) {
+        set_error("pg_knn_build_batch_workspace: bytes is NULL or ncoll < 1");
+        return PG_EINVAL;
+    }
+    *bytes = knn_layout(p, n, d, ncoll).total;
+    return PG_OK;
+}
+
+extern "C" pg_status pg_knn_build_batch(pg_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                                        const int64_t *offsets, int32_t ncoll, const int64_t *stop_updates,
+                                        const pg_knn_params *p, void *ws, size_t ws_bytes, int32_t *knn_ids,
+                                        float *knn_d2, int32_t *iters) {
+    PG_TRY(check_build_args("pg_knn_build_batch", ctx, X, n, d, ldx, p, knn_ids, knn_d2));
+    PG_TRY(check_batch("pg_knn_build_batch", p, n, offsets, ncoll));
+    if (!stop_updates) {
+        set_error("pg_knn_build_batch: stop_updates is NULL");
+        return PG_EINVAL;
+    }
+    const size_t need = knn_layout(p, n, d, ncoll).total;
+    if (!ws || ws_bytes < need) {
+        set_error("pg_knn_build_batch: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        return PG_ENOMEM;
+    }
+    return knn_build_run(ctx, X, n, d, ldx, p, ws, knn_ids, knn_d2, nullptr,
+                         BatchSpec{ncoll, offsets, stop_updates, iters});
 }
 
 // ---------------------------------------------------------------------------

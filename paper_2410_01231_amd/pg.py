@@ -59,7 +59,8 @@ class SearchParams(ctypes.Structure):
 EXPORTS = ["pg_version", "pg_last_error", "pg_ctx_create", "pg_ctx_destroy", "pg_ctx_set_timing",
            "pg_ctx_kernel_time", "pg_ctx_reset_timing", "pg_knn_build_workspace", "pg_knn_build",
            "pg_exact_knn", "pg_prune_workspace", "pg_prune", "pg_search", "pg_hnsw_levels",
-           "pg_half_rows", "pg_knn_build_noalloc", "pg_quality_examination"]
+           "pg_half_rows", "pg_knn_build_noalloc", "pg_quality_examination", "pg_knn_build_batch_workspace",
+           "pg_knn_build_batch"]
 
 _lib = None
 
@@ -86,6 +87,9 @@ def load_library(path: str = LIB_PATH):
                                  P, P, POINTER(KnnStats)]
     lib.pg_knn_build_noalloc.argtypes = [P, P, c_int64, c_int32, c_int64, POINTER(KnnParams), P, P,
                                          POINTER(KnnStats)]
+    lib.pg_knn_build_batch_workspace.argtypes = [POINTER(KnnParams), c_int64, c_int32, c_int32, POINTER(c_size_t)]
+    lib.pg_knn_build_batch.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, P, POINTER(KnnParams), P,
+                                       c_size_t, P, P, P]
     lib.pg_quality_examination.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int32, c_int32, P, c_int64,
                                            P, P, P, P]
     lib.pg_exact_knn.argtypes = [P, P, c_int64, c_int32, c_int64, P, c_int64, c_int64, P, c_int32,
@@ -226,6 +230,41 @@ def knn_build(X, K, S=None, max_iters=12, seed=0, stop_updates=None, delta=0.001
              "retries": st.retries,
              "spilled": st.spilled, "join_path": JOIN_PATHS.get(st.join_path, st.join_path)}
     return ids, d2, stats
+
+
+def knn_build_batch(X, offsets, K, S=None, max_iters=12, seed=0, delta=0.001, stop_updates=None,
+                    precision=FP32, margin_rel=0.0, ctx=None):
+    """NN-Descent lists of several collections in one build (pg_knn_build_batch):
+    X holds the collections' rows one after another, collection c being rows
+    offsets[c]:offsets[c + 1].  Returns (ids, d2, iters): n x K lists with ids
+    local to each collection (each equal to knn_build on the collection's
+    rows alone) and each collection's iteration count.  stop_updates (one per
+    collection) defaults to delta * n_c * K."""
+    import numpy as np
+    lib = load_library()
+    X = _dev_f32(X, "X")
+    n, d = X.shape
+    S = (K + 1) // 2 if S is None else S
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    ncoll = len(off) - 1
+    if stop_updates is None:
+        stop_updates = [int(delta * int(off[c + 1] - off[c]) * K) for c in range(ncoll)]
+    stop = np.ascontiguousarray(np.asarray(stop_updates, dtype=np.int64))
+    if stop.shape != (ncoll,):
+        raise ValueError("stop_updates needs one value per collection")
+    p = KnnParams(K=K, S=S, max_iters=max_iters, exact=0, stop_updates=0, seed=seed & (2**64 - 1),
+                  precision=precision, margin_rel=float(margin_rel))
+    ws_bytes = c_size_t()
+    _check(lib.pg_knn_build_batch_workspace(ctypes.byref(p), n, d, ncoll, ctypes.byref(ws_bytes)), "workspace")
+    ws = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=X.device)
+    ids = torch.empty((n, K), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((n, K), dtype=torch.float32, device=X.device)
+    iters = np.zeros(ncoll, dtype=np.int32)
+    ctx = ctx or context(X.device.index)
+    _check(lib.pg_knn_build_batch(ctx.handle, _ptr(X), n, d, X.stride(0), c_void_p(off.ctypes.data), ncoll,
+                                  c_void_p(stop.ctypes.data), ctypes.byref(p), _ptr(ws), ws_bytes.value, _ptr(ids),
+                                  _ptr(d2), c_void_p(iters.ctypes.data)), "pg_knn_build_batch")
+    return ids, d2, iters.tolist()
 
 
 NOALLOC_WS_BYTES = 128 << 20  # PG_NOALLOC_WS_BYTES of include/pg.h
