@@ -62,6 +62,7 @@ WORKLOADS = {
                  cpu_sample=10_000,
                  gen="uniform_int", desc="uniform-int 10kx128, K=32 R=32 FP32"),
 }
+SERVE_BATCH = 16  # builds of one shape the serving loop runs as one batched build
 L_LADDER = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector and FP32 MFMA (dense)
 PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 MFMA
@@ -475,8 +476,8 @@ def run_serve(args):
     log(f"[bench] serving mix: {len(jobs)} jobs, {points} points")
     budget = int(args.serve_budget_gb * (1 << 30))
 
-    def run(arrivals):
-        srv = Server(budget, workers=8)
+    def run(arrivals, batch):
+        srv = Server(budget, workers=8, batch_builds=batch)
         done_q = {j.job_id: 0 for j in jobs}
         lock = threading.Lock()
 
@@ -503,24 +504,29 @@ def run_serve(args):
         qres = [f.result()[1] for f in fq]
         wall = time.perf_counter() - t0
         srv.close()
-        log(f"[bench] serving run: {wall:.2f} s, peak ledger {srv.peak_in_use / 2**30:.1f} GiB")
+        log(f"[bench] serving run (batch {batch}): {wall:.2f} s, peak ledger {srv.peak_in_use / 2**30:.1f} GiB, "
+            f"{len(srv.batch_log)} batched builds")
         return wall, blat, qres, srv.peak_in_use
 
     def ms(v):
         return {k: (1000.0 * x if x is not None else None) for k, x in percentiles(v).items()}
 
-    wall, _, _, peak = run([0.0] * len(jobs))
+    # saturated: everything submitted at once, builds one by one and batched
+    wall1, _, _, peak = run([0.0] * len(jobs), 1)
+    wall, _, _, peakb = run([0.0] * len(jobs), SERVE_BATCH)
+    peak = max(peak, peakb)
     rate = len(jobs) / wall
     loads = []
     for load in (0.5, 0.9):
         gaps = rng.exponential(1.0 / (load * rate), size=len(jobs))
-        wall2, blat, qres, peak2 = run(np.cumsum(gaps) - gaps[0])
+        wall2, blat, qres, peak2 = run(np.cumsum(gaps) - gaps[0], SERVE_BATCH)
         peak = max(peak, peak2)
         loads.append({"load": load, "arrival_rate_jobs_per_s": load * rate, "wall_s": wall2,
                       "build_latency_ms": ms(blat), "query_latency_ms": ms([t.latency for t in qres]),
                       "query_service_ms": ms([t.service for t in qres])})
         log(f"[bench] serving at {load} x saturated rate: build p50/p99 {loads[-1]['build_latency_ms']}")
-    return {"jobs": len(jobs), "points": points, "budget_bytes": budget,
+    return {"jobs": len(jobs), "points": points, "budget_bytes": budget, "batch_builds": SERVE_BATCH,
+            "saturated_s_one_by_one": wall1, "saturated_points_per_s_one_by_one": points / wall1,
             "saturated_s": wall, "saturated_jobs_per_s": rate, "saturated_points_per_s": points / wall,
             "peak_in_use_bytes": peak, "poisson": loads}
 

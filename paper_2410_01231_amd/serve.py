@@ -19,6 +19,16 @@ their collection is released fail then, and close() fails whatever can no
 longer run.  Results do not depend on what else runs: every kernel of the
 library is deterministic, so a collection's graph and a query's results are
 the same alone and in the mix.
+
+With batch_builds > 1 the dispatcher takes, behind a build of at most
+batch_max_rows rows it starts, the next queued builds of the same shape (d,
+K, S, R, iteration cap, seed, precision) and size limit that fit, up to
+batch_builds of them, and runs their NN-Descent as one batched build
+(pg_knn_build_batch: every kernel of an iteration runs once over all the
+collections, each with its own stop rule), then refines the collections side
+by side.  Each collection's graph is still the one it gets alone.  Small
+collections gain (their kernels are too small to fill the GPU on their own);
+larger ones already fill it and run alone.
 """
 from __future__ import annotations
 
@@ -96,9 +106,12 @@ class Server:
     for its workspace sizes.  Both can be replaced (tests drive the ledger
     with fakes)."""
 
-    def __init__(self, budget_bytes: int, workers: int = 4, device: int = 0, runner=None, footprint=None):
+    def __init__(self, budget_bytes: int, workers: int = 4, device: int = 0, runner=None, footprint=None,
+                 batch_builds: int = 1, batch_max_rows: int = 1 << 15):
         self.budget = int(budget_bytes)
         self.device = device
+        self.batch_builds = max(1, int(batch_builds))
+        self.batch_max_rows = int(batch_max_rows)
         self._runner = runner or self._gpu_run
         self._footprint = footprint or self._gpu_footprint
         self._pool = ThreadPoolExecutor(max_workers=workers)
@@ -115,6 +128,7 @@ class Server:
         self._querying: set[str] = set()   # collections with a query running
         self.peak_in_use = 0
         self.admission_log: list[str] = []
+        self.batch_log: list[list[str]] = []  # the builds of each batched build
         self._closed = False
         self._dispatcher = threading.Thread(target=self._dispatch, daemon=True)
         self._dispatcher.start()
@@ -209,14 +223,44 @@ class Server:
                         del self._queue[i]
                         break
                     self._cv.wait(timeout=0.05)
-                self._in_use += head.footprint
+                group = [head]
+                if head.kind == "build" and self.batch_builds > 1 and self._small(head.payload):
+                    group += self._take_batch(head, self._in_use + head.footprint)
+                    if len(group) > 1:
+                        self.batch_log.append([r.payload.job_id for r in group])
+                for r in group:
+                    self._in_use += r.footprint
+                    self.admission_log.append(f"{r.kind}:{r.payload.job_id}")
                 self._running += 1
                 if head.kind == "query":
                     self._querying.add(head.payload.job_id)
                 self.peak_in_use = max(self.peak_in_use, self._in_use)
-                name = head.payload.job_id
-                self.admission_log.append(f"{head.kind}:{name}")
-            self._pool.submit(self._execute, head)
+            if len(group) > 1:
+                self._pool.submit(self._execute_batch, group)
+            else:
+                self._pool.submit(self._execute, head)
+
+    @staticmethod
+    def _shape(job):
+        return (job.X.shape[1], job.K, job.S, job.R, job.max_iters, job.seed, job.precision)
+
+    def _small(self, job) -> bool:
+        return job.X.shape[0] <= self.batch_max_rows
+
+    def _take_batch(self, head, in_use):
+        """The queued builds after `head`, in order, with its shape and that
+        fit, up to batch_builds in all (caller holds the lock)."""
+        taken, keep = [], collections.deque()
+        for r in self._queue:
+            if (r.kind == "build" and len(taken) + 1 < self.batch_builds and self._small(r.payload) and
+                    self._shape(r.payload) == self._shape(head.payload) and
+                    in_use + r.footprint <= self.budget):
+                taken.append(r)
+                in_use += r.footprint
+            else:
+                keep.append(r)
+        self._queue = keep
+        return taken
 
     def _pick(self):
         """Index of the next request to start: builds in arrival order (a build
@@ -279,6 +323,37 @@ class Server:
                     self._querying.discard(req.payload.job_id)
                 self._cv.notify_all()
 
+    def _execute_batch(self, group) -> None:
+        t0 = time.perf_counter()
+        for r in group:
+            r.timing.started = t0
+        try:
+            graphs = self._runner("build_batch", [r.payload for r in group], None)
+            errors = [None] * len(group)
+        except BaseException as e:  # every build of the batch fails
+            graphs, errors = [None] * len(group), [e] * len(group)
+        t1 = time.perf_counter()
+        with self._cv:
+            for r, graph, err in zip(group, graphs, errors):
+                jid = r.payload.job_id
+                r.timing.finished = t1
+                if err is not None:
+                    self._state[jid] = "failed"
+                    self._fail_queued(jid, f"collection {jid!r} failed to build: {err}")
+                elif self._state.get(jid) != "released":
+                    self._graphs[jid] = graph
+                    self._state[jid] = "ready"
+                    self._resident[jid] = r.resident
+                    self._in_use += r.resident
+                self._in_use -= r.footprint
+            self._running -= 1
+            self._cv.notify_all()
+        for r, graph, err in zip(group, graphs, errors):
+            if err is not None:
+                r.future.set_exception(err)
+            else:
+                r.future.set_result((graph, r.timing))
+
     # --------------------------------------------------------------- GPU side
     def _gpu_footprint(self, kind, payload):
         from . import pg
@@ -294,10 +369,52 @@ class Server:
         prune_ws = pg.prune_workspace_bytes(n, d, job.K, job.R)
         return rows + graph + lists + knn_ws + prune_ws, rows + graph
 
+    def _gpu_build_batch(self, jobs):
+        """NN-Descent of every job in one batched build, then the jobs'
+        refinements side by side, each on a stream and context of its own
+        (which then serve the collection's queries)."""
+        import torch
+
+        from . import pg
+        stream = torch.cuda.Stream(self.device)
+        dev = f"cuda:{self.device}"
+        with torch.cuda.device(self.device), torch.cuda.stream(stream):
+            ctx = pg.Context(self.device, stream)
+            off = np.concatenate([[0], np.cumsum([j.X.shape[0] for j in jobs])]).astype(np.int64)
+            Xcat = torch.empty((int(off[-1]), jobs[0].X.shape[1]), dtype=torch.float32, device=dev)
+            for c, job in enumerate(jobs):
+                Xcat[int(off[c]):int(off[c + 1])].copy_(torch.from_numpy(np.ascontiguousarray(job.X,
+                                                                                               dtype=np.float32)))
+            j0 = jobs[0]
+            ids, d2, iters = pg.knn_build_batch(Xcat, off, j0.K, S=j0.S, max_iters=j0.max_iters, seed=j0.seed,
+                                                delta=0.001, precision=j0.precision, ctx=ctx)
+            stream.synchronize()
+
+        def refine(c):
+            job = jobs[c]
+            a, b = int(off[c]), int(off[c + 1])
+            qs = torch.cuda.Stream(self.device)
+            with torch.cuda.device(self.device), torch.cuda.stream(qs):
+                qctx = pg.Context(self.device, qs)
+                Xd = Xcat[a:b].clone()
+                g = pg.prune(Xd, ids[a:b], job.R, cand_d2=d2[a:b], ctx=qctx)
+                x16, exact = pg.half_rows(Xd, ctx=qctx)
+                entries = torch.cat([g["ep"], g["roots"]]).contiguous()
+                qs.synchronize()
+            return {"X": Xd, "ids": g["ids"], "deg": g["deg"], "ep": g["ep"], "roots": g["roots"],
+                    "entries": entries, "x16": x16 if exact else None, "ctx": qctx, "stream": qs,
+                    "knn_stats": {"iters": iters[c]}}
+        with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+            graphs = list(ex.map(refine, range(len(jobs))))
+        del Xcat, ids, d2
+        return graphs
+
     def _gpu_run(self, kind, payload, graph):
         import torch
 
         from . import pg
+        if kind == "build_batch":
+            return self._gpu_build_batch(payload)
         if kind == "build":
             job = payload
             stream = torch.cuda.Stream(self.device)

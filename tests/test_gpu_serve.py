@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 def _jobs(datagen):
     from paper_2410_01231_amd.serve import BuildJob, QueryBatch
-    specs = [(2500, 32), (4000, 96), (3000, 48), (6000, 32), (2000, 128), (5000, 64)]
+    specs = [(2500, 32), (4000, 96), (3000, 32), (6000, 32), (2000, 128), (5000, 64), (1500, 32)]
     jobs, queries = [], []
     for i, (n, d) in enumerate(specs):
         X, Q = datagen.unit_mixture(n, 96, d=d, n_clusters=20, seed=50 + i)
@@ -23,7 +23,8 @@ def _host(g):
     return {k: g[k].cpu().numpy() for k in ("ids", "deg", "ep", "roots")}
 
 
-def test_results_alone_equal_results_in_the_mix(datagen):
+@pytest.fixture(scope="module")
+def alone(datagen):
     from paper_2410_01231_amd.serve import Server
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     jobs, queries = _jobs(datagen)
@@ -36,11 +37,19 @@ def test_results_alone_equal_results_in_the_mix(datagen):
         alone_q[j.job_id] = [srv.submit_query(q).result(timeout=300)[0] for q in qs]
         srv.release(j.job_id)
     srv.close()
+    return jobs, queries, alone_g, alone_q
+
+
+@pytest.mark.parametrize("batch", [1, 4])
+def test_results_alone_equal_results_in_the_mix(alone, batch):
+    # batch > 1: compatible builds run as one batched NN-Descent build
+    from paper_2410_01231_amd.serve import Server
+    jobs, queries, alone_g, alone_q = alone
     # in the mix: everything submitted at once, four in flight, a budget that
     # holds only a few collections at a time
     fps = sorted((Server._gpu_footprint(None, "build", j)[0] for j in jobs), reverse=True)
     budget = fps[0] + fps[1] + fps[2]
-    srv = Server(budget, workers=4)
+    srv = Server(budget, workers=4, batch_builds=batch)
     fb = [srv.submit_build(j) for j in jobs]
     fq = [[srv.submit_query(q) for q in qs] for qs in queries]
     for j, f, qs in zip(jobs, fb, fq):
@@ -53,5 +62,8 @@ def test_results_alone_equal_results_in_the_mix(datagen):
             assert np.array_equal(ids, want[0]) and np.array_equal(d2, want[1]), j.job_id
         srv.release(j.job_id)
     srv.close()
-    print(f"[serve] budget {budget} B, peak in use {srv.peak_in_use} B, order {srv.admission_log}", flush=True)
+    print(f"[serve] budget {budget} B, peak in use {srv.peak_in_use} B, order {srv.admission_log}, "
+          f"batches {srv.batch_log}", flush=True)
+    if batch > 1:
+        assert srv.batch_log  # some builds ran batched
     assert srv.peak_in_use <= budget

@@ -180,3 +180,43 @@ def test_queries_of_one_collection_wait_outside_admission():
     assert q1.result(timeout=5)[0] == "A" and q2.result(timeout=5)[0] == "A"
     assert order == ["A", "B", "A"]
     srv.close()
+
+
+def test_compatible_builds_are_batched_within_the_budget():
+    # batch_builds = 3: behind the build it starts, the dispatcher takes the
+    # next queued builds of the same shape that fit, up to three in all; a
+    # build of another shape and one that does not fit wait for later
+    batches = []
+
+    def runner(kind, payload, graph):
+        if kind == "build_batch":
+            batches.append([j.job_id for j in payload])
+            return [{"graph_of": j.job_id} for j in payload]
+        if kind == "build":
+            batches.append([payload.job_id])
+            return {"graph_of": payload.job_id}
+        return ("answer", payload.job_id, graph["graph_of"])
+
+    sizes = {"A": 10, "B": 10, "W": 10, "C": 10, "D": 90, "E": 10, "F": 10}
+
+    def footprint(kind, payload):
+        return (1, 0) if kind == "query" else (sizes[payload.job_id], 2)
+
+    srv = Server(100, workers=1, runner=runner, footprint=footprint, batch_builds=3)
+    wide = BuildJob("W", np.zeros((4, 8), np.float32))
+    futs = [srv.submit_build(job(x)) for x in "AB"] + [srv.submit_build(wide)] + \
+        [srv.submit_build(job(x)) for x in "CDEF"]
+    q = srv.submit_query(QueryBatch("C", np.zeros((1, 4), np.float32)))
+    for f, name in zip(futs, "ABWCDEF"):
+        g, _ = f.result(timeout=5)
+        assert g == {"graph_of": name}
+    assert q.result(timeout=5)[0] == ("answer", "C", "C")
+    srv.close()
+    # every build ran exactly once; batches hold one shape and fit the budget
+    assert sorted(sum(batches, [])) == sorted("ABWCDEF")
+    assert batches[0] == ["A", "B", "C"]
+    for b in batches:
+        assert len(b) <= 3
+        assert len({("W" in b and x == "W") or x == "W" for x in b}) == 1
+        assert sum(sizes[x] for x in b) <= 100
+    assert srv.peak_in_use <= 100
