@@ -527,22 +527,26 @@ extern "C" pg_status pg_search(pg_ctx *ctx, const float *X, int64_t n, int32_t d
 namespace pgi {
 
 // FP16 copy of the rows of X (row stride d rounded up to 8, zero padded);
-// *exact becomes 0 if any element does not survive the round trip
+// *exact becomes 0 if any element does not survive the round trip.  Grid
+// stride; one flag update per block at most (updates of one address from
+// every block serialise, so one per element group would dominate the copy).
 __global__ __launch_bounds__(256) void k_half_rows(const float *__restrict__ X, int64_t n, int d, int64_t ldx,
                                                    _Float16 *__restrict__ X16, int64_t ld16,
                                                    int32_t *__restrict__ exact) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
-    if (t < n * ld16) {
+    const int64_t total = n * ld16;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = t / ld16;
         const int c = (int)(t % ld16);
         float x = 0.f;
         if (c < d) x = X[r * ldx + c];
         const _Float16 h = (_Float16)x;
         X16[t] = h;
-        bad = (float)h != x;
+        bad |= (float)h != x;
     }
-    if (__ballot(bad) != 0 && lane_id() == 0) atomicAnd(exact, 0);
+    if (__syncthreads_or(bad) && threadIdx.x == 0 && __atomic_load_n(exact, __ATOMIC_RELAXED) != 0)
+        atomicAnd(exact, 0);
 }
 
 __global__ void k_set_flag(int32_t *__restrict__ p) { *p = 1; }
@@ -562,7 +566,8 @@ extern "C" pg_status pg_half_rows(pg_ctx *ctx, const float *X, int64_t n, int32_
     const int64_t ld16 = ((int64_t)d + 7) & ~(int64_t)7;
     hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, ctx->stream, exact);
     const int64_t total = n * ld16;
-    hipLaunchKernelGGL(k_half_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, ctx->stream, X, n, d, ldx,
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, (int64_t)ctx->num_cu * 16);
+    hipLaunchKernelGGL(k_half_rows, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, X, n, d, ldx,
                        reinterpret_cast<_Float16 *>(X16), ld16, exact);
     PG_HIP(hipGetLastError());
     return PG_OK;

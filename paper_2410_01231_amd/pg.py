@@ -182,11 +182,11 @@ def _dev_i32(t, name):
     return t.contiguous()
 
 
-def knn_workspace_bytes(n, d, K, S=None, max_iters=12, precision=FP32):
+def knn_workspace_bytes(n, d, K, S=None, max_iters=12, precision=FP32, bucket_cap=0):
     """Workspace bytes pg_knn_build needs for n rows of d dimensions."""
     lib = load_library()
     S = (K + 1) // 2 if S is None else S
-    p = KnnParams(K=K, S=S, max_iters=max_iters, precision=precision)
+    p = KnnParams(K=K, S=S, max_iters=max_iters, precision=precision, bucket_cap=bucket_cap)
     ws = c_size_t()
     _check(lib.pg_knn_build_workspace(ctypes.byref(p), n, d, ctypes.byref(ws)), "workspace")
     return int(ws.value)
