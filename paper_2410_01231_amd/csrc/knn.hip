@@ -531,7 +531,7 @@ __global__ void k_spill_scatter(const int32_t *__restrict__ spill_t, const uint6
 
 constexpr int JW = 2;            // sources (waves) per workgroup
 constexpr int JT = JW * PG_WAVE;
-constexpr int JDC = 16;          // dims per LDS chunk
+constexpr int JDC = 8;           // dims per LDS chunk
 constexpr int TRW = 4, TCL = 8;  // largest micro-tile: 4 new members x 8 members
 template <int R, int C>
 struct JoinTile {
@@ -566,7 +566,10 @@ static size_t join_lds_bytes(int maxm) { return JW * join_wave_lds(maxm); }
 // accumulates in registers in the canonical order (dims ascending, one fma
 // per dim).  Proposals are counted per (lane, member), ranges are reserved
 // per member in the node's bucket (then the spill list), and written.
-__global__ __launch_bounds__(JT) void k_join(
+// Held to three waves per SIMD (167 VGPRs with 8-dimension chunks; 16-dim
+// chunks took 221 and two waves): GIST-shaped join 1.42 -> 1.32 s,
+// Deep-shaped 3.13 -> 2.26 s.  Four waves would spill.
+__global__ __launch_bounds__(JT, 3) void k_join(
     const float *__restrict__ X, int64_t ldx, int d, int K, const int32_t *__restrict__ jn,
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
     const int32_t *__restrict__ jo_c, int JO, const uint64_t *__restrict__ keys,
@@ -1234,7 +1237,7 @@ static size_t join_hybrid_lds_bytes(int maxm) {
 }
 
 template <int P>
-__global__ __launch_bounds__(HW * PG_WAVE, 2) void k_join_hybrid(
+__global__ __launch_bounds__(HW * PG_WAVE, 3) void k_join_hybrid(
     const float *__restrict__ X, int64_t ldx, const void *__restrict__ X16, int d, int d16,
     const float *__restrict__ norms, int K, const int32_t *__restrict__ jn,
     const int32_t *__restrict__ jn_c, int JN, const int32_t *__restrict__ jo,
