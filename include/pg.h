@@ -195,8 +195,8 @@ pg_status pg_knn_build_batch(pg_ctx *ctx, const float *X, int64_t n, int32_t d, 
  * Results are those of pg_knn_build with the same arguments.  Builds whose
  * workspace (pg_knn_build_workspace) exceeds PG_NOALLOC_WS_BYTES fail with
  * PG_ENOMEM before any work is enqueued: at K = 32, S = 16 that is up to
- * n = 39,488 rows with PG_FP32 (fewer with PG_FP16 / PG_BF16, which also keep
- * a 16-bit copy of X there: 36,710 rows at d = 128, 27,160 at d = 768).  The call allocates nothing (no hipMalloc / hipFree).
+ * n = 30,788 rows with PG_FP32 (fewer with PG_FP16 / PG_BF16, which also keep
+ * a 16-bit copy of X there: 29,074 rows at d = 128, 22,740 at d = 768).  The call allocates nothing (no hipMalloc / hipFree).
  * Every call on a device shares that device's array: calls that overlap on
  * one device (several host threads, or several streams in flight) race and
  * corrupt each other's results, so the caller must serialise them. */
