@@ -561,8 +561,8 @@ static size_t join_lds_bytes(int maxm) { return JW * join_wave_lds(maxm); }
 // JDC dims at a time: with 4 x 8 micro-tiles a lane's 8 consecutive members
 // at one dim are two conflict-free 16-byte reads and its 4 new members one
 // (shared by the lanes of the same row block).  The pair set is covered by
-// micro-tiles of 4 x 8, 2 x 4 or 1 x 2 (new members x members, the smallest
-// shape that needs no more rounds), one per lane per round; every pair's squared distance
+// micro-tiles of 4 x 8, 4 x 4, 2 x 4 or 1 x 2 (new members x members, the
+// smallest shape that needs no more rounds), one per lane per round; every pair's squared distance
 // accumulates in registers in the canonical order (dims ascending, one fma
 // per dim).  Proposals are counted per (lane, member), ranges are reserved
 // per member in the node's bucket (then the spill list), and written.
@@ -621,19 +621,20 @@ __global__ __launch_bounds__(JT, 3) void k_join(
         const int e = lane + PG_WAVE * j;
         fid[j] = e < mp * (JDC / 4) ? ids[e / (JDC / 4)] : -1;
     }
-    // micro-tiles of TR new members x TC members (TC = 2 TR) that hold a pair
-    // with col > row: cb >= rb / 2
+    // micro-tiles of TR new members x TC members that hold a pair with col >
+    // row: cb >= (TR rb + 1) / TC in row block rb
     auto tiles = [&](int tr, int tc) {
         const int RB = (nn + tr - 1) / tr, CB = mp / tc;
         int T = 0;
-        for (int rb = 0; rb < RB; ++rb) T += CB - (rb >> 1);
+        for (int rb = 0; rb < RB; ++rb) T += CB - (tr * rb + 1) / tc;
         return T;
     };
     auto rounds = [&](auto shape) {
         constexpr int TR = decltype(shape)::rows, TC = decltype(shape)::cols;
-        static_assert(TC == 2 * TR && TR * TC <= 32, "micro-tile shape");
-        // bit c of every row of a lane's pair mask
-        constexpr uint32_t col_bits = TR == 4 ? 0x01010101u : (TR == 2 ? 0x11u : 0x1u);
+        static_assert(TC % 4 == 0 || TC == 2, "micro-tile columns: one or two LDS reads");
+        static_assert(TR * TC <= 32, "micro-tile shape");
+        // bit c of every row of a lane's pair mask (bit a TC + c)
+        constexpr uint32_t col_bits = TR == 4 ? (TC == 8 ? 0x01010101u : 0x1111u) : (TR == 2 ? 0x11u : 0x1u);
         const int CB = mp / TC;
         const int T = tiles(TR, TC);
         for (int round0 = 0; round0 < T; round0 += PG_WAVE) {
@@ -643,12 +644,12 @@ __global__ __launch_bounds__(JT, 3) void k_join(
                 int b = round0 + lane;
                 if (b < T) {
                     int rb = 0;
-                    while (b >= CB - (rb >> 1)) {
-                        b -= CB - (rb >> 1);
+                    while (b >= CB - (TR * rb + 1) / TC) {
+                        b -= CB - (TR * rb + 1) / TC;
                         ++rb;
                     }
                     brb = rb;
-                    bcb = (rb >> 1) + b;
+                    bcb = (TR * rb + 1) / TC + b;
                 }
             }
 #pragma unroll
@@ -792,15 +793,17 @@ __global__ __launch_bounds__(JT, 3) void k_join(
     };
     // Every lane takes one micro-tile per round, and a round costs its wave the
     // full dimension loop whatever the number of busy lanes.  Small join sets
-    // (few new members) leave most lanes idle with 4 x 8 tiles; 2 x 4 and 1 x 2
-    // tiles spread the same pairs over more lanes.  The smallest shape that
-    // needs no more rounds than 4 x 8 is taken (the rows are staged once per
-    // round).
+    // (few new members) leave most lanes idle with 4 x 8 tiles; 4 x 4, 2 x 4
+    // and 1 x 2 tiles spread the same pairs over more lanes.  The smallest
+    // shape that needs no more rounds than 4 x 8 is taken (the rows are staged
+    // once per round).
     const int r48 = (tiles(4, 8) + PG_WAVE - 1) / PG_WAVE;
     if ((tiles(1, 2) + PG_WAVE - 1) / PG_WAVE <= r48)
         rounds(JoinTile<1, 2>{});
     else if ((tiles(2, 4) + PG_WAVE - 1) / PG_WAVE <= r48)
         rounds(JoinTile<2, 4>{});
+    else if ((tiles(4, 4) + PG_WAVE - 1) / PG_WAVE <= r48)
+        rounds(JoinTile<4, 4>{});
     else
         rounds(JoinTile<4, 8>{});
     // one atomic per wave

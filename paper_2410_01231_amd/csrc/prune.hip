@@ -370,6 +370,8 @@ __global__ __launch_bounds__(256) void k_prune_prep_mixed(const float *__restric
 constexpr int PM_DC = 32;            // dimensions per staged chunk
 constexpr int PM_RS = PM_DC + 8;     // LDS row stride in halves (16-byte pad)
 constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept nodes
+constexpr int PM_LIST = 1024;        // undecided pairs listed before their chains run
+constexpr int PM_PF = PM_ROWS * (PM_DC / 8) / PG_WAVE;  // 16-byte row loads per lane and chunk
 
 // One wave per node, rounds of up to 64 candidates as in k_prune; the
 // distances to u are the given (canonical) ones, the pairwise ones come from
@@ -389,7 +391,7 @@ constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept 
 // test involves only the three points, so it is skipped now.  k2p counts the
 // pairs skipped and the pairs tested.
 template <bool MIX>
-__global__ __launch_bounds__(64, 4) void k_prune_mfma(
+__global__ __launch_bounds__(64, 3) void k_prune_mfma(
     const _Float16 *__restrict__ X16, int d16, const float *__restrict__ norms, int64_t n,
     const int32_t *__restrict__ src1, const float *__restrict__ src1_d2, int C1,
     const int32_t *__restrict__ src1_deg, const int64_t *__restrict__ src2_off,
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
     __shared__ float cn[PG_WAVE], kn[PG_WAVE];
     // mixed: pairs of the current tile left to the chains (row << 6 | column),
     // and the occlusion bits they produce
-    __shared__ uint16_t rl[MIX ? 1024 : 1];
+    __shared__ uint16_t rl[MIX ? PM_LIST : 1];
     __shared__ unsigned long long kill_lds[MIX ? PG_WAVE : 1];
     __shared__ unsigned long long occk_lds;
     __shared__ int32_t prev_lds[PG_WAVE];
@@ -488,28 +490,15 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             if (lane == 0) occk_lds = 0;
             __builtin_amdgcn_wave_barrier();
         }
-        // mixed: the undecided pairs of a tile (bit g of umask: register g,
-        // row rowof(g), column `col`) are listed and decided on the chains;
-        // kept: the rows are kept nodes (occk_lds), else candidates (kill_lds)
-        auto settle = [&](uint32_t umask, auto rowof, int col, bool kept) {
-            const int nu = __popc(umask);
-            int ro = nu;
-#pragma unroll
-            for (int o = 1; o < PG_WAVE; o <<= 1) {
-                const int t = __shfl_up(ro, o, PG_WAVE);
-                if (lane >= o) ro += t;
-            }
-            const int rtot = __shfl(ro, PG_WAVE - 1, PG_WAVE);
-            ro -= nu;
-            if (rtot == 0) return;
-            uint32_t mm = umask;
-            while (mm) {
-                const int g = __builtin_ctz(mm);
-                mm &= mm - 1;
-                rl[ro++] = (uint16_t)((rowof(g) << 6) | col);
-            }
+        // mixed: the undecided pairs of the round's tiles (bit g of umask:
+        // register g, row rowof(g), column `col`) are listed, then decided on
+        // the chains in one pass per kind; kept: the rows are kept nodes
+        // (occk_lds), else candidates (kill_lds)
+        int rl_n = 0;  // entries listed (the same on every lane)
+        auto flush = [&](bool kept) {
+            if (rl_n == 0) return;
             __builtin_amdgcn_wave_barrier();
-            for (int e = lane; e < rtot; e += PG_WAVE) {
+            for (int e = lane; e < rl_n; e += PG_WAVE) {
                 const int ent = rl[e], i = ent >> 6, j = ent & 63;
                 const uint64_t ki = kept ? kept_key[i] : chunk_key[i], kj = chunk_key[j];
                 const float b = dist_chain(X + (int64_t)key_id(ki) * ldx, X + (int64_t)key_id(kj) * ldx, d);
@@ -521,6 +510,27 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            rl_n = 0;
+        };
+        auto settle = [&](uint32_t umask, auto rowof, int col, bool kept) {
+            const int nu = __popc(umask);
+            int ro = nu;
+#pragma unroll
+            for (int o = 1; o < PG_WAVE; o <<= 1) {
+                const int t = __shfl_up(ro, o, PG_WAVE);
+                if (lane >= o) ro += t;
+            }
+            const int rtot = __shfl(ro, PG_WAVE - 1, PG_WAVE);
+            if (rtot == 0) return;
+            if (rl_n + rtot > PM_LIST) flush(kept);
+            ro += rl_n - nu;
+            uint32_t mm = umask;
+            while (mm) {
+                const int g = __builtin_ctz(mm);
+                mm &= mm - 1;
+                rl[ro++] = (uint16_t)((rowof(g) << 6) | col);
+            }
+            rl_n += rtot;
         };
         // mixed: decide a pair from its estimate when the bound allows;
         // returns 1 (occludes), 0 (does not) or 2 (undecided)
@@ -533,21 +543,37 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             if (!at.on && bh < pmix_lo(pmx, c, e, acc)) return 1;
             return 2;
         };
-        // stage rows [0, nrows) of this round (candidates, then kept nodes at
-        // 64..) for dimensions [c0, c0 + dc)
-        auto stage = [&](int c0, int dc, int nrows) {
+        // rows [0, nrows) of this round (candidates, then kept nodes at 64..)
+        // for dimensions [c0, c0 + dc): the next chunk loads into registers
+        // while the MFMAs read the current one from LDS
+        pm_f16x8 pf[PM_PF];
+        auto fetch = [&](int c0, int dc, int nrows) {
+            const int vpr = dc / 8;
+#pragma unroll
+            for (int t = 0; t < PM_PF; ++t) {
+                const int v = lane + t * PG_WAVE;
+                pf[t] = pm_f16x8{};
+                if (v < nrows * vpr) {
+                    const int r = v / vpr, c = (v - r * vpr) * 8;
+                    int32_t id = -1;
+                    if (r < 64)
+                        id = r < cm ? key_id(chunk_key[r]) : -1;
+                    else
+                        id = r - 64 < nk ? key_id(kept_key[r - 64]) : -1;
+                    if (id >= 0) pf[t] = *reinterpret_cast<const pm_f16x8 *>(X16 + (int64_t)id * d16 + c0 + c);
+                }
+            }
+        };
+        auto put = [&](int dc, int nrows) {
             const int vpr = dc / 8;
             __syncthreads();
-            for (int v = lane; v < nrows * vpr; v += PG_WAVE) {
-                const int r = v / vpr, c = (v - r * vpr) * 8;
-                int32_t id = -1;
-                if (r < 64)
-                    id = r < cm ? key_id(chunk_key[r]) : -1;
-                else
-                    id = r - 64 < nk ? key_id(kept_key[r - 64]) : -1;
-                pm_f16x8 x = pm_f16x8{};
-                if (id >= 0) x = *reinterpret_cast<const pm_f16x8 *>(X16 + (int64_t)id * d16 + c0 + c);
-                *reinterpret_cast<pm_f16x8 *>(rows + r * PM_RS + c) = x;
+#pragma unroll
+            for (int t = 0; t < PM_PF; ++t) {
+                const int v = lane + t * PG_WAVE;
+                if (v < nrows * vpr) {
+                    const int r = v / vpr, c = (v - r * vpr) * 8;
+                    *reinterpret_cast<pm_f16x8 *>(rows + r * PM_RS + c) = pf[t];
+                }
             }
             __syncthreads();
         };
@@ -560,9 +586,12 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             pm_f32x16 t00, t01, t11;
 #pragma unroll
             for (int g = 0; g < 16; ++g) t00[g] = t01[g] = t11[g] = 0.f;
+            const int nrows = two ? 64 : 32;
+            fetch(0, min(PM_DC, d16), nrows);
             for (int c0 = 0; c0 < d16; c0 += PM_DC) {
                 const int dc = min(PM_DC, d16 - c0);
-                stage(c0, dc, two ? 64 : 32);
+                put(dc, nrows);
+                if (c0 + PM_DC < d16) fetch(c0 + PM_DC, min(PM_DC, d16 - c0 - PM_DC), nrows);
                 for (int k = 0; k < dc; k += 16) {
                     const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
                     t00 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a0, t00, 0, 0, 0);
@@ -606,16 +635,21 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
                 cand_tile(t01, 0, 1);
                 cand_tile(t11, 1, 1);
             }
-            if (MIX) killv |= kill_lds[lane];
+            if (MIX) {
+                flush(false);
+                killv |= kill_lds[lane];
+            }
         }
         // ---- occlusion by the nodes kept in earlier rounds (second pass)
         if (nk > 0) {
             pm_f32x16 k0, k1;
 #pragma unroll
             for (int g = 0; g < 16; ++g) k0[g] = k1[g] = 0.f;
+            fetch(0, min(PM_DC, d16), PM_ROWS);
             for (int c0 = 0; c0 < d16; c0 += PM_DC) {
                 const int dc = min(PM_DC, d16 - c0);
-                stage(c0, dc, PM_ROWS);
+                put(dc, PM_ROWS);
+                if (c0 + PM_DC < d16) fetch(c0 + PM_DC, min(PM_DC, d16 - c0 - PM_DC), PM_ROWS);
                 for (int k = 0; k < dc; k += 16) {
                     const pm_f16x8 ak = *reinterpret_cast<const pm_f16x8 *>(rk + k);
                     const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
@@ -654,7 +688,10 @@ __global__ __launch_bounds__(64, 4) void k_prune_mfma(
             };
             kept_tile(k0, 0);
             if (two) kept_tile(k1, 1);
-            if (MIX) occk |= occk_lds;
+            if (MIX) {
+                flush(true);
+                occk |= occk_lds;
+            }
         }
         // ---- greedy scan of Alg. 3 over this round's candidates
         uint64_t dead = occk;
