@@ -2073,10 +2073,12 @@ static pg_status knn_build_run(pg_ctx *ctx, const float *X, int64_t n, int32_t d
         PG_HIP(hipGetLastError());
     }
     if (stats) stats->join_path = path;
-    // ---- locality order of the join sources (nearest of P pivot rows)
+    // ---- locality order of the join sources (nearest of P pivot rows).  The
+    // order never changes the result.  At 10M x 96, 256 pivots against 1024
+    // assign in 38 instead of 115 ms and cost the join 24 ms of locality.
     int32_t *order = (int32_t *)(w + L.order);
     {
-        const int64_t P = std::min<int64_t>(1024, n / 4096);
+        const int64_t P = std::min<int64_t>(256, n / 4096);
         if (P <= 1) {
             hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, order, n);
         } else {
