@@ -391,7 +391,7 @@ constexpr int PM_PF = PM_ROWS * (PM_DC / 8) / PG_WAVE;  // 16-byte row loads per
 // test involves only the three points, so it is skipped now.  k2p counts the
 // pairs skipped and the pairs tested.
 template <bool MIX>
-__global__ __launch_bounds__(64, 3) void k_prune_mfma(
+__global__ __launch_bounds__(64, MIX ? 3 : 4) void k_prune_mfma(
     const _Float16 *__restrict__ X16, int d16, const float *__restrict__ norms, int64_t n,
     const int32_t *__restrict__ src1, const float *__restrict__ src1_d2, int C1,
     const int32_t *__restrict__ src1_deg, const int64_t *__restrict__ src2_off,
@@ -544,8 +544,9 @@ __global__ __launch_bounds__(64, 3) void k_prune_mfma(
             return 2;
         };
         // rows [0, nrows) of this round (candidates, then kept nodes at 64..)
-        // for dimensions [c0, c0 + dc): the next chunk loads into registers
-        // while the MFMAs read the current one from LDS
+        // for dimensions [c0, c0 + dc).  Mixed: the next chunk loads into
+        // registers while the MFMAs read the current one from LDS (exact
+        // 16-bit data: loaded chunk by chunk, four waves per SIMD)
         pm_f16x8 pf[PM_PF];
         auto fetch = [&](int c0, int dc, int nrows) {
             const int vpr = dc / 8;
@@ -587,11 +588,12 @@ __global__ __launch_bounds__(64, 3) void k_prune_mfma(
 #pragma unroll
             for (int g = 0; g < 16; ++g) t00[g] = t01[g] = t11[g] = 0.f;
             const int nrows = two ? 64 : 32;
-            fetch(0, min(PM_DC, d16), nrows);
+            if (MIX) fetch(0, min(PM_DC, d16), nrows);
             for (int c0 = 0; c0 < d16; c0 += PM_DC) {
                 const int dc = min(PM_DC, d16 - c0);
+                if (!MIX) fetch(c0, dc, nrows);
                 put(dc, nrows);
-                if (c0 + PM_DC < d16) fetch(c0 + PM_DC, min(PM_DC, d16 - c0 - PM_DC), nrows);
+                if (MIX && c0 + PM_DC < d16) fetch(c0 + PM_DC, min(PM_DC, d16 - c0 - PM_DC), nrows);
                 for (int k = 0; k < dc; k += 16) {
                     const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
                     t00 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, a0, t00, 0, 0, 0);
@@ -645,11 +647,12 @@ __global__ __launch_bounds__(64, 3) void k_prune_mfma(
             pm_f32x16 k0, k1;
 #pragma unroll
             for (int g = 0; g < 16; ++g) k0[g] = k1[g] = 0.f;
-            fetch(0, min(PM_DC, d16), PM_ROWS);
+            if (MIX) fetch(0, min(PM_DC, d16), PM_ROWS);
             for (int c0 = 0; c0 < d16; c0 += PM_DC) {
                 const int dc = min(PM_DC, d16 - c0);
+                if (!MIX) fetch(c0, dc, PM_ROWS);
                 put(dc, PM_ROWS);
-                if (c0 + PM_DC < d16) fetch(c0 + PM_DC, min(PM_DC, d16 - c0 - PM_DC), PM_ROWS);
+                if (MIX && c0 + PM_DC < d16) fetch(c0 + PM_DC, min(PM_DC, d16 - c0 - PM_DC), PM_ROWS);
                 for (int k = 0; k < dc; k += 16) {
                     const pm_f16x8 ak = *reinterpret_cast<const pm_f16x8 *>(rk + k);
                     const pm_f16x8 a0 = *reinterpret_cast<const pm_f16x8 *>(r0 + k);
