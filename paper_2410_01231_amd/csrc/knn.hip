@@ -629,183 +629,212 @@ __global__ __launch_bounds__(JT, 3) void k_join(
         for (int rb = 0; rb < RB; ++rb) T += CB - (tr * rb + 1) / tc;
         return T;
     };
-    auto rounds = [&](auto shape) {
+    // one round: every lane sums the micro-tile of TR rows x TC columns at
+    // (row0, col0) of the join set over all dimensions, then the pairs are
+    // decided and emitted; a lane without a tile (have = false) sums rows 0
+    // and emits nothing
+    auto round = [&](auto shape, int row0, int col0, bool have) __attribute__((always_inline)) {
         constexpr int TR = decltype(shape)::rows, TC = decltype(shape)::cols;
         static_assert(TC % 4 == 0 || TC == 2, "micro-tile columns: one or two LDS reads");
         static_assert(TR * TC <= 32, "micro-tile shape");
         // bit c of every row of a lane's pair mask (bit a TC + c)
         constexpr uint32_t col_bits = TR == 4 ? (TC == 8 ? 0x01010101u : 0x1111u) : (TR == 2 ? 0x11u : 0x1u);
-        const int CB = mp / TC;
-        const int T = tiles(TR, TC);
-        for (int round0 = 0; round0 < T; round0 += PG_WAVE) {
-            float acc[TR][TC];
-            int brb = -1, bcb = 0;
-            {
-                int b = round0 + lane;
-                if (b < T) {
-                    int rb = 0;
-                    while (b >= CB - (TR * rb + 1) / TC) {
-                        b -= CB - (TR * rb + 1) / TC;
-                        ++rb;
-                    }
-                    brb = rb;
-                    bcb = (TR * rb + 1) / TC + b;
+        if (!have) row0 = col0 = 0;
+        float acc[TR][TC];
+#pragma unroll
+        for (int a = 0; a < TR; ++a)
+#pragma unroll
+            for (int c = 0; c < TC; ++c) acc[a][c] = 0.0f;
+        // the rows of the next chunk load while the current one is summed
+        float4 v[JPF];
+        auto fetch = [&](int c0) {
+            const int dl = min(JDC, d - c0);
+#pragma unroll
+            for (int j = 0; j < JPF; ++j) {
+                const int q = (lane + PG_WAVE * j) % (JDC / 4);
+                v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (fid[j] >= 0 && 4 * q < dl)
+                    v[j] = *reinterpret_cast<const float4 *>(X + (int64_t)fid[j] * ldx + c0 + 4 * q);
+            }
+        };
+        fetch(0);
+        for (int c0 = 0; c0 < d; c0 += JDC) {
+            const int dl = min(JDC, d - c0);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < JPF; ++j) {
+                const int e = lane + PG_WAVE * j;
+                if (e < mp * (JDC / 4)) {
+                    const int q = e % (JDC / 4), i = e / (JDC / 4);
+                    tile[(4 * q + 0) * MPS + i] = v[j].x;
+                    tile[(4 * q + 1) * MPS + i] = v[j].y;
+                    tile[(4 * q + 2) * MPS + i] = v[j].z;
+                    tile[(4 * q + 3) * MPS + i] = v[j].w;
                 }
             }
-#pragma unroll
-            for (int a = 0; a < TR; ++a)
-#pragma unroll
-                for (int c = 0; c < TC; ++c) acc[a][c] = 0.0f;
-            // the rows of the next chunk load while the current one is summed
-            float4 v[JPF];
-            auto fetch = [&](int c0) {
-                const int dl = min(JDC, d - c0);
-#pragma unroll
-                for (int j = 0; j < JPF; ++j) {
-                    const int q = (lane + PG_WAVE * j) % (JDC / 4);
-                    v[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (fid[j] >= 0 && 4 * q < dl)
-                        v[j] = *reinterpret_cast<const float4 *>(X + (int64_t)fid[j] * ldx + c0 + 4 * q);
+            if (c0 + JDC < d) fetch(c0 + JDC);
+            __builtin_amdgcn_wave_barrier();
+            const float *rp = tile + row0;
+            const float *cp = tile + col0;
+            for (int k = 0; k < dl; ++k) {
+                float rv[TR], cv[TC];
+                if constexpr (TR == 4) {
+                    const float4 r4 = *reinterpret_cast<const float4 *>(rp + k * MPS);
+                    rv[0] = r4.x, rv[1] = r4.y, rv[2] = r4.z, rv[3] = r4.w;
+                } else if constexpr (TR == 2) {
+                    const float2 r2 = *reinterpret_cast<const float2 *>(rp + k * MPS);
+                    rv[0] = r2.x, rv[1] = r2.y;
+                } else {
+                    rv[0] = rp[k * MPS];
                 }
-            };
-            fetch(0);
-            for (int c0 = 0; c0 < d; c0 += JDC) {
-                const int dl = min(JDC, d - c0);
-                __builtin_amdgcn_wave_barrier();
+                if constexpr (TC >= 4) {
 #pragma unroll
-                for (int j = 0; j < JPF; ++j) {
-                    const int e = lane + PG_WAVE * j;
-                    if (e < mp * (JDC / 4)) {
-                        const int q = e % (JDC / 4), i = e / (JDC / 4);
-                        tile[(4 * q + 0) * MPS + i] = v[j].x;
-                        tile[(4 * q + 1) * MPS + i] = v[j].y;
-                        tile[(4 * q + 2) * MPS + i] = v[j].z;
-                        tile[(4 * q + 3) * MPS + i] = v[j].w;
+                    for (int j = 0; j < TC; j += 4) {
+                        const float4 c4 = *reinterpret_cast<const float4 *>(cp + k * MPS + j);
+                        cv[j] = c4.x, cv[j + 1] = c4.y, cv[j + 2] = c4.z, cv[j + 3] = c4.w;
                     }
+                } else {
+                    const float2 c2 = *reinterpret_cast<const float2 *>(cp + k * MPS);
+                    cv[0] = c2.x, cv[1] = c2.y;
                 }
-                if (c0 + JDC < d) fetch(c0 + JDC);
-                __builtin_amdgcn_wave_barrier();
-                if (brb >= 0) {
-                    const float *rp = tile + TR * brb;
-                    const float *cp = tile + TC * bcb;
-                    for (int k = 0; k < dl; ++k) {
-                        float rv[TR], cv[TC];
-                        if constexpr (TR == 4) {
-                            const float4 r4 = *reinterpret_cast<const float4 *>(rp + k * MPS);
-                            rv[0] = r4.x, rv[1] = r4.y, rv[2] = r4.z, rv[3] = r4.w;
-                        } else if constexpr (TR == 2) {
-                            const float2 r2 = *reinterpret_cast<const float2 *>(rp + k * MPS);
-                            rv[0] = r2.x, rv[1] = r2.y;
-                        } else {
-                            rv[0] = rp[k * MPS];
-                        }
-                        if constexpr (TC >= 4) {
 #pragma unroll
-                            for (int j = 0; j < TC; j += 4) {
-                                const float4 c4 = *reinterpret_cast<const float4 *>(cp + k * MPS + j);
-                                cv[j] = c4.x, cv[j + 1] = c4.y, cv[j + 2] = c4.z, cv[j + 3] = c4.w;
-                            }
-                        } else {
-                            const float2 c2 = *reinterpret_cast<const float2 *>(cp + k * MPS);
-                            cv[0] = c2.x, cv[1] = c2.y;
-                        }
-#pragma unroll
-                        for (int a = 0; a < TR; ++a)
-#pragma unroll
-                            for (int c = 0; c < TC; ++c) {
-                                const float t = rv[a] - cv[c];
-                                acc[a][c] = fmaf(t, t, acc[a][c]);
-                            }
-                    }
-                }
-            }
-            // ---- emission: decide every pair once (bit masks), one LDS offset per
-            // (lane, member), reserve ranges per member, write
-            uint32_t to_row = 0, to_col = 0;  // bit a*8+c
-            int off_row[TR], off_col[TC];
-            if (brb >= 0) {
-#pragma unroll
-                for (int a = 0; a < TR; ++a) {
-                    const int r = TR * brb + a;
+                for (int a = 0; a < TR; ++a)
 #pragma unroll
                     for (int c = 0; c < TC; ++c) {
-                        const int col = TC * bcb + c;
-                        if (r >= nn || col >= m || (col < nn && col <= r)) continue;
-                        const float d2 = acc[a][c];
-                        const uint64_t kw = pack_key(d2, ids[col]), kv = pack_key(d2, ids[r]);
-                        // a repeat pass (mark != null) skips keys already listed, so
-                        // every repeat inserts at least one new key into each node it serves
-                        if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
-                            to_row |= 1u << (a * TC + c);
-                        if (mk[col] && kv < kth[col] && !(mark && list_has(keys + (int64_t)ids[col] * K, K, kv)))
-                            to_col |= 1u << (a * TC + c);
+                        const float t = rv[a] - cv[c];
+                        acc[a][c] = fmaf(t, t, acc[a][c]);
                     }
-                }
+            }
+        }
+        // ---- emission: decide every pair once (bit masks), one LDS offset per
+        // (lane, member), reserve ranges per member, write
+        uint32_t to_row = 0, to_col = 0;  // bit a*TC+c
+        int off_row[TR], off_col[TC];
+        if (have) {
 #pragma unroll
-                for (int a = 0; a < TR; ++a) {
-                    const int c_r = __popc((to_row >> (a * TC)) & ((1u << TC) - 1u));
-                    off_row[a] = c_r ? atomicAdd(&cnt[TR * brb + a], c_r) : 0;
-                }
+            for (int a = 0; a < TR; ++a) {
+                const int r = row0 + a;
 #pragma unroll
                 for (int c = 0; c < TC; ++c) {
-                    const int c_c = __popc(to_col & (col_bits << c));
-                    off_col[c] = c_c ? atomicAdd(&cnt[TC * bcb + c], c_c) : 0;
+                    const int col = col0 + c;
+                    if (r >= nn || col >= m || (col < nn && col <= r)) continue;
+                    const float d2 = acc[a][c];
+                    const uint64_t kw = pack_key(d2, ids[col]), kv = pack_key(d2, ids[r]);
+                    // a repeat pass (mark != null) skips keys already listed, so
+                    // every repeat inserts at least one new key into each node it serves
+                    if (mk[r] && kw < kth[r] && !(mark && list_has(keys + (int64_t)ids[r] * K, K, kw)))
+                        to_row |= 1u << (a * TC + c);
+                    if (mk[col] && kv < kth[col] && !(mark && list_has(keys + (int64_t)ids[col] * K, K, kv)))
+                        to_col |= 1u << (a * TC + c);
                 }
             }
-            __builtin_amdgcn_wave_barrier();
-            local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
-            __builtin_amdgcn_wave_barrier();
-            if (brb >= 0) {
 #pragma unroll
-                for (int a = 0; a < TR; ++a) {
-                    const int r = TR * brb + a;
+            for (int a = 0; a < TR; ++a) {
+                const int c_r = __popc((to_row >> (a * TC)) & ((1u << TC) - 1u));
+                off_row[a] = c_r ? atomicAdd(&cnt[row0 + a], c_r) : 0;
+            }
 #pragma unroll
-                    for (int c = 0; c < TC; ++c) {
-                        const int col = TC * bcb + c;
-                        const uint32_t bit = 1u << (a * TC + c);
-                        if (!((to_row | to_col) & bit)) continue;
-                        const float d2 = acc[a][c];
-                        if (to_row & bit) {
-                            const int32_t v = ids[r];
-                            const int slot = base[r] + off_row[a]++;
-                            const uint64_t kw = pack_key(d2, ids[col]);
-                            if (slot < B)
-                                bucket[(int64_t)v * B + slot] = kw;
-                            else
-                                spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k,
-                                          seg_end, ovf_next, cslot);
-                        }
-                        if (to_col & bit) {
-                            const int32_t w = ids[col];
-                            const int slot = base[col] + off_col[c]++;
-                            const uint64_t kv = pack_key(d2, ids[r]);
-                            if (slot < B)
-                                bucket[(int64_t)w * B + slot] = kv;
-                            else
-                                spill_put(w, kv, sbase[col] + (slot - max(base[col], B)), spill_t, spill_k,
-                                          seg_end, ovf_next, cslot);
-                        }
+            for (int c = 0; c < TC; ++c) {
+                const int c_c = __popc(to_col & (col_bits << c));
+                off_col[c] = c_c ? atomicAdd(&cnt[col0 + c], c_c) : 0;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        local_props += reserve_ranges(m, ids, cnt, base, sbase, pcnt, B, cslot, seg_begin);
+        __builtin_amdgcn_wave_barrier();
+        if (have) {
+#pragma unroll
+            for (int a = 0; a < TR; ++a) {
+                const int r = row0 + a;
+#pragma unroll
+                for (int c = 0; c < TC; ++c) {
+                    const int col = col0 + c;
+                    const uint32_t bit = 1u << (a * TC + c);
+                    if (!((to_row | to_col) & bit)) continue;
+                    const float d2 = acc[a][c];
+                    if (to_row & bit) {
+                        const int32_t v = ids[r];
+                        const int slot = base[r] + off_row[a]++;
+                        const uint64_t kw = pack_key(d2, ids[col]);
+                        if (slot < B)
+                            bucket[(int64_t)v * B + slot] = kw;
+                        else
+                            spill_put(v, kw, sbase[r] + (slot - max(base[r], B)), spill_t, spill_k,
+                                      seg_end, ovf_next, cslot);
+                    }
+                    if (to_col & bit) {
+                        const int32_t w = ids[col];
+                        const int slot = base[col] + off_col[c]++;
+                        const uint64_t kv = pack_key(d2, ids[r]);
+                        if (slot < B)
+                            bucket[(int64_t)w * B + slot] = kv;
+                        else
+                            spill_put(w, kv, sbase[col] + (slot - max(base[col], B)), spill_t, spill_k,
+                                      seg_end, ovf_next, cslot);
                     }
                 }
             }
-            __builtin_amdgcn_wave_barrier();
         }
+        __builtin_amdgcn_wave_barrier();
+    };
+    // tile b of the row-major list of TR x TC micro-tiles (row block rb holds
+    // the column blocks cb >= (TR rb + 1) / TC); rb = -1 past the end
+    auto tile_at = [&](int b, int tr, int tc, int T, int &rb, int &cb) __attribute__((always_inline)) {
+        rb = -1, cb = 0;
+        if (b >= T) return;
+        const int CB = mp / tc;
+        int r = 0;
+        while (b >= CB - (tr * r + 1) / tc) {
+            b -= CB - (tr * r + 1) / tc;
+            ++r;
+        }
+        rb = r;
+        cb = (tr * r + 1) / tc + b;
     };
     // Every lane takes one micro-tile per round, and a round costs its wave the
-    // full dimension loop whatever the number of busy lanes.  Small join sets
-    // (few new members) leave most lanes idle with 4 x 8 tiles; 4 x 4, 2 x 4
-    // and 1 x 2 tiles spread the same pairs over more lanes.  The smallest
-    // shape that needs no more rounds than 4 x 8 is taken (the rows are staged
-    // once per round).
-    const int r48 = (tiles(4, 8) + PG_WAVE - 1) / PG_WAVE;
-    if ((tiles(1, 2) + PG_WAVE - 1) / PG_WAVE <= r48)
-        rounds(JoinTile<1, 2>{});
-    else if ((tiles(2, 4) + PG_WAVE - 1) / PG_WAVE <= r48)
-        rounds(JoinTile<2, 4>{});
-    else if ((tiles(4, 4) + PG_WAVE - 1) / PG_WAVE <= r48)
-        rounds(JoinTile<4, 4>{});
-    else
-        rounds(JoinTile<4, 8>{});
+    // full dimension loop (2 TR TC instructions per dimension) whatever the
+    // number of busy lanes, plus a staging of the member rows.  For the same
+    // number of rounds as 4 x 8 tiles, the cheapest covering is taken: a
+    // smaller shape on its own grid (small join sets keep more lanes busy),
+    // or 4 x 8 tiles with the last round's rem tiles split into 4 x 4, 2 x 4
+    // or 1 x 2 sub-tiles when rem <= 32, 16 or 4 (that round then costs a
+    // half, a quarter or a sixteenth of a full one).
+    const int T48 = tiles(4, 8), T44 = tiles(4, 4), T24 = tiles(2, 4), T12 = tiles(1, 2);
+    const int r48 = (T48 + PG_WAVE - 1) / PG_WAVE;
+    const int rem48 = T48 - (r48 - 1) * PG_WAVE;
+    const int r44 = (T44 + PG_WAVE - 1) / PG_WAVE, r24 = (T24 + PG_WAVE - 1) / PG_WAVE,
+              r12 = (T12 + PG_WAVE - 1) / PG_WAVE;
+    int best = 64 * (r48 - 1) + (rem48 > 32 ? 64 : rem48 > 16 ? 32 : rem48 > 4 ? 16 : 4), pick = 0;
+    if (r44 <= r48 && 32 * r44 < best) best = 32 * r44, pick = 1;
+    if (r24 <= r48 && 16 * r24 < best) best = 16 * r24, pick = 2;
+    if (r12 <= r48 && 4 * r12 < best) best = 4 * r12, pick = 3;
+    // shapes: 0 = 4 x 8, 1 = 4 x 4, 2 = 2 x 4, 3 = 1 x 2
+    const int nr = pick == 0 ? r48 : pick == 1 ? r44 : pick == 2 ? r24 : r12;
+    for (int r = 0; r < nr; ++r) {
+        int shape, rb, cb, row0, col0;
+        if (pick != 0) {
+            shape = pick;
+            const int tr = pick == 1 ? 4 : pick == 2 ? 2 : 1, tc = pick == 1 ? 4 : pick == 2 ? 4 : 2;
+            tile_at(r * PG_WAVE + lane, tr, tc, pick == 1 ? T44 : pick == 2 ? T24 : T12, rb, cb);
+            row0 = tr * rb;
+            col0 = tc * cb;
+        } else {
+            shape = (r < nr - 1 || rem48 > 32) ? 0 : rem48 > 16 ? 1 : rem48 > 4 ? 2 : 3;
+            const int sh = shape == 3 ? 4 : shape;  // log2 of the sub-tiles per 4 x 8 tile
+            const int sub = lane & ((1 << sh) - 1);
+            tile_at(r * PG_WAVE + (lane >> sh), 4, 8, T48, rb, cb);
+            row0 = 4 * rb + (shape == 2 ? 2 * (sub >> 1) : shape == 3 ? (sub >> 2) : 0);
+            col0 = 8 * cb + (shape == 1 ? 4 * sub : shape == 2 ? 4 * (sub & 1) : shape == 3 ? 2 * (sub & 3) : 0);
+        }
+        if (shape == 0)
+            round(JoinTile<4, 8>{}, row0, col0, rb >= 0);
+        else if (shape == 1)
+            round(JoinTile<4, 4>{}, row0, col0, rb >= 0);
+        else if (shape == 2)
+            round(JoinTile<2, 4>{}, row0, col0, rb >= 0);
+        else
+            round(JoinTile<1, 2>{}, row0, col0, rb >= 0);
+    }
     // one atomic per wave
 #pragma unroll
     for (int o = 1; o < PG_WAVE; o <<= 1) {
