@@ -89,6 +89,21 @@ def measured_traffic(path_name, workload):
     return float(m.group(1)) if m else None
 
 
+# issue ceiling of the FP32 direct form without packed FP32: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz lane instructions/s, two instructions (subtract, FMA) per
+# pair and dimension counted as 3 flops
+DIRECT_FORM_CEILING_TFLOPS = 256 * 4 * 16 * 2.4e9 * 1.5 / 1e12
+
+
+def compulsory_bytes(st, n, d, K, S, sixteen):
+    """Bytes an NN-Descent build must move at least: per iteration the rows
+    once (FP32, or the 16-bit copy), the lists read and written, the sampled
+    and reverse sets written and read, and 12 bytes per proposal."""
+    row = 2 * ((d + 15) // 16 * 16) if sixteen else 4 * d
+    fixed = n * row + 2 * n * K * 8 + 2 * n * (2 * S + K + S) * 4
+    return sum(fixed + 12 * p for p in st["proposals"][:st["iters"]])
+
+
 def roofline(join_path, work, launches, total_ms, name, workload):
     """Roofline entry of the join kernel: flops or bytes per launch over its mean duration."""
     avg_ms = total_ms / max(launches, 1)
@@ -100,12 +115,16 @@ def roofline(join_path, work, launches, total_ms, name, workload):
     else:
         bound, unit, peak, scale = "hbm", "GB/s", PEAK_HBM_GBS, 1e9
     achieved = per_launch / (avg_ms / 1000.0) / scale if launches else 0.0
-    return {"kernel": "join", "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak,
-            "traffic": measured_traffic(name, workload),
-            "work_per_launch": per_launch,
-            "work_unit": "flops" if scale == 1e12 else "bytes",
-            "avg_launch_ms": avg_ms, "launches": launches}
+    out = {"kernel": "join", "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+           "frac": achieved / peak,
+           "traffic": measured_traffic(name, workload),
+           "work_per_launch": per_launch,
+           "work_unit": "flops" if scale == 1e12 else "bytes",
+           "avg_launch_ms": avg_ms, "launches": launches}
+    if join_path == "fp32-valu":
+        out["issue_ceiling"] = DIRECT_FORM_CEILING_TFLOPS
+        out["frac_of_issue_ceiling"] = achieved / DIRECT_FORM_CEILING_TFLOPS
+    return out
 
 
 def mfma_utilisation(join_path, pairs, d, join_ms):
@@ -684,7 +703,17 @@ def run_path(steps, warmup, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path, name)
         "kernel_ms_per_step": {k: v[0] / steps for k, v in kt_.items()},
         "roofline": roofline(st["join_path"], join_work, join_n, join_ms, path["name"], name),
         "mfma_utilisation": mfma_utilisation(st["join_path"], sum(st["pairs"]) * steps, w["d"], join_ms),
+        "bytes_per_build": bytes_per_build(st, w, join_n / steps, path["name"], name),
     }
+
+
+def bytes_per_build(st, w, join_launches, path_name, workload):
+    """The build's compulsory bytes beside the join's HBM traffic measured by
+    the counters (per launch, from the profile) times its launches."""
+    tr = measured_traffic(path_name, workload)
+    return {"compulsory": compulsory_bytes(st, w["n"], w["d"], w["K"], w["S"],
+                                           not st["join_path"].startswith("fp32")),
+            "join_measured": tr * join_launches if tr is not None else None}
 
 
 if __name__ == "__main__":
