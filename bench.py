@@ -63,6 +63,10 @@ WORKLOADS = {
                  gen="uniform_int", desc="uniform-int 10kx128, K=32 R=32 FP32"),
 }
 SERVE_BATCH = 16  # builds of one shape the serving loop runs as one batched build
+# knobs of the build (bucket capacity, first-iteration passes) the autotuner
+# chose for each set and join precision on one MI355X (`--tune` writes it);
+# they change the speed of a build, never its lists
+TUNE_CACHE = os.path.join(ROOT, "paper_2410_01231_amd", "tune_cache.json")
 L_LADDER = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector and FP32 MFMA (dense)
 PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 MFMA
@@ -248,7 +252,15 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "HBM byte counters against a copy of known size) and exit")
+    ap.add_argument("--tune", action="store_true",
+                    help="only tune the build knobs of the suite's sets (or --workload) per join "
+                         "precision into --tune-cache and exit")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, metavar="PATH")
+    ap.add_argument("--default-knobs", action="store_true",
+                    help="build with the library's default knobs, not the tuned ones")
     args = ap.parse_args()
+    global TUNED
+    TUNED = not args.default_knobs
     if args.oracle_one_core:
         oracle_one_core()
         return
@@ -272,6 +284,9 @@ def main():
     from paper_2410_01231_amd import pg
     torch.cuda.set_device(0)
     ctx = pg.context(0)
+    if args.tune:
+        run_tune(args, pg, torch, ctx)
+        return
 
     names = SUITE if args.workload == "suite" else [args.workload]
     legs = {}
@@ -602,9 +617,13 @@ def run_path(steps, warmup, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path, name)
     prec = path["precision"]
     last = {}
 
+    knobs = tuned_knobs(pg, ctx, Xd, w, prec) if TUNED else None
+    log(f"[bench] {name} {path['name']} knobs {knobs or 'default'}")
+    kn = {k: v for k, v in (knobs or {}).items() if k != "precision"}
+
     def build():
         ids, d2, st = pg.knn_build(Xd, K, S=S, max_iters=w["iters"], seed=1, delta=0.001,
-                                   precision=prec, margin_rel=path.get("margin_rel", 0.0), ctx=ctx)
+                                   precision=prec, margin_rel=path.get("margin_rel", 0.0), ctx=ctx, **kn)
         g = pg.prune(Xd, ids, R, cand_d2=d2, ctx=ctx)
         last["d2"] = d2
         return ids, st, g
@@ -704,7 +723,39 @@ def run_path(steps, warmup, w, pg, torch, ctx, Xd, Qd, gt, kt, samp, path, name)
         "roofline": roofline(st["join_path"], join_work, join_n, join_ms, path["name"], name),
         "mfma_utilisation": mfma_utilisation(st["join_path"], sum(st["pairs"]) * steps, w["d"], join_ms),
         "bytes_per_build": bytes_per_build(st, w, join_n / steps, path["name"], name),
+        "knobs": knobs or "default",
     }
+
+
+TUNED = True
+
+
+def tuned_knobs(pg, ctx, Xd, w, prec):
+    """The autotuner's cached knobs for this set and precision, or None (the
+    library's defaults) when the shape is not in the cache.  The cache key
+    names the join path of the default build, taken from one iteration."""
+    from paper_2410_01231_amd import tune
+    _, _, st = pg.knn_build(Xd, w["K"], S=w["S"], max_iters=1, seed=1, ctx=ctx)
+    return tune.lookup(w["n"], w["d"], w["K"], w["S"], st["join_path"], prec, TUNE_CACHE)
+
+
+def run_tune(args, pg, torch, ctx):
+    """Tune the knobs of every set of the suite (or --workload) per join
+    precision and write them to --tune-cache."""
+    from paper_2410_01231_amd import tune
+    names = SUITE if args.workload == "suite" else [args.workload]
+    for name in names:
+        w = WORKLOADS[name]
+        X, _ = gen_data(w)
+        Xd = torch.from_numpy(X).cuda()
+        del X
+        for pname in w["paths"].split(","):
+            prec = PATHS[pname]["precision"]
+            kn = tune.tune_knn(Xd, w["K"], S=w["S"], seed=1, max_iters=w["iters"], delta=0.001,
+                               cache_path=args.tune_cache, ctx=ctx, precision=prec)
+            log(f"[bench] tuned {name} {pname}: {kn}")
+        del Xd
+        torch.cuda.empty_cache()
 
 
 def bytes_per_build(st, w, join_launches, path_name, workload):
