@@ -52,6 +52,27 @@ def built():
                 samp=np.random.default_rng(23).choice(N, size=SAMPLE, replace=False))
 
 
+def test_tuned_knobs_give_the_default_lists(built):
+    # the bucket capacity and first-iteration passes the benchmark takes from
+    # the autotuner's cache change the speed of the build, not its lists
+    import os
+    from paper_2410_01231_amd import tune
+    pg = built["pg"]
+    cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "paper_2410_01231_amd", "tune_cache.json")
+    kn = tune.lookup(N, D, K, S, "fp32-valu", pg.FP32, cache)
+    if kn is None:
+        pytest.skip("no tuned knobs for this shape")
+    kn = {k: v for k, v in kn.items() if k != "precision"}
+    t = pg.knn_build(built["Xd"], K, S=S, max_iters=T, seed=1, delta=0.001, precision=pg.FP32, **kn)
+    print(f"[fullsize-deep] tuned knobs {kn}: retries {t[2]['retries']}", flush=True)
+    a = built["f32"]
+    assert torch.equal(a[0], t[0]) and torch.equal(a[1], t[1])
+    assert a[2]["updates"] == t[2]["updates"]
+    del t
+    torch.cuda.empty_cache()
+
+
 def test_mixed_path_equals_fp32(built):
     a, b = built["f32"], built["f16"]
     assert a[2]["join_path"] == "fp32-valu" and b[2]["join_path"] == "bf16-mixed"
