@@ -796,21 +796,44 @@ __device__ __forceinline__ bool dkey_less(const DKey &a, const DKey &b) {
     return a.d2 < b.d2 || (a.d2 == b.d2 && a.id < b.id);
 }
 
+// One row per lane, the squared distance to the centroid summed in FP64 in
+// dimension order.  The rows reach the lanes through LDS, 16 dimensions at a
+// time: four lanes load one row's 64 bytes, so a load instruction touches 16
+// rows instead of 64.
+constexpr int AC_DC = 16;
+constexpr int AC_RS = AC_DC + 1;  // LDS row stride (floats): conflict-free column reads
+
 __global__ __launch_bounds__(256) void k_argmin_center(const float *__restrict__ X, int64_t n, int d,
                                                        int64_t ldx, const double *__restrict__ cen,
                                                        double *__restrict__ pd, int32_t *__restrict__ pid) {
     __shared__ double sd[256];
     __shared__ int32_t si[256];
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    DKey best{INFINITY, 0x7fffffff};
-    if (v < n) {
-        double s = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const double t = __dsub_rn((double)X[v * ldx + j], cen[j]);
+    __shared__ float rows[4][PG_WAVE * AC_RS];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 + wv * PG_WAVE;  // this wave's first row
+    const int64_t v = row0 + lane;
+    float *tile = rows[wv];
+    double s = 0.0;
+    for (int c0 = 0; c0 < d; c0 += AC_DC) {
+        const int dl = min(AC_DC, d - c0);
+#pragma unroll
+        for (int k = 0; k < AC_DC / 4; ++k) {
+            const int f = lane + PG_WAVE * k, r = f / (AC_DC / 4), q = f % (AC_DC / 4);
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row0 + r < n && 4 * q < dl)
+                x = *reinterpret_cast<const float4 *>(X + (row0 + r) * ldx + c0 + 4 * q);
+            float *t = tile + r * AC_RS + 4 * q;
+            t[0] = x.x, t[1] = x.y, t[2] = x.z, t[3] = x.w;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int j = 0; j < dl; ++j) {
+            const double t = __dsub_rn((double)tile[lane * AC_RS + j], cen[c0 + j]);
             s = __dadd_rn(s, __dmul_rn(t, t));
         }
-        best = {s, (int32_t)v};
+        __builtin_amdgcn_wave_barrier();
     }
+    DKey best{INFINITY, 0x7fffffff};
+    if (v < n) best = {s, (int32_t)v};
     sd[threadIdx.x] = best.d2;
     si[threadIdx.x] = best.id;
     __syncthreads();
