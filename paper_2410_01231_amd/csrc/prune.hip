@@ -371,6 +371,10 @@ constexpr int PM_DC = 32;            // dimensions per staged chunk
 constexpr int PM_RS = PM_DC + 8;     // LDS row stride in halves (16-byte pad)
 constexpr int PM_ROWS = 96;          // 64 round candidates, then up to 32 kept nodes
 constexpr int PM_LIST = 1024;        // undecided pairs listed before their chains run
+constexpr int PM_CD = 16;            // dimensions per LDS chunk of the chains' FP32 rows
+constexpr int PM_CS = PM_CD + 4;     // their LDS row stride (floats; 16-byte aligned)
+constexpr int PM_STAGE_D = 256;      // rows at least this long are staged for the chains
+static_assert(PM_ROWS * PM_CS * 4 <= PM_ROWS * PM_RS * 2, "the chains' rows fit in the 16-bit row buffer");
 constexpr int PM_PF = PM_ROWS * (PM_DC / 8) / PG_WAVE;  // 16-byte row loads per lane and chunk
 
 // One wave per node, rounds of up to 64 candidates as in k_prune; the
@@ -390,7 +394,7 @@ constexpr int PM_PF = PM_ROWS * (PM_DC / 8) / PG_WAVE;  // 16-byte row loads per
 // did not occlude the later (else the later would have been dropped); the
 // test involves only the three points, so it is skipped now.  k2p counts the
 // pairs skipped and the pairs tested.
-template <bool MIX>
+template <bool MIX, bool STG>
 __global__ __launch_bounds__(64, MIX ? 3 : 4) void k_prune_mfma(
     const _Float16 *__restrict__ X16, int d16, const float *__restrict__ norms, int64_t n,
     const int32_t *__restrict__ src1, const float *__restrict__ src1_d2, int C1,
@@ -409,6 +413,8 @@ __global__ __launch_bounds__(64, MIX ? 3 : 4) void k_prune_mfma(
     __shared__ unsigned long long kill_lds[MIX ? PG_WAVE : 1];
     __shared__ unsigned long long occk_lds;
     __shared__ int32_t prev_lds[PG_WAVE];
+    // mixed: ids of the rows the listed pairs involve, in staging order
+    __shared__ int32_t srow[STG ? PM_ROWS : 1];
     const int lane = lane_id(), h = lane >> 5, l32 = lane & 31;
     const int64_t u = blockIdx.x;
     const int c1 = src1_deg ? min(src1_deg[u], C1) : C1;
@@ -495,18 +501,89 @@ __global__ __launch_bounds__(64, MIX ? 3 : 4) void k_prune_mfma(
         // the chains in one pass per kind; kept: the rows are kept nodes
         // (occk_lds), else candidates (kill_lds)
         int rl_n = 0;  // entries listed (the same on every lane)
+        // STG (rows of PM_STAGE_D dimensions or more): the chains read the FP32 rows the listed
+        // pairs involve, each row once per flush: PM_CD dimensions of every
+        // involved row at a time go through LDS (four lanes load a row's 64
+        // bytes), and each lane adds them to its pair's chain (dims ascending,
+        // one fma per dim: the canonical chain).  GIST-shaped prune 180 -> 125
+        // ms.  Short rows: each lane streams its pair's two rows (the staging
+        // costs more than it saves at 96 dimensions: 265 -> 271 ms).
         auto flush = [&](bool kept) {
             if (rl_n == 0) return;
             __builtin_amdgcn_wave_barrier();
+            if (!STG) {
+                for (int e = lane; e < rl_n; e += PG_WAVE) {
+                    const int ent = rl[e], i = ent >> 6, j = ent & 63;
+                    const uint64_t ki = kept ? kept_key[i] : chunk_key[i], kj = chunk_key[j];
+                    const float b = dist_chain(X + (int64_t)key_id(ki) * ldx, X + (int64_t)key_id(kj) * ldx, d);
+                    if (occludes(key_d2(ki), b, key_d2(kj), strict, at)) {
+                        if (kept)
+                            atomicOr(&occk_lds, 1ull << j);
+                        else
+                            atomicOr(&kill_lds[i], 1ull << j);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                rl_n = 0;
+                return;
+            }
+            // involved rows: candidates (bit j of m0) and kept nodes (bit i of m1)
+            uint64_t m0 = 0, m1 = 0;
             for (int e = lane; e < rl_n; e += PG_WAVE) {
                 const int ent = rl[e], i = ent >> 6, j = ent & 63;
-                const uint64_t ki = kept ? kept_key[i] : chunk_key[i], kj = chunk_key[j];
-                const float b = dist_chain(X + (int64_t)key_id(ki) * ldx, X + (int64_t)key_id(kj) * ldx, d);
-                if (occludes(key_d2(ki), b, key_d2(kj), strict, at)) {
-                    if (kept)
-                        atomicOr(&occk_lds, 1ull << j);
-                    else
-                        atomicOr(&kill_lds[i], 1ull << j);
+                m0 |= 1ull << j;
+                if (kept)
+                    m1 |= 1ull << i;
+                else
+                    m0 |= 1ull << i;
+            }
+#pragma unroll
+            for (int o = 1; o < PG_WAVE; o <<= 1) {
+                m0 |= shfl_xor64(m0, o);
+                m1 |= shfl_xor64(m1, o);
+            }
+            const int n0 = __popcll(m0), nr = n0 + __popcll(m1);
+            if ((m0 >> lane) & 1ull) srow[__popcll(m0 & lanemask_lt())] = key_id(chunk_key[lane]);
+            if ((m1 >> lane) & 1ull) srow[n0 + __popcll(m1 & lanemask_lt())] = key_id(kept_key[lane]);
+            __builtin_amdgcn_wave_barrier();
+            float *fr = reinterpret_cast<float *>(rows);  // nr rows of PM_CS floats
+            for (int b0 = 0; b0 < rl_n; b0 += PG_WAVE) {
+                const int e = b0 + lane;
+                const bool have = e < rl_n;
+                int i = 0, j = 0, pi = 0, pj = 0;
+                if (have) {
+                    const int ent = rl[e];
+                    i = ent >> 6, j = ent & 63;
+                    pj = __popcll(m0 & ((1ull << j) - 1ull));
+                    pi = kept ? n0 + __popcll(m1 & ((1ull << i) - 1ull)) : __popcll(m0 & ((1ull << i) - 1ull));
+                }
+                float b = 0.0f;
+                for (int c0 = 0; c0 < d; c0 += PM_CD) {
+                    const int dl = min(PM_CD, d - c0);
+                    __builtin_amdgcn_wave_barrier();
+                    for (int v = lane; v < nr * (PM_CD / 4); v += PG_WAVE) {
+                        const int r = v / (PM_CD / 4), q = v % (PM_CD / 4);
+                        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (4 * q < dl) x = *reinterpret_cast<const float4 *>(X + (int64_t)srow[r] * ldx + c0 + 4 * q);
+                        *reinterpret_cast<float4 *>(fr + r * PM_CS + 4 * q) = x;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (have) {
+                        const float *a = fr + pi * PM_CS, *c = fr + pj * PM_CS;
+                        for (int k = 0; k < dl; ++k) {
+                            const float t = a[k] - c[k];
+                            b = fmaf(t, t, b);
+                        }
+                    }
+                }
+                if (have) {
+                    const uint64_t ki = kept ? kept_key[i] : chunk_key[i], kj = chunk_key[j];
+                    if (occludes(key_d2(ki), b, key_d2(kj), strict, at)) {
+                        if (kept)
+                            atomicOr(&occk_lds, 1ull << j);
+                        else
+                            atomicOr(&kill_lds[i], 1ull << j);
+                    }
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -1855,7 +1932,9 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
     {
         TimedLaunch tl(ctx, K_PRUNE, (double)n * C * C / 2.0 * 3.0 * d);
         if ((exact16 || mix) && cand_d2)
-            hipLaunchKernelGGL(exact16 ? k_prune_mfma<false> : k_prune_mfma<true>, dim3((unsigned)n), dim3(64), 0,
+            hipLaunchKernelGGL((exact16 ? k_prune_mfma<false, false>
+                                        : (d >= PM_STAGE_D ? k_prune_mfma<true, true> : k_prune_mfma<true, false>)),
+                               dim3((unsigned)n), dim3(64), 0,
                                st, x16, L.d16, nrm, n, cand_ids, cand_d2, C, (const int32_t *)nullptr,
                                (const int64_t *)nullptr, (const int32_t *)nullptr, (const float *)nullptr, R, at,
                                p->strict_ties, s_ids, s_d2, s_deg, X, ldx, d, pmx, p->k2p_prev_ids,
@@ -1884,7 +1963,9 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
         PG_HIP(hipGetLastError());
         TimedLaunch tl(ctx, K_PRUNE, -1.0);
         if (exact16 || mix)
-            hipLaunchKernelGGL(exact16 ? k_prune_mfma<false> : k_prune_mfma<true>, dim3((unsigned)n), dim3(64), 0,
+            hipLaunchKernelGGL((exact16 ? k_prune_mfma<false, false>
+                                        : (d >= PM_STAGE_D ? k_prune_mfma<true, true> : k_prune_mfma<true, false>)),
+                               dim3((unsigned)n), dim3(64), 0,
                                st, x16, L.d16, nrm, n, p_ids, p_d2, R, p_deg, off, rev, rev_d2, R, at,
                                p->strict_ties, g_ids, g_d2, g_deg, X, ldx, d, pmx, (const int32_t *)nullptr,
                                (const int32_t *)nullptr, 0, (unsigned long long *)nullptr);

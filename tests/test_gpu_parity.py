@@ -336,14 +336,19 @@ def test_prune_given_distances_match_computed_on_float_data(pg, datagen):
 
 @pytest.mark.parametrize("law,alpha,strict", [("gist", 60.0, False), ("gist", 65.0, False),
                                                ("deep", 60.0, True), ("deep", 89.0, False),
-                                               ("sift", 60.0, False), ("sift", 120.0, False)])
+                                               ("sift", 60.0, False), ("sift", 120.0, False),
+                                               ("gist512", 60.0, False), ("gist512", 89.0, True)])
 def test_prune_mixed_tiles_equal_chains_on_float_data(pg, datagen, law, alpha, strict):
     # float data: the MFMA prune on the centred FP16 copy decides only what
     # its error bound allows and takes the FP32 chain for the rest, so its
     # graph equals the all-chain prune, for every stage (the reverse unions
-    # run on both kernels too); duplicated rows give zero distances and ties
+    # run on both kernels too); duplicated rows give zero distances and ties.
+    # Rows of 256 dimensions or more take their chains from rows staged
+    # through LDS (gist512), shorter ones stream them per lane.
     log("mixed prune", law, alpha, strict)
-    if law == "gist":
+    if law == "gist512":
+        X, _ = datagen.gist_like(2500, 0, d=512, n_clusters=10, seed=8)
+    elif law == "gist":
         X, _ = datagen.gist_like(3000, 0, d=240, n_clusters=10, seed=5)
     elif law == "deep":
         X, _ = datagen.unit_mixture(4000, 0, d=96, n_clusters=20, seed=6)
