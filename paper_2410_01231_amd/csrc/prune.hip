@@ -379,7 +379,9 @@ constexpr int PM_PF = PM_ROWS * (PM_DC / 8) / PG_WAVE;  // 16-byte row loads per
 
 // One wave per node, rounds of up to 64 candidates as in k_prune; the
 // distances to u are the given (canonical) ones, the pairwise ones come from
-// Gram tiles: candidates x candidates (upper tiles) and kept x candidates.
+// Gram tiles: candidates x candidates (upper tiles) and kept x candidates
+// (at most 32 nodes kept in earlier rounds: the host sends the reverse
+// unions, which may need several rounds, here only when R <= 32).
 // Occlusion among this round's candidates is kept per occluding row (lane i
 // holds the set of later candidates that i occludes); the greedy scan of
 // Alg. 3 ORs in the set of every candidate it keeps.
@@ -1929,6 +1931,10 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
     }
     int32_t *s_ids = rev_stage ? p_ids : g_ids, *s_deg = rev_stage ? p_deg : g_deg;
     float *s_d2 = rev_stage ? p_d2 : g_d2;
+    // The MFMA kernel's second pass holds at most 32 nodes kept in earlier
+    // rounds.  A PRUNE list (C <= 64) takes one round; a reverse union can
+    // exceed 64 candidates, so that stage runs on it only when R <= 32.
+    const bool mfma_reverse = R <= 32;
     {
         TimedLaunch tl(ctx, K_PRUNE, (double)n * C * C / 2.0 * 3.0 * d);
         if ((exact16 || mix) && cand_d2)
@@ -1962,7 +1968,7 @@ extern "C" pg_status pg_prune(pg_ctx *ctx, const float *X, int64_t n, int32_t d,
                            p_deg, n, R, off, cnt, rev, rev_d2);
         PG_HIP(hipGetLastError());
         TimedLaunch tl(ctx, K_PRUNE, -1.0);
-        if (exact16 || mix)
+        if ((exact16 || mix) && mfma_reverse)
             hipLaunchKernelGGL((exact16 ? k_prune_mfma<false, false>
                                         : (d >= PM_STAGE_D ? k_prune_mfma<true, true> : k_prune_mfma<true, false>)),
                                dim3((unsigned)n), dim3(64), 0,
